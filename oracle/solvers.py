@@ -1,0 +1,400 @@
+"""BiCGStab (Algorithm 1) and pipelined BiCGStab (Algorithm 2) in FP64 with exact
+dot products -- oracle.
+
+Vector updates are numpy element-wise expressions in exactly the parenthesisation
+below; numpy rounds every operation separately (no contraction), which is the
+literal-order reading of the paper's recurrences.  All inner products go through
+``dot`` (exact, rounded once); A.v goes through ``spmv`` (row-sequential).
+
+Readings of Algorithm 2 (p-BiCGStab) where the printed text is garbled or silent:
+
+* w_0 is A r_0 (the printed ``A - r_0`` is a typo; w_i = A r_i is the invariant
+  the update of w_{i+1} and the alpha recurrence rely on);
+* the scalar omega and the vector w share the symbol w in the paper; here the
+  scalar is ``omega`` and the vector is ``w``;
+* in iteration 0, p_{-1}, s_{-1}, z_{-1}, v_{-1}, omega_{-1} are multiplied by
+  beta_{-1} = 0; they are undefined, so p_0 = r_0, s_0 = w_0, z_0 = t_0 are plain
+  copies;
+* the shadow residual r_hat is r_0 (every inner product in the paper is taken
+  against r_0);
+* beta_i = (alpha_i / omega_i) (r_hat, r_{i+1}) / (r_hat, r_i) is evaluated left to
+  right: ((alpha/omega) * rho_new) / rho;
+* alpha_{i+1} = rho_new / ((r_hat, w_{i+1}) + beta (r_hat, s_i) - (beta omega)(r_hat, z_i))
+  is evaluated as rho_new / (((rw + beta*rs) - (beta*omega)*rz));
+* x_{i+1} = x_i + alpha p_i + omega q_i is evaluated as (x + alpha*p) + omega*q.
+
+Stopping (the paper states tolerances but not the norm): after each iteration
+rec = sqrt((r, r)) / ||b||; when rec <= tol the true relative residual
+sqrt((b - A x, b - A x)) / ||b|| is computed and the solve stops if it is <= tol,
+otherwise it continues.  ``iterations`` counts completed loop bodies.
+
+Breakdowns (the paper is silent): ||b|| = 0 -> x = 0, OK; (r_hat, w_0) = 0 or an
+alpha denominator = 0 or rho = 0 or omega = 0 -> BREAKDOWN; (y, y) = 0 and
+(q, q) = 0 -> lucky breakdown: x = x + alpha p and the true residual decides;
+(y, y) = 0 with q != 0 -> BREAKDOWN; any non-finite scalar -> ERR_NONFINITE.
+The current iterate is always returned.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import exact
+from .spmv import spmv as _spmv, spmv_f32 as _spmv_f32
+
+OK, NOT_CONVERGED, BREAKDOWN, STAGNATED = 0, 1, 2, 3
+ERR_INVALID, ERR_HIP, ERR_NONFINITE, ERR_WORKSPACE = -1, -2, -3, -4
+
+
+@dataclasses.dataclass
+class Result:
+    x: np.ndarray
+    status: int
+    iterations: int
+    true_relres: float
+    rec_relres: float
+    true_checks: int = 0
+    history: list = dataclasses.field(default_factory=list)
+    iterates: list = dataclasses.field(default_factory=list)  # (x, r, alpha, omega) per iteration
+    outer_iterations: int = 0
+    fell_back: int = 0
+
+
+def default_dot(n: int):
+    """Exact dot: tier 1 for small n, the bit-identical C tier for large n."""
+    if n <= 20000:
+        return lambda a, b: exact.exact_dot(a.tolist(), b.tolist())
+    from . import ctier
+    return ctier.exact_dot
+
+
+def _finite(*v):
+    return all(math.isfinite(t) for t in v)
+
+
+class _Operator:
+    """A (unpreconditioned) or A.M (right preconditioning); x = M y at the end."""
+
+    def __init__(self, A, M, spmv):
+        self.A, self.M, self.spmv = A, M, spmv
+
+    def apply(self, v):
+        if self.M is None:
+            return self.spmv(self.A, v)
+        return self.spmv(self.A, self.spmv(self.M, v))
+
+    def to_x(self, y):
+        return y if self.M is None else self.spmv(self.M, y)
+
+
+def _true_relres(A, b, x, normb, dot, spmv):
+    res = b - spmv(A, x)
+    return math.sqrt(dot(res, res)) / normb
+
+
+def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=None,
+              record=0) -> Result:
+    """p-BiCGStab, Algorithm 2, with the readings in the module docstring.
+
+    With ``M`` (a CSR right preconditioner) the recurrences run on A.M and y,
+    starting from y_0 = 0, and x = M y; ``x0`` must then be None.
+    ``record`` keeps (x_i, r_i, alpha, omega) for the first ``record`` iterations.
+    """
+    spmv = spmv or _spmv
+    n = A.n
+    dot = dot or default_dot(n)
+    op = _Operator(A, M, spmv)
+    b = np.asarray(b, dtype=np.float64)
+    if M is not None and x0 is not None:
+        raise ValueError("right-preconditioned solve starts from y0 = 0")
+    y = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+
+    def finish(status, iters, rec, hist, its, checks, true=None):
+        x = op.to_x(y)
+        if true is None:
+            true = _true_relres(A, b, x, normb, dot, spmv) if normb > 0 else 0.0
+        return Result(x, status, iters, true, rec, checks, hist, its)
+
+    nb2 = dot(b, b)
+    if not math.isfinite(nb2):
+        return Result(op.to_x(y), ERR_NONFINITE, 0, math.nan, math.nan)
+    normb = math.sqrt(nb2)
+    if normb == 0.0:
+        return Result(np.zeros(n), OK, 0, 0.0, 0.0)
+    # initialisation (Algorithm 2, before the loop)
+    r = b - spmv(A, op.to_x(y)) if x0 is not None else b.copy()
+    rhat = r.copy()
+    w = op.apply(r)
+    t = op.apply(w)
+    rho = dot(rhat, r)
+    rw = dot(rhat, w)
+    rec = math.sqrt(dot(r, r)) / normb
+    hist, its, checks = [], [], 0
+    if rec <= tol:
+        checks += 1
+        tr = _true_relres(A, b, op.to_x(y), normb, dot, spmv)
+        if tr <= tol:
+            return finish(OK, 0, rec, hist, its, checks, tr)
+    if not _finite(rho, rw):
+        return finish(ERR_NONFINITE, 0, rec, hist, its, checks)
+    if rw == 0.0:
+        return finish(BREAKDOWN, 0, rec, hist, its, checks)
+    alpha = rho / rw
+    beta = omega = 0.0
+    p = s = z = v = None
+    for i in range(max_iter):
+        if i == 0:
+            p, s, z = r.copy(), w.copy(), t.copy()
+        else:
+            p = r + beta * (p - omega * s)
+            s = w + beta * (s - omega * z)
+            z = t + beta * (z - omega * v)
+        q = r - alpha * s
+        yv = w - alpha * z
+        qy = dot(q, yv)
+        yy = dot(yv, yv)
+        rs = dot(rhat, s)
+        rz = dot(rhat, z)
+        v = op.apply(z)
+        if not _finite(qy, yy, rs, rz):
+            return finish(ERR_NONFINITE, i, rec, hist, its, checks)
+        if yy == 0.0:
+            if dot(q, q) == 0.0:  # lucky breakdown: r_{i+1} = q_i = 0
+                y = y + alpha * p
+                checks += 1
+                tr = _true_relres(A, b, op.to_x(y), normb, dot, spmv)
+                return finish(OK if tr <= tol else BREAKDOWN, i + 1, 0.0, hist, its, checks, tr)
+            return finish(BREAKDOWN, i, rec, hist, its, checks)
+        omega = qy / yy
+        if omega == 0.0:
+            return finish(BREAKDOWN, i, rec, hist, its, checks)
+        y = (y + alpha * p) + omega * q
+        r = q - omega * yv
+        w = yv - omega * (t - alpha * v)
+        t = op.apply(w)
+        rho_new = dot(rhat, r)
+        rw = dot(rhat, w)
+        rr = dot(r, r)
+        rec = math.sqrt(rr) / normb
+        hist.append(rec)
+        if len(its) < record:
+            its.append((op.to_x(y), r.copy(), alpha, omega))
+        beta = ((alpha / omega) * rho_new) / rho
+        den = (rw + beta * rs) - (beta * omega) * rz
+        alpha_new = rho_new / den if den != 0.0 else math.nan
+        if rec <= tol:
+            checks += 1
+            tr = _true_relres(A, b, op.to_x(y), normb, dot, spmv)
+            if tr <= tol:
+                return finish(OK, i + 1, rec, hist, its, checks, tr)
+        if not _finite(rho_new, rw, rr, beta) or (den != 0.0 and not math.isfinite(alpha_new)):
+            return finish(ERR_NONFINITE, i + 1, rec, hist, its, checks)
+        if rho_new == 0.0 or den == 0.0:
+            return finish(BREAKDOWN, i + 1, rec, hist, its, checks)
+        alpha, rho = alpha_new, rho_new
+    return finish(NOT_CONVERGED, max_iter, rec, hist, its, checks)
+
+
+def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, record=0) -> Result:
+    """BiCGStab, Algorithm 1 (van der Vorst), same dots, stopping rule and breakdowns.
+
+    Per iteration: s = A p; alpha = rho / (r_hat, s); q = r - alpha s; y = A q;
+    omega = (q, y) / (y, y); x = (x + alpha p) + omega q; r = q - omega y;
+    rho' = (r_hat, r); beta = ((alpha / omega) rho') / rho; p = r + beta (p - omega s).
+    """
+    spmv = spmv or _spmv
+    n = A.n
+    dot = dot or default_dot(n)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    nb2 = dot(b, b)
+    if not math.isfinite(nb2):
+        return Result(x, ERR_NONFINITE, 0, math.nan, math.nan)
+    normb = math.sqrt(nb2)
+    if normb == 0.0:
+        return Result(np.zeros(n), OK, 0, 0.0, 0.0)
+
+    def finish(status, iters, rec, true=None):
+        if true is None:
+            true = _true_relres(A, b, x, normb, dot, spmv)
+        return Result(x, status, iters, true, rec, checks, hist, its)
+
+    r = b - spmv(A, x) if x0 is not None else b.copy()
+    rhat = r.copy()
+    p = r.copy()
+    rho = dot(rhat, r)
+    rec = math.sqrt(dot(r, r)) / normb
+    hist, its, checks = [], [], 0
+    if rec <= tol:
+        checks += 1
+        tr = _true_relres(A, b, x, normb, dot, spmv)
+        if tr <= tol:
+            return finish(OK, 0, rec, tr)
+    if not math.isfinite(rho):
+        return finish(ERR_NONFINITE, 0, rec)
+    for i in range(max_iter):
+        s = spmv(A, p)
+        rs = dot(rhat, s)
+        if not math.isfinite(rs):
+            return finish(ERR_NONFINITE, i, rec)
+        if rs == 0.0 or rho == 0.0:
+            return finish(BREAKDOWN, i, rec)
+        alpha = rho / rs
+        q = r - alpha * s
+        yv = spmv(A, q)
+        qy = dot(q, yv)
+        yy = dot(yv, yv)
+        if not _finite(qy, yy):
+            return finish(ERR_NONFINITE, i, rec)
+        if yy == 0.0:
+            if dot(q, q) == 0.0:
+                x = x + alpha * p
+                checks += 1
+                tr = _true_relres(A, b, x, normb, dot, spmv)
+                return finish(OK if tr <= tol else BREAKDOWN, i + 1, 0.0, tr)
+            return finish(BREAKDOWN, i, rec)
+        omega = qy / yy
+        if omega == 0.0:
+            return finish(BREAKDOWN, i, rec)
+        x = (x + alpha * p) + omega * q
+        r = q - omega * yv
+        rho_new = dot(rhat, r)
+        rr = dot(r, r)
+        rec = math.sqrt(rr) / normb
+        hist.append(rec)
+        if len(its) < record:
+            its.append((x.copy(), r.copy(), alpha, omega))
+        beta = ((alpha / omega) * rho_new) / rho
+        if rec <= tol:
+            checks += 1
+            tr = _true_relres(A, b, x, normb, dot, spmv)
+            if tr <= tol:
+                return finish(OK, i + 1, rec, tr)
+        if not _finite(rho_new, rr, beta):
+            return finish(ERR_NONFINITE, i + 1, rec)
+        if rho_new == 0.0:
+            return finish(BREAKDOWN, i + 1, rec)
+        p = r + beta * (p - omega * s)
+        rho = rho_new
+    return finish(NOT_CONVERGED, max_iter, rec)
+
+
+# ---------------------------------------------------------------------------
+# FP32 inner p-BiCGStab inside FP64 iterative refinement
+# ---------------------------------------------------------------------------
+
+def dot_f32_seq(a: np.ndarray, b: np.ndarray) -> np.float32:
+    """Plain float32 dot, sequential left-to-right accumulation."""
+    s = np.float32(0.0)
+    prod = (a.astype(np.float32) * b.astype(np.float32)).astype(np.float32)
+    for v in prod:
+        s = np.float32(s + v)
+    return s
+
+
+def pbicgstab_f32(A32, b32, tol=1e-5, max_iter=5000, dot=None) -> tuple[np.ndarray, int, float]:
+    """Algorithm 2 entirely in float32 (values, vectors, SpMV, dots, scalars), x0 = 0.
+
+    Stops on the recursive residual only: sqrt((r, r)) / ||b|| <= tol, or on
+    breakdown / non-finite scalars, returning the current iterate.
+    Returns (x, iterations, rec).
+    """
+    f = np.float32
+    dot = dot or dot_f32_seq
+    n = A32.n
+    x = np.zeros(n, dtype=f)
+    nb = f(np.sqrt(f(dot(b32, b32))))
+    if nb == 0:
+        return x, 0, 0.0
+    r = b32.astype(f).copy()
+    rhat = r.copy()
+    w = _spmv_f32(A32, r)
+    t = _spmv_f32(A32, w)
+    rho = f(dot(rhat, r))
+    rw = f(dot(rhat, w))
+    if rw == 0 or not np.isfinite(rw):
+        return x, 0, 1.0
+    alpha = f(rho / rw)
+    beta = omega = f(0)
+    rec = 1.0
+    for i in range(max_iter):
+        if i == 0:
+            p, s, z = r.copy(), w.copy(), t.copy()
+        else:
+            p = r + beta * (p - omega * s)
+            s = w + beta * (s - omega * z)
+            z = t + beta * (z - omega * v)
+        q = r - alpha * s
+        yv = w - alpha * z
+        qy = f(dot(q, yv))
+        yy = f(dot(yv, yv))
+        rs = f(dot(rhat, s))
+        rz = f(dot(rhat, z))
+        v = _spmv_f32(A32, z)
+        if yy == 0 or not np.isfinite(yy):
+            if yy == 0:
+                x = x + alpha * p
+            return x, i + 1, 0.0
+        omega = f(qy / yy)
+        if omega == 0 or not np.isfinite(omega):
+            return x, i, rec
+        x = (x + alpha * p) + omega * q
+        r = q - omega * yv
+        w = yv - omega * (t - alpha * v)
+        t = _spmv_f32(A32, w)
+        rho_new = f(dot(rhat, r))
+        rw = f(dot(rhat, w))
+        rr = f(dot(r, r))
+        rec = float(f(np.sqrt(rr)) / nb)
+        if rec <= tol:
+            return x, i + 1, rec
+        beta = f(f(f(alpha / omega) * rho_new) / rho)
+        den = f(f(rw + f(beta * rs)) - f(f(beta * omega) * rz))
+        if rho_new == 0 or den == 0 or not np.isfinite(den):
+            return x, i + 1, rec
+        alpha = f(rho_new / den)
+        rho = rho_new
+    return x, max_iter, rec
+
+
+def ir_solve(A, b, tol=1e-10, inner_tol=1e-5, max_outer=30, max_inner=5000, dot=None,
+             dot32=None, spmv=None) -> Result:
+    """FP64 iterative refinement around an FP32 inner p-BiCGStab.
+
+    outer k:  r = b - A x (FP64 SpMV), nu = sqrt(exdot(r, r));
+              stop if nu / ||b|| <= tol;  r32 = fp32(r / nu);
+              d = p-BiCGStab_fp32(fp32(A), r32, x0 = 0, tol = inner_tol);
+              x = x + nu * fp64(d).
+    STAGNATED when nu_{k+1} > 0.9 nu_k.  x starts at 0.
+    """
+    from synthgen import CSR
+    spmv = spmv or _spmv
+    n = A.n
+    dot = dot or default_dot(n)
+    b = np.asarray(b, dtype=np.float64)
+    A32 = CSR(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32))
+    normb = math.sqrt(dot(b, b))
+    x = np.zeros(n)
+    if normb == 0.0:
+        return Result(x, OK, 0, 0.0, 0.0)
+    total_inner = 0
+    nu_prev = math.inf
+    rel = math.inf
+    for k in range(max_outer + 1):
+        r = b - spmv(A, x)
+        nu = math.sqrt(dot(r, r))
+        rel = nu / normb
+        if rel <= tol:
+            return Result(x, OK, total_inner, rel, rel, outer_iterations=k)
+        if nu > 0.9 * nu_prev:
+            return Result(x, STAGNATED, total_inner, rel, rel, outer_iterations=k)
+        if k == max_outer:
+            break
+        nu_prev = nu
+        r32 = (r / nu).astype(np.float32)
+        d, its, _ = pbicgstab_f32(A32, r32, inner_tol, max_inner, dot32)
+        total_inner += its
+        x = x + nu * d.astype(np.float64)
+    return Result(x, NOT_CONVERGED, total_inner, rel, rel, outer_iterations=max_outer)

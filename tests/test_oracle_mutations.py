@@ -1,0 +1,70 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case rewrites one expression of the oracle's source on the CPU (a dropped
+term, a wrong sign, a wrong index, a transposed operand, a wrong rounding) and
+checks that the corresponding pin then fails.  The oracle files are not touched.
+"""
+import inspect
+import math
+import textwrap
+
+import numpy as np
+import pytest
+
+from oracle import exact, rational, solvers
+from tests.test_oracle_solvers import small_unsym
+
+
+def _mutant(func, old, new):
+    src = textwrap.dedent(inspect.getsource(func))
+    assert old in src, old
+    ns = dict(func.__globals__)
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return ns[func.__name__]
+
+
+def _tracks_rational(pb):
+    for seed in range(4):
+        A, D, b = small_unsym(seed, n=8, diag=12.0)
+        xs = rational.pbicgstab_q(A, b, 3)
+        res = pb(A, b, tol=0.0, max_iter=len(xs), record=len(xs))
+        if len(res.iterates) != len(xs):
+            return False
+        for (xf, _, _, _), xq in zip(res.iterates, xs):
+            xq = np.array([float(v) for v in xq])
+            if not np.linalg.norm(xf - xq) <= 1e-12 * np.linalg.norm(xq):
+                return False
+    return True
+
+
+MUTATIONS = [
+    ("(rw + beta * rs)", "(rw + beta * rz)"),            # wrong index
+    ("r = q - omega * yv", "r = q + omega * yv"),       # wrong sign
+    ("z = t + beta * (z - omega * v)", "z = t + beta * z"),  # dropped term
+    ("beta = ((alpha / omega) * rho_new) / rho", "beta = ((omega / alpha) * rho_new) / rho"),  # transposed
+    ("y = (y + alpha * p) + omega * q", "y = (y + alpha * p) + omega * p"),  # wrong operand
+    ("w = yv - omega * (t - alpha * v)", "w = yv - omega * t"),  # dropped term
+]
+
+
+def test_unmutated_oracle_passes():
+    assert _tracks_rational(solvers.pbicgstab)
+
+
+@pytest.mark.parametrize("old,new", MUTATIONS)
+def test_mutated_pbicgstab_is_caught(old, new):
+    assert not _tracks_rational(_mutant(solvers.pbicgstab, old, new))
+
+
+def test_mutated_rounding_is_caught():
+    trunc = _mutant(exact.round_scaled, "return S / (1 << SCALE)",
+                    "return float(S >> SCALE) if S > 0 else -float((-S) >> SCALE)")
+    # tie case 1 + 2^-53 and a subnormal case
+    assert trunc((1 << exact.SCALE) + (1 << (exact.SCALE - 53)) + 1) != 1.0 + 2.0 ** -52
+
+
+def test_mutated_product_scale_is_caught():
+    bad = _mutant(exact.scaled_product, "sh = ea + eb + SCALE", "sh = ea + eb + SCALE - 1")
+    good = exact.scaled_product(3.0, 5.0)
+    assert exact.round_scaled(bad(3.0, 5.0)) != exact.round_scaled(good)
+    assert math.isclose(exact.round_scaled(good), 15.0)
