@@ -1,0 +1,174 @@
+/*
+ * pbicgstab.h -- C-ABI of the MI355X (gfx950) exact-reduction pipelined BiCGStab library
+ * (libpbicgstab.so).
+ *
+ * The library solves A x = b for a square, unsymmetric sparse A given in CSR form,
+ * from b and x0, with the pipelined BiCGStab of Cools and Vanroose (paper: Algorithm 2)
+ * or van der Vorst's BiCGStab (paper: Algorithm 1).  Every inner product of the FP64
+ * solvers is accumulated exactly and rounded once to FP64, ExBLAS-style (paper,
+ * Section 2, the paragraph on reproducibility of the pure-MPI solver): results do not
+ * depend on launch shape, operation order or reduction tree.
+ *
+ * Conventions shared by every call:
+ *  - Pointers are DEVICE pointers unless the comment says (host).
+ *  - `stream` is a hipStream_t passed as void*; every call is stream-ordered.
+ *    Only pbicgstab_solve synchronises (it polls a small status block between
+ *    batches of iterations).  No call allocates device memory: the caller owns every
+ *    buffer, including the workspace `ws` of `ws_bytes` bytes (256-byte aligned).
+ *  - CSR: int32 row_ptr[n+1], int32 col_idx[nnz] (column indices in [0, n), sorted
+ *    ascending within each row; range checks are the caller's responsibility),
+ *    values FP64 (or FP32 where stated).  nnz < 2^31.
+ *  - Return value: PBCG_OK (0), a positive informative status (solve only: the
+ *    current iterate is returned in x and `info` is filled), or a negative error.
+ *    Argument errors are detected on the host before anything is launched.
+ *  - Calls that share a workspace must not overlap in time (different streams with
+ *    different workspaces are independent).
+ */
+#ifndef PBICGSTAB_H
+#define PBICGSTAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PBCG_OK = 0,
+    PBCG_NOT_CONVERGED = 1,   /* max_iter reached before the true residual met tol       */
+    PBCG_BREAKDOWN = 2,       /* a zero denominator (r_hat,w0), (y,y) with q != 0, omega,
+                                 rho or the alpha denominator                                */
+    PBCG_STAGNATED = 3,       /* refinement: outer residual not reduced by 10%             */
+    PBCG_ERR_INVALID = -1,    /* bad argument (null pointer, n < 0, nnz mismatch, ...)     */
+    PBCG_ERR_HIP = -2,        /* a HIP runtime call failed                                  */
+    PBCG_ERR_NONFINITE = -3,  /* NaN/Inf in b or in a recurrence scalar                     */
+    PBCG_ERR_WORKSPACE = -4   /* ws == NULL or ws_bytes below the required size             */
+} pbcg_status;
+
+typedef enum { PBCG_F64 = 0, PBCG_F32 = 1 } pbcg_dtype;
+typedef enum { PBCG_ALG_PBICGSTAB = 0, PBCG_ALG_BICGSTAB = 1 } pbcg_alg;
+typedef enum { PBCG_PREC_FP64 = 0, PBCG_PREC_FP32_IR = 1 } pbcg_prec;
+
+/* Square CSR matrix.  `val` points to nnz values of type `val_type`. */
+typedef struct {
+    int32_t n;
+    int32_t val_type;          /* pbcg_dtype */
+    int64_t nnz;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const void* val;
+} pbcg_csr;
+
+/* Solver options (host struct). */
+typedef struct {
+    double tol;                /* stop when the TRUE relative residual ||b-Ax||/||b|| <= tol */
+    int32_t max_iter;          /* iterations (FP64 solve) / inner iterations per outer step  */
+    int32_t alg;               /* pbcg_alg                                                    */
+    int32_t prec;              /* pbcg_prec                                                   */
+    int32_t max_outer;         /* FP32-IR: outer refinement steps (default 30 if 0)           */
+    double inner_tol;          /* FP32-IR: inner recursive tolerance (default 1e-5 if 0)      */
+    const pbcg_csr* M;         /* right preconditioner on the same n (NULL = none): the
+                                  solver runs on A.M and returns x = M y                      */
+    int32_t fallback;          /* with M: on breakdown / non-finite / stall restart the
+                                  unpreconditioned solver from the better iterate             */
+    int32_t history_len;       /* entries available in `history`                              */
+    double* history;           /* optional device buffer: recursive ||r_i||/||b|| per iteration */
+    double* r_out;             /* optional device n-vector: the final recursive residual     */
+    int32_t batch;             /* iterations enqueued between status polls (default 16)      */
+    int32_t stall_window;      /* with M + fallback: iterations without halving the recursive
+                                  residual that count as a stall (default 200)               */
+} pbcg_opts;
+
+/* Result summary (host struct). */
+typedef struct {
+    int32_t status;
+    int32_t iterations;        /* completed loop bodies (FP32-IR: total inner iterations)   */
+    int32_t outer_iterations;  /* FP32-IR refinement steps                                   */
+    int32_t true_checks;       /* true-residual evaluations                                  */
+    int32_t fell_back;         /* 1 if the preconditioned solve fell back                    */
+    int32_t pad;
+    double true_relres;        /* ||b - A x|| / ||b|| of the returned x (exact dots)         */
+    double rec_relres;         /* last recursive ||r|| / ||b||                               */
+    double seconds;            /* host wall time of the call                                 */
+} pbcg_info;
+
+/* Device vectors of one p-BiCGStab iteration (for the phase entry points). */
+typedef struct {
+    double *x, *r, *rhat, *w, *t, *p, *s, *z, *q, *y, *v;
+} pbcg_vectors;
+
+/* ---------------------------------------------------------------------------------
+ * Sparse matrix-vector product y = A x (paper: the products A p_i, A q_i, A z_i,
+ * A w_i of Algorithms 1 and 2).  A: FP64 or FP32 values; x, y: FP64; FP64 accumulation
+ * in a fixed per-matrix order (deterministic run to run; not the oracle's sequential
+ * order, so agreement is within gamma_len * sum |a x|).  y must not alias x.
+ */
+int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream);
+
+/* FP32 y = A x with FP32 values, vectors and accumulation (the inner solver's SpMV). */
+int csr_spmv_f32(const pbcg_csr* A32, const float* x, float* y, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Exact dot product (paper Section 2, ExBLAS paragraph): *out = RN_even(sum x_i y_i)
+ * with the sum formed exactly -- bit-identical for every launch shape.  Exact zero
+ * gives +0; |sum| >= 2^1024 - 2^970 gives +-inf; NaN input, inf*0 or both +inf and
+ * -inf products give NaN; otherwise an inf product gives that inf.  n >= 0.
+ * `out` is one device double.  Needs exdot_workspace_bytes(n) bytes of workspace.
+ */
+size_t exdot_workspace_bytes(int64_t n);
+int exdot(int64_t n, const double* x, const double* y, double* out,
+          void* ws, size_t ws_bytes, void* stream);
+
+/* Same as exdot with an explicit launch shape (grid >= 1 blocks of `block` in
+ * {64,128,256,512,1024} threads) and per-lane expansion length k in {2,3,4,6,8}.
+ * The result is independent of all three.  Workspace: exdot_workspace_bytes(n) covers
+ * grid <= 1024. */
+int exdot_config(int64_t n, const double* x, const double* y, double* out,
+                 int32_t grid, int32_t block, int32_t k,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * One fused pass of p-BiCGStab (paper Algorithm 2).  `scal` is a device array
+ * {alpha, beta, omega}.
+ * Phase A: p = r + beta (p - omega s); s = w + beta (s - omega z); z = t + beta (z - omega v)
+ *          (first != 0: p = r, s = w, z = t);  q = r - alpha s;  y = w - alpha z;
+ *          dots_out[0..3] = (q,y), (y,y), (r_hat,s), (r_hat,z)   (exact, device).
+ * Phase B: x = (x + alpha p) + omega q;  r = q - omega y;  w = y - omega (t - alpha v);
+ *          dots_out[0..2] = (r_hat,r), (r_hat,w), (r,r)             (exact, device).
+ * Every update is evaluated in this parenthesisation with separately rounded operations.
+ * Workspace: pbcg_phase_workspace_bytes(n).
+ */
+size_t pbcg_phase_workspace_bytes(int32_t n);
+int pbcg_phase_a(int32_t n, const pbcg_vectors* V, const double* scal, int32_t first,
+                 double* dots_out, void* ws, size_t ws_bytes, void* stream);
+int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal,
+                 double* dots_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Solve A x = b (paper: p-BiCGStab(A, b, x0), Algorithm 2; BiCGStab(A, b, x0),
+ * Algorithm 1).  x holds x0 on entry and the returned iterate on exit.  Stopping: the
+ * recursive residual sqrt((r,r))/||b|| is checked every iteration; when it is <= tol
+ * the true residual ||b - A x||/||b|| is evaluated and the solve stops if it is <= tol.
+ * prec = PBCG_PREC_FP32_IR runs an FP32 inner p-BiCGStab (FP32 values, vectors, SpMV
+ * and plain FP32 dot products, recursive tolerance inner_tol) inside FP64 iterative
+ * refinement whose residual, exact dots and solution update are FP64.
+ * `info` (host) may be NULL.  Workspace: pbicgstab_workspace_bytes(n, nnz, opts).
+ */
+size_t pbicgstab_workspace_bytes(int32_t n, int64_t nnz, const pbcg_opts* opts);
+int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_opts* opts,
+                    pbcg_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Fill `opts` (host) with defaults: tol 1e-10, max_iter 10000, p-BiCGStab, FP64. */
+void pbcg_default_opts(pbcg_opts* opts);
+
+/* Human-readable name of a status code (static string). */
+const char* pbcg_status_string(int status);
+
+/* Library ABI version (bumped on any change of the structs above). */
+int pbcg_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBICGSTAB_H */

@@ -1,0 +1,799 @@
+// C-ABI of libpbicgstab.so: argument checks, workspace layout, kernel launches and
+// the host driver of the solvers.  See include/pbicgstab.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/pbicgstab.h"
+#include "kernels.hpp"
+
+using namespace pbcg;
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int DOT_GRID_MAX = 1024;   // records available in a dot site
+constexpr int DOT_GRID_DEFAULT = 512;
+constexpr int KEXP = 4;              // expansion terms per lane in the solver kernels
+
+#define HIPCHK(expr)                              \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return PBCG_ERR_HIP; \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- workspace carving
+struct Carver {
+    char* base;
+    size_t off = 0;
+    size_t limit;
+    bool ok = true;
+    explicit Carver(void* b, size_t lim) : base((char*)b), limit(lim) {}
+    template <class T>
+    T* take(size_t count) {
+        off = align_up(off, 256);
+        T* p = (T*)(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        if (off > limit) ok = false;
+        return p;
+    }
+};
+
+size_t site_bytes(int grid_max) {
+    return 256 + align_up((size_t)grid_max * 4 * sizeof(xd::RecHdr), 256) +
+           align_up((size_t)grid_max * 4 * xd::NCH * sizeof(long long), 256) + 3 * 256;
+}
+
+xd::Site carve_site(Carver& c, int grid_max, unsigned int** counter_out) {
+    xd::Site s;
+    s.counter = c.take<unsigned int>(64);
+    s.hdr = c.take<xd::RecHdr>((size_t)grid_max * 4);
+    s.dig = c.take<long long>((size_t)grid_max * 4 * xd::NCH);
+    if (counter_out) *counter_out = s.counter;
+    return s;
+}
+
+int dot_grid(int64_t n) {
+    int64_t g = (n + (int64_t)BLOCK * 8 - 1) / ((int64_t)BLOCK * 8);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, DOT_GRID_DEFAULT));
+}
+
+// lanes per row from the mean row length (fixed per matrix -> fixed summation order)
+int spmv_lanes(int32_t n, int64_t nnz) {
+    double mean = n > 0 ? (double)nnz / (double)n : 1.0;
+    int L = 2;
+    while (L < mean && L < 64) L <<= 1;
+    return L;
+}
+
+bool csr_ok(const pbcg_csr* A) {
+    return A && A->n >= 0 && A->nnz >= 0 && A->nnz < (int64_t(1) << 31) &&
+           (A->n == 0 || (A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val)))) &&
+           (A->val_type == PBCG_F64 || A->val_type == PBCG_F32);
+}
+
+// ---------------------------------------------------------------- launchers
+template <class VT, class XT, class AT, class Epi>
+void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hipStream_t s) {
+    const int n = A->n;
+    if (n == 0) return;
+    const int L = spmv_lanes(A->n, A->nnz);
+    const int rows = BLOCK / L;
+    const int grid = (n + rows - 1) / rows;
+    const VT* val = (const VT*)A->val;
+#define SPMV_CASE(LL) \
+    case LL: spmv_kernel<LL, VT, XT, AT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, halt); break;
+    switch (L) {
+        SPMV_CASE(2) SPMV_CASE(4) SPMV_CASE(8) SPMV_CASE(16) SPMV_CASE(32) SPMV_CASE(64)
+    }
+#undef SPMV_CASE
+}
+
+// FP64 accumulation, values FP64 or FP32, x FP64
+template <class Epi>
+void launch_spmv64(const pbcg_csr* A, const double* x, Epi epi, const int* halt, hipStream_t s) {
+    if (A->val_type == PBCG_F64) launch_spmv_t<double, double, double>(A, x, epi, halt, s);
+    else launch_spmv_t<float, double, double>(A, x, epi, halt, s);
+}
+
+template <int D, class VT, class Epi>
+void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site site, const int* halt,
+                       hipStream_t s) {
+    const int n = A->n;
+    const int L = spmv_lanes(A->n, A->nnz);
+    const int rows = BLOCK / L;
+    int grid = std::max(1, std::min(DOT_GRID_DEFAULT, (n + rows - 1) / rows));
+    const VT* val = (const VT*)A->val;
+#define SD_CASE(LL) \
+    case LL: spmv_dot_kernel<LL, D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, site, halt); break;
+    switch (L) {
+        SD_CASE(2) SD_CASE(4) SD_CASE(8) SD_CASE(16) SD_CASE(32) SD_CASE(64)
+    }
+#undef SD_CASE
+}
+
+template <int D, class Epi>
+void launch_spmv_dot(const pbcg_csr* A, const double* x, Epi epi, xd::Site site, const int* halt,
+                     hipStream_t s) {
+    if (A->val_type == PBCG_F64) launch_spmv_dot_t<D, double>(A, x, epi, site, halt, s);
+    else launch_spmv_dot_t<D, float>(A, x, epi, site, halt, s);
+}
+
+template <int D, class Op>
+void launch_ew_dot(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
+                   int grid = 0, int block = BLOCK, int K = KEXP) {
+    if (grid <= 0) grid = dot_grid(n);
+#define EW_CASE(KK) \
+    case KK: ew_dot_kernel<D, KK, Op><<<grid, block, 0, s>>>(op, n, site, halt); break;
+    switch (K) {
+        EW_CASE(2) EW_CASE(3) EW_CASE(4) EW_CASE(6) EW_CASE(8)
+        default: ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt);
+    }
+#undef EW_CASE
+}
+
+template <int D, class Op>
+void launch_ew_fdot(Op op, int64_t n, FSite site, const int* halt, hipStream_t s) {
+    int grid = dot_grid(n);
+    ew_fdot_kernel<D, Op><<<grid, BLOCK, 0, s>>>(op, n, site, halt);
+}
+
+template <class F>
+void launch_ew(F f, int64_t n, const int* halt, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t g = std::min<int64_t>((n + BLOCK - 1) / BLOCK, 4096);
+    ew_kernel<F><<<(int)g, BLOCK, 0, s>>>(f, n, halt);
+}
+
+template <class F>
+void launch_single(F f, hipStream_t s) {
+    single_kernel<F><<<1, 64, 0, s>>>(f);
+}
+
+// ---------------------------------------------------------------- small device functors
+struct FnZeroU32 {
+    unsigned int* p; int count;
+    __device__ void operator()() const { for (int i = 0; i < count; ++i) p[i] = 0u; }
+};
+struct FnCopy {
+    double* dst; const double* src;
+    __device__ void operator()(int64_t i) const { dst[i] = src[i]; }
+};
+struct FnCopy3 {
+    double *a, *b, *c; const double* src;
+    __device__ void operator()(int64_t i) const { double v = src[i]; a[i] = v; b[i] = v; if (c) c[i] = v; }
+};
+struct FnZero {
+    double* dst;
+    __device__ void operator()(int64_t i) const { dst[i] = 0.0; }
+};
+struct FnAxpyState {      // x = x + alpha p  (alpha from state)
+    double* x; const double* p; const State* st;
+    __device__ void operator()(int64_t i) const { x[i] = x[i] + st->alpha * p[i]; }
+};
+struct FnQ {              // q = r - alpha s
+    double* q; const double* r; const double* s; const double* scal;
+    __device__ void operator()(int64_t i) const { q[i] = r[i] - scal[0] * s[i]; }
+};
+struct FnPUpdate {        // p = r + beta (p - omega s), skipped before the first iteration
+    double* p; const double* r; const double* s; const State* st;
+    __device__ void operator()(int64_t i) const {
+        if (st->iter == 0) return;
+        p[i] = r[i] + st->beta * (p[i] - st->omega * s[i]);
+    }
+};
+struct FnCastScaled {     // r32 = fp32(r / nu)
+    float* r32; const double* r; const State* st;
+    __device__ void operator()(int64_t i) const { r32[i] = (float)(r[i] / st->last_dot); }
+};
+struct FnIRUpdate {       // x = x + nu * fp64(d)
+    double* x; const float* d; const State* st;
+    __device__ void operator()(int64_t i) const { x[i] = x[i] + st->last_dot * (double)d[i]; }
+};
+struct FnCastVal {
+    float* dst; const double* src;
+    __device__ void operator()(int64_t i) const { dst[i] = (float)src[i]; }
+};
+struct FnZeroF {
+    float* dst;
+    __device__ void operator()(int64_t i) const { dst[i] = 0.0f; }
+};
+struct FnFAxpyState {
+    float* x; const float* p; const FState* st;
+    __device__ void operator()(int64_t i) const { x[i] = x[i] + st->alpha * p[i]; }
+};
+struct FnInitState {
+    State* st; double tol; int max_iter; double* hist; int hist_len;
+    __device__ void operator()() const {
+        State z;
+        memset(&z, 0, sizeof(z));
+        z.tol = tol; z.max_iter = max_iter; z.hist = hist; z.hist_len = hist_len;
+        *st = z;
+    }
+};
+struct FnInitFState {
+    FState* st; float tol; int max_iter;
+    __device__ void operator()() const {
+        FState z;
+        memset(&z, 0, sizeof(z));
+        z.tol = tol; z.max_iter = max_iter;
+        *st = z;
+    }
+};
+struct FnResume {          // clear halt flags (host decided to continue)
+    State* st;
+    __device__ void operator()() const { st->halt = 0; st->reason = 0; }
+};
+struct FnSqrtLastDot {     // last_dot = sqrt(last_dot)
+    State* st;
+    __device__ void operator()() const { st->last_dot = sqrt(st->last_dot); }
+};
+struct FnIterPlus {        // lucky breakdown: one more completed iteration
+    State* st;
+    __device__ void operator()() const { st->iter += 1; st->rec = 0.0; }
+};
+struct FinLastDot {
+    State* st;
+    __device__ void operator()(const double* d) const { st->last_dot = d[0]; }
+};
+
+// pinned host mirror of the state for polling
+struct Pinned {
+    State* s = nullptr;
+    FState* f = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool ready = false;
+    ~Pinned() {}
+};
+thread_local Pinned g_pin;
+
+int pin_init() {
+    if (g_pin.ready) return 0;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 2 * sizeof(State) + 2 * sizeof(FState), hipHostMallocDefault) != hipSuccess) return -1;
+    g_pin.s = (State*)p;
+    g_pin.f = (FState*)((char*)p + 2 * sizeof(State));
+    for (int i = 0; i < 2; ++i)
+        if (hipEventCreateWithFlags(&g_pin.ev[i], hipEventDisableTiming) != hipSuccess) return -1;
+    g_pin.ready = true;
+    return 0;
+}
+
+}  // namespace
+
+// ============================================================================ C-ABI
+extern "C" {
+
+int pbcg_abi_version(void) { return 1; }
+
+const char* pbcg_status_string(int status) {
+    switch (status) {
+        case PBCG_OK: return "ok";
+        case PBCG_NOT_CONVERGED: return "not converged";
+        case PBCG_BREAKDOWN: return "breakdown";
+        case PBCG_STAGNATED: return "stagnated";
+        case PBCG_ERR_INVALID: return "invalid argument";
+        case PBCG_ERR_HIP: return "HIP runtime error";
+        case PBCG_ERR_NONFINITE: return "non-finite value";
+        case PBCG_ERR_WORKSPACE: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+void pbcg_default_opts(pbcg_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-10;
+    o->max_iter = 10000;
+    o->alg = PBCG_ALG_PBICGSTAB;
+    o->prec = PBCG_PREC_FP64;
+    o->max_outer = 30;
+    o->inner_tol = 1e-5;
+    o->batch = 16;
+    o->stall_window = 200;
+}
+
+int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream) {
+    if (!csr_ok(A) || (A->n > 0 && (!x || !y))) return PBCG_ERR_INVALID;
+    if (x == y && A->n > 0) return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    launch_spmv64(A, x, EpiStore<double>{y}, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int csr_spmv_f32(const pbcg_csr* A, const float* x, float* y, void* stream) {
+    if (!csr_ok(A) || A->val_type != PBCG_F32 || (A->n > 0 && (!x || !y)) || (x == y && A->n > 0))
+        return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    launch_spmv_t<float, float, float>(A, x, EpiStore<float>{y}, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+size_t exdot_workspace_bytes(int64_t n) {
+    (void)n;
+    return site_bytes(DOT_GRID_MAX);
+}
+
+int exdot_config(int64_t n, const double* x, const double* y, double* out, int32_t grid, int32_t block,
+                 int32_t k, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 0 || !out || (n > 0 && (!x || !y))) return PBCG_ERR_INVALID;
+    if (grid < 1 || grid > DOT_GRID_MAX) return PBCG_ERR_INVALID;
+    if (!(block == 64 || block == 128 || block == 256 || block == 512 || block == 1024)) return PBCG_ERR_INVALID;
+    if (!(k == 2 || k == 3 || k == 4 || k == 6 || k == 8)) return PBCG_ERR_INVALID;
+    if (!ws || ws_bytes < exdot_workspace_bytes(n)) return PBCG_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return PBCG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    xd::Site site = carve_site(c, DOT_GRID_MAX, nullptr);
+    launch_single(FnZeroU32{site.counter, 1}, s);
+    DotsOp<1, FinStore> op{};
+    op.a[0] = x; op.b[0] = y;
+    op.fin = FinStore{out, 1};
+    launch_ew_dot<1>(op, n, site, nullptr, s, grid, block, k);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int exdot(int64_t n, const double* x, const double* y, double* out, void* ws, size_t ws_bytes, void* stream) {
+    return exdot_config(n, x, y, out, dot_grid(n), BLOCK, KEXP, ws, ws_bytes, stream);
+}
+
+size_t pbcg_phase_workspace_bytes(int32_t n) {
+    (void)n;
+    return site_bytes(DOT_GRID_MAX);
+}
+
+static bool vecs_ok(const pbcg_vectors* V, bool a) {
+    if (!V) return false;
+    if (a) return V->r && V->w && V->t && V->v && V->rhat && V->p && V->s && V->z && V->q && V->y;
+    return V->x && V->p && V->q && V->y && V->t && V->v && V->rhat && V->r && V->w;
+}
+
+int pbcg_phase_a(int32_t n, const pbcg_vectors* V, const double* scal, int32_t first, double* dots_out,
+                 void* ws, size_t ws_bytes, void* stream) {
+    if (n < 0 || !scal || !dots_out || (n > 0 && !vecs_ok(V, true))) return PBCG_ERR_INVALID;
+    if (!ws || ws_bytes < pbcg_phase_workspace_bytes(n) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    xd::Site site = carve_site(c, DOT_GRID_MAX, nullptr);
+    launch_single(FnZeroU32{site.counter, 1}, s);
+    PhaseA<FinStore> op{V->r, V->w, V->t, V->v, V->rhat, V->p, V->s, V->z, V->q, V->y, scal, first ? 1 : 0,
+                        FinStore{dots_out, 4}};
+    launch_ew_dot<4>(op, n, site, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal, double* dots_out, void* ws,
+                 size_t ws_bytes, void* stream) {
+    if (n < 0 || !scal || !dots_out || (n > 0 && !vecs_ok(V, false))) return PBCG_ERR_INVALID;
+    if (!ws || ws_bytes < pbcg_phase_workspace_bytes(n) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    xd::Site site = carve_site(c, DOT_GRID_MAX, nullptr);
+    launch_single(FnZeroU32{site.counter, 1}, s);
+    PhaseB<FinStore> op{V->x, V->p, V->q, V->y, V->t, V->v, V->rhat, V->r, V->w, scal, FinStore{dots_out, 3}};
+    launch_ew_dot<3>(op, n, site, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+}  // extern "C"
+
+
+// ============================================================================ solver driver
+namespace {
+
+struct FnCopyF {
+    float* dst; const float* src;
+    __device__ void operator()(int64_t i) const { dst[i] = src[i]; }
+};
+
+struct Work {
+    State* st;
+    FState* fst;
+    xd::Site site;
+    FSite fsite;
+    double *rhat, *r, *w, *t, *p, *s, *z, *q, *y, *v, *tmp, *tmp2, *hist;
+    float *r32, *rh32, *w32, *t32, *p32, *s32, *z32, *q32, *y32, *v32, *d32, *val32;
+    size_t need;
+    bool ok;
+};
+
+Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts* o) {
+    Carver c(ws, bytes);
+    Work W{};
+    W.st = c.take<State>(1);
+    W.fst = c.take<FState>(1);
+    W.site = carve_site(c, DOT_GRID_MAX, nullptr);
+    W.fsite.counter = c.take<unsigned int>(64);
+    W.fsite.part = c.take<float>((size_t)DOT_GRID_MAX * 4);
+    const size_t N = (size_t)std::max(n, 1);
+    double** v64[] = {&W.rhat, &W.r, &W.w, &W.t, &W.p, &W.s, &W.z, &W.q, &W.y, &W.v, &W.tmp, &W.tmp2};
+    for (double** pp : v64) *pp = c.take<double>(N);
+    const bool need_hist = o && o->M && o->fallback;
+    W.hist = need_hist ? c.take<double>((size_t)std::max(o->max_iter, 1)) : nullptr;
+    if (o && o->prec == PBCG_PREC_FP32_IR) {
+        float** v32[] = {&W.r32, &W.rh32, &W.w32, &W.t32, &W.p32, &W.s32,
+                         &W.z32, &W.q32, &W.y32, &W.v32, &W.d32};
+        for (float** pp : v32) *pp = c.take<float>(N);
+        W.val32 = c.take<float>((size_t)std::max<int64_t>(nnz, 1));
+    }
+    W.need = c.off + 256;
+    W.ok = c.ok && W.need <= bytes;
+    return W;
+}
+
+constexpr int CONTINUE = -100;
+
+struct Driver {
+    const pbcg_csr* A;
+    const pbcg_csr* M;     // right preconditioner or null
+    const double* b;
+    double* x;             // holds y when M != null
+    const pbcg_opts* o;
+    Work W;
+    hipStream_t s;
+    int* halt;
+    int batch;
+    pbcg_csr A32;          // FP32 copy of A (refinement)
+
+    // out = A in, or A (M in)
+    void op(const double* in, double* out) {
+        if (M) {
+            launch_spmv64(M, in, EpiStore<double>{W.tmp2}, halt, s);
+            launch_spmv64(A, W.tmp2, EpiStore<double>{out}, halt, s);
+        } else {
+            launch_spmv64(A, in, EpiStore<double>{out}, halt, s);
+        }
+    }
+
+    int sync_state(State* h) {
+        HIPCHK(hipMemcpyAsync(h, W.st, sizeof(State), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return 0;
+    }
+
+    // true residual of the current iterate (x = M y with a preconditioner) -> st->true_rel
+    void true_residual_enqueue() {
+        const double* xt = x;
+        if (M) {
+            launch_spmv64(M, x, EpiStore<double>{W.tmp2}, nullptr, s);
+            xt = W.tmp2;
+        }
+        EpiResidDot<FinTrue> epi{b, W.tmp, FinTrue{W.st}};
+        launch_spmv_dot<1>(A, xt, epi, W.site, nullptr, s);
+    }
+
+    void dot_enqueue(const double* a, const double* bb, int64_t n) {
+        DotsOp<1, FinLastDot> op{};
+        op.a[0] = a; op.b[0] = bb; op.fin = FinLastDot{W.st};
+        launch_ew_dot<1>(op, n, W.site, nullptr, s);
+    }
+
+    // a halted state after init or an iteration: a final status, or CONTINUE
+    int handle_halt(State& h) {
+        const int n = A->n;
+        const int reason = h.reason;
+        if (reason & R_CHECK) {
+            true_residual_enqueue();
+            if (sync_state(&h)) return PBCG_ERR_HIP;
+            if (h.true_rel <= h.tol) return PBCG_OK;
+        }
+        if (reason & R_NONFINITE) return PBCG_ERR_NONFINITE;
+        if (reason & R_YYZERO) {
+            dot_enqueue(W.q, W.q, n);
+            if (sync_state(&h)) return PBCG_ERR_HIP;
+            if (h.last_dot == 0.0) {  // lucky breakdown: x = x + alpha p completes the iteration
+                launch_ew(FnAxpyState{x, W.p, W.st}, n, nullptr, s);
+                launch_single(FnIterPlus{W.st}, s);
+                true_residual_enqueue();
+                if (sync_state(&h)) return PBCG_ERR_HIP;
+                return h.true_rel <= h.tol ? PBCG_OK : PBCG_BREAKDOWN;
+            }
+            return PBCG_BREAKDOWN;
+        }
+        if (reason & R_BREAKDOWN) return PBCG_BREAKDOWN;
+        if (reason & R_MAXIT) return PBCG_NOT_CONVERGED;
+        return CONTINUE;
+    }
+
+    void enqueue_iteration_p(bool first) {
+        const int n = A->n;
+        const double* scal = &W.st->alpha;
+        PhaseA<FinOmega> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
+                            FinOmega{W.st, 1}};
+        launch_ew_dot<4>(pa, n, W.site, halt, s);
+        op(W.z, W.v);
+        PhaseB<FinPhaseB> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
+        launch_ew_dot<3>(pb, n, W.site, halt, s);
+        op(W.w, W.t);
+    }
+
+    void enqueue_iteration_b() {
+        const int n = A->n;
+        const double* scal = &W.st->alpha;
+        launch_ew(FnPUpdate{W.p, W.r, W.s, W.st}, n, halt, s);
+        launch_spmv_dot<1>(A, W.p, EpiSDot{W.s, W.rhat, FinAlphaB{W.st}}, W.site, halt, s);
+        launch_ew(FnQ{W.q, W.r, W.s, scal}, n, halt, s);
+        launch_spmv_dot<2>(A, W.q, EpiYDot{W.y, W.q, FinOmega{W.st, 0}}, W.site, halt, s);
+        OpBiCGStabXR ox{x, W.p, W.q, W.y, W.rhat, W.r, scal, FinBiCGStabXR{W.st}};
+        launch_ew_dot<2>(ox, n, W.site, halt, s);
+    }
+
+    // FP64 p-BiCGStab / BiCGStab on A (or A.M).  x: x0 in, iterate out (y with M).
+    int run_fp64(State& h) {
+        const int n = A->n;
+        const bool bicg = o->alg == PBCG_ALG_BICGSTAB;
+        double* hist = o->history;
+        int hist_len = hist ? o->history_len : 0;
+        if (!hist && W.hist) { hist = W.hist; hist_len = o->max_iter; }
+        launch_single(FnInitState{W.st, o->tol, o->max_iter, hist, hist_len}, s);
+        launch_single(FnZeroU32{W.site.counter, 1}, s);
+        {
+            DotsOp<1, FinNormB> nb{};
+            nb.a[0] = b; nb.b[0] = b; nb.fin = FinNormB{W.st};
+            launch_ew_dot<1>(nb, n, W.site, nullptr, s);
+        }
+        if (M) {  // y0 = 0, r0 = b
+            launch_ew(FnZero{x}, n, nullptr, s);
+            launch_ew(FnCopy3{W.r, W.rhat, bicg ? W.p : nullptr, b}, n, nullptr, s);
+        } else {
+            launch_spmv64(A, x, EpiResid<double>{b, W.r, W.rhat, bicg ? W.p : nullptr}, nullptr, s);
+        }
+        if (!bicg) {
+            op(W.r, W.w);
+            op(W.w, W.t);
+            DotsOp<3, FinInitP> d3{};
+            d3.a[0] = W.rhat; d3.b[0] = W.r;
+            d3.a[1] = W.rhat; d3.b[1] = W.w;
+            d3.a[2] = W.r;    d3.b[2] = W.r;
+            d3.fin = FinInitP{W.st};
+            launch_ew_dot<3>(d3, n, W.site, halt, s);
+        } else {
+            DotsOp<2, FinInitB> d2{};
+            d2.a[0] = W.rhat; d2.b[0] = W.r;
+            d2.a[1] = W.r;    d2.b[1] = W.r;
+            d2.fin = FinInitB{W.st};
+            launch_ew_dot<2>(d2, n, W.site, halt, s);
+        }
+        HIPCHK(hipGetLastError());
+        if (sync_state(&h)) return PBCG_ERR_HIP;
+        if (h.halt) {
+            if (h.reason & R_ZERO_RHS) {
+                launch_ew(FnZero{x}, n, nullptr, s);
+                return PBCG_OK;
+            }
+            int r = handle_halt(h);
+            if (r != CONTINUE) return r;
+            launch_single(FnResume{W.st}, s);
+        }
+        if (o->max_iter == 0) return PBCG_NOT_CONVERGED;
+        bool first = true;
+        int polled = 0, batches = 0;
+        // device-side halts end the loop; this bound only guards against a broken state
+        const long long limit = (long long)o->max_iter + 4LL * batch + 64;
+        long long enqueued = 0;
+        while (true) {
+            if (enqueued > limit) return PBCG_ERR_HIP;
+            enqueued += batch;
+            for (int k = 0; k < batch; ++k) {
+                if (bicg) enqueue_iteration_b();
+                else enqueue_iteration_p(first);
+                first = false;
+            }
+            HIPCHK(hipGetLastError());
+            const int slot = batches & 1;
+            HIPCHK(hipMemcpyAsync(&g_pin.s[slot], W.st, sizeof(State), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(g_pin.ev[slot], s));
+            ++batches;
+            if (batches - polled >= 2) {  // keep one batch queued behind the one being waited on
+                const int ps = polled & 1;
+                HIPCHK(hipEventSynchronize(g_pin.ev[ps]));
+                ++polled;
+                if (g_pin.s[ps].halt) {
+                    if (sync_state(&h)) return PBCG_ERR_HIP;   // later batches were no-ops
+                    int r = handle_halt(h);
+                    if (r != CONTINUE) return r;
+                    launch_single(FnResume{W.st}, s);
+                    polled = batches;
+                    enqueued = h.iter;  // batches queued behind the halt were no-ops
+                }
+            }
+        }
+    }
+
+    // FP32 p-BiCGStab (Algorithm 2) on A32 with right-hand side W.r32, x0 = 0 -> W.d32.
+    int run_fp32_inner(int& iters) {
+        const int n = A->n;
+        FState* fs = W.fst;
+        int* fh = &fs->halt;
+        const float* scal = &fs->alpha;
+        launch_single(FnInitFState{fs, (float)o->inner_tol, std::max(o->max_iter, 1)}, s);
+        launch_single(FnZeroU32{W.fsite.counter, 1}, s);
+        launch_ew(FnZeroF{W.d32}, n, nullptr, s);
+        launch_ew(FnCopyF{W.rh32, W.r32}, n, nullptr, s);
+        launch_spmv_t<float, float, float>(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s);
+        launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, nullptr, s);
+        {
+            FDotsOp<3, FFinInit> d{};
+            d.a[0] = W.r32;  d.b[0] = W.r32;
+            d.a[1] = W.rh32; d.b[1] = W.r32;
+            d.a[2] = W.rh32; d.b[2] = W.w32;
+            d.fin = FFinInit{fs};
+            launch_ew_fdot<3>(d, n, W.fsite, nullptr, s);
+        }
+        FState hf{};
+        HIPCHK(hipMemcpyAsync(&hf, fs, sizeof(FState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        iters = 0;
+        if (hf.halt) return 0;
+        bool first = true;
+        int polled = 0, batches = 0;
+        const long long limit = (long long)std::max(o->max_iter, 1) + 4LL * batch + 64;
+        long long enqueued = 0;
+        while (true) {
+            if (enqueued > limit) return PBCG_ERR_HIP;
+            enqueued += batch;
+            for (int k = 0; k < batch; ++k) {
+                FPhaseA<FFinOmega> pa{W.r32, W.w32, W.t32, W.v32, W.rh32, W.p32, W.s32, W.z32, W.q32, W.y32,
+                                      scal, first ? 1 : 0, FFinOmega{fs}};
+                launch_ew_fdot<4>(pa, n, W.fsite, fh, s);
+                launch_spmv_t<float, float, float>(&A32, W.z32, EpiStore<float>{W.v32}, fh, s);
+                FPhaseB<FFinPhaseB> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
+                                       FFinPhaseB{fs}};
+                launch_ew_fdot<3>(pb, n, W.fsite, fh, s);
+                launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, fh, s);
+                first = false;
+            }
+            HIPCHK(hipGetLastError());
+            const int slot = batches & 1;
+            HIPCHK(hipMemcpyAsync(&g_pin.f[slot], fs, sizeof(FState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(g_pin.ev[slot], s));
+            ++batches;
+            if (batches - polled >= 2) {
+                const int ps = polled & 1;
+                HIPCHK(hipEventSynchronize(g_pin.ev[ps]));
+                ++polled;
+                if (g_pin.f[ps].halt) {
+                    HIPCHK(hipMemcpyAsync(&hf, fs, sizeof(FState), hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                    iters = hf.iter;
+                    if (hf.reason & R_YYZERO) {  // (y,y) = 0: x = x + alpha p completes the iteration
+                        launch_ew(FnFAxpyState{W.d32, W.p32, fs}, n, nullptr, s);
+                        iters += 1;
+                    }
+                    return 0;
+                }
+            }
+        }
+    }
+
+    // FP64 iterative refinement around the FP32 inner solver.
+    int run_ir(State& h, int& outer, int& inner_total) {
+        const int n = A->n;
+        launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0}, s);
+        launch_single(FnZeroU32{W.site.counter, 1}, s);
+        launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
+        A32 = *A;
+        A32.val = W.val32;
+        A32.val_type = PBCG_F32;
+        {
+            DotsOp<1, FinNormB> nb{};
+            nb.a[0] = b; nb.b[0] = b; nb.fin = FinNormB{W.st};
+            launch_ew_dot<1>(nb, n, W.site, nullptr, s);
+        }
+        HIPCHK(hipGetLastError());
+        if (sync_state(&h)) return PBCG_ERR_HIP;
+        outer = 0;
+        inner_total = 0;
+        if (h.reason & R_ZERO_RHS) {
+            launch_ew(FnZero{x}, n, nullptr, s);
+            return PBCG_OK;
+        }
+        if (h.reason & R_NONFINITE) return PBCG_ERR_NONFINITE;
+        const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
+        double nu_prev = INFINITY;
+        for (int k = 0; k <= max_outer; ++k) {
+            EpiResidDot<FinIR> epi{b, W.r, FinIR{W.st}};
+            launch_spmv_dot<1>(A, x, epi, W.site, nullptr, s);
+            if (sync_state(&h)) return PBCG_ERR_HIP;
+            outer = k;
+            const double nu = h.last_dot;
+            if (h.true_rel <= o->tol) return PBCG_OK;
+            if (!std::isfinite(nu)) return PBCG_ERR_NONFINITE;
+            if (nu > 0.9 * nu_prev) return PBCG_STAGNATED;
+            if (k == max_outer) break;
+            nu_prev = nu;
+            launch_ew(FnCastScaled{W.r32, W.r, W.st}, n, nullptr, s);
+            int its = 0;
+            if (run_fp32_inner(its)) return PBCG_ERR_HIP;
+            inner_total += its;
+            launch_ew(FnIRUpdate{x, W.d32, W.st}, n, nullptr, s);
+        }
+        return PBCG_NOT_CONVERGED;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t pbicgstab_workspace_bytes(int32_t n, int64_t nnz, const pbcg_opts* opts) {
+    pbcg_opts d;
+    if (!opts) { pbcg_default_opts(&d); opts = &d; }
+    Work W = carve_work(nullptr, SIZE_MAX, n, nnz, opts);
+    return W.need;
+}
+
+int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_opts* opts, pbcg_info* info,
+                    void* ws, size_t ws_bytes, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (!csr_ok(A) || !opts) return PBCG_ERR_INVALID;
+    if (A->n > 0 && (!b || !x)) return PBCG_ERR_INVALID;
+    if (opts->max_iter < 0 || !(opts->tol >= 0.0)) return PBCG_ERR_INVALID;
+    if (opts->alg != PBCG_ALG_PBICGSTAB && opts->alg != PBCG_ALG_BICGSTAB) return PBCG_ERR_INVALID;
+    if (opts->prec != PBCG_PREC_FP64 && opts->prec != PBCG_PREC_FP32_IR) return PBCG_ERR_INVALID;
+    if (opts->M && (!csr_ok(opts->M) || opts->M->n != A->n)) return PBCG_ERR_INVALID;
+    if (opts->M && opts->alg != PBCG_ALG_PBICGSTAB) return PBCG_ERR_INVALID;
+    if (opts->prec == PBCG_PREC_FP32_IR && (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || A->val_type != PBCG_F64))
+        return PBCG_ERR_INVALID;
+    if (opts->history && opts->history_len < 0) return PBCG_ERR_INVALID;
+    if (!ws || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
+    Work W = carve_work(ws, ws_bytes, A->n, A->nnz, opts);
+    if (!W.ok) return PBCG_ERR_WORKSPACE;
+    if (A->n == 0) {
+        if (info) info->status = PBCG_OK;
+        return PBCG_OK;
+    }
+    if (pin_init()) return PBCG_ERR_HIP;
+    Driver D{};
+    D.A = A; D.M = opts->M; D.b = b; D.x = x; D.o = opts; D.W = W; D.s = (hipStream_t)stream;
+    D.halt = &W.st->halt;
+    D.batch = opts->batch > 0 ? opts->batch : 16;
+    State h{};
+    int status;
+    int outer = 0, inner_total = 0;
+    if (opts->prec == PBCG_PREC_FP32_IR) {
+        status = D.run_ir(h, outer, inner_total);
+    } else {
+        status = D.run_fp64(h);
+    }
+    if (status != PBCG_ERR_HIP) {
+        const bool have_true = (opts->prec == PBCG_PREC_FP32_IR) ||
+                               (status == PBCG_OK && (h.reason & (R_CHECK | R_YYZERO)));
+        if (!have_true && !(h.reason & R_ZERO_RHS)) {
+            D.true_residual_enqueue();
+        }
+        if (D.M) {  // x = M y
+            launch_spmv64(D.M, x, EpiStore<double>{W.tmp2}, nullptr, D.s);
+            launch_ew(FnCopy{x, W.tmp2}, A->n, nullptr, D.s);
+        }
+        if (opts->r_out)
+            (void)hipMemcpyAsync(opts->r_out, W.r, sizeof(double) * (size_t)A->n, hipMemcpyDeviceToDevice, D.s);
+        if (D.sync_state(&h)) status = PBCG_ERR_HIP;
+        if (hipGetLastError() != hipSuccess) status = PBCG_ERR_HIP;
+    }
+    if (info) {
+        const bool zr = (h.reason & R_ZERO_RHS) != 0;
+        info->status = status;
+        info->iterations = opts->prec == PBCG_PREC_FP32_IR ? inner_total : h.iter;
+        info->outer_iterations = outer;
+        info->true_checks = h.true_checks;
+        info->true_relres = zr ? 0.0 : h.true_rel;
+        info->rec_relres = zr ? 0.0 : (opts->prec == PBCG_PREC_FP32_IR ? h.true_rel : h.rec);
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,632 @@
+// HIP kernels of the p-BiCGStab hot path (gfx950, wave64).
+//
+//  * spmv_kernel       vector-CSR SpMV: L lanes per row (L = 2..64, chosen per matrix
+//                      from its mean row length), coalesced val/col reads, x gathers,
+//                      xor-butterfly row reduction (same bits in every lane), one
+//                      row group per L lanes, XCD-aware block -> row-range mapping.
+//  * spmv_dot_kernel   the same row loop, persistent grid, with an epilogue that
+//                      produces D exact dot products (BiCGStab, true residual).
+//  * ew_dot_kernel     one fused element-wise pass (vector updates) with D exact dot
+//                      products accumulated on the fly (p-BiCGStab phases A and B).
+//  * ew_fdot_kernel    the FP32 analogue with plain FP32 dot products reduced in a
+//                      fixed tree (the inner solver of the refinement driver).
+// Every arithmetic expression is written in the parenthesisation of the paper's
+// recurrences and compiled without contraction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "state.hpp"
+#include "xdot.hpp"
+
+#pragma clang fp contract(off)
+
+namespace pbcg {
+
+constexpr int NUM_XCD = 8;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so neighbouring rows share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    int xcd = b % NUM_XCD, idx = b / NUM_XCD;
+    int base = G / NUM_XCD, rem = G % NUM_XCD;
+    return xcd * base + min(xcd, rem) + idx;
+}
+
+// ----------------------------------------------------------------------------- SpMV
+template <class T>
+struct EpiStore {
+    T* y;
+    __device__ __forceinline__ void operator()(int row, T s) const { y[row] = s; }
+};
+
+// r = b - A x; optional copies into c1, c2 (r_hat, p at initialisation)
+template <class T>
+struct EpiResid {
+    const T* b;
+    T* r;
+    T* c1;
+    T* c2;
+    __device__ __forceinline__ void operator()(int row, T s) const {
+        T v = b[row] - s;
+        r[row] = v;
+        if (c1) c1[row] = v;
+        if (c2) c2[row] = v;
+    }
+};
+
+template <int L, class VT, class XT, class AT, class Epi>
+__global__ void __launch_bounds__(256)
+spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+            const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, const int* halt) {
+    if (halt && *halt) return;
+    const int rows_per_block = blockDim.x / L;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int row = blk * rows_per_block + (int)threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= n) return;  // whole L-lane groups exit together
+    const int a = rp[row], b = rp[row + 1];
+    AT s = AT(0);
+    for (int k = a + lane; k < b; k += L) {
+        AT prod = (AT)val[k] * (AT)x[ci[k]];
+        s = s + prod;
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
+    if (lane == 0) epi(row, s);
+}
+
+// ----------------------------------------------------------------------------- dot sites
+#define XD_SHARED(D)                                   \
+    __shared__ unsigned long long sh_acc[(D) * xd::NCH]; \
+    __shared__ long long sh_tmp[(D) * xd::NCH];          \
+    __shared__ uint32_t sh_flags[(D)];                   \
+    __shared__ int sh_rng[2 * (D)];                      \
+    __shared__ int sh_last;                              \
+    __shared__ double sh_res[(D)];
+
+// Exact element-wise fused kernel.  Op provides:
+//   load()                      read device scalars
+//   elem(i, xa[D], ya[D])       updates for element i; dot operands
+//   finalize(const double* d)   run by one thread of the last block
+template <int D, int K, class Op>
+__global__ void __launch_bounds__(1024)
+ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt) {
+    if (halt && *halt) return;
+    XD_SHARED(D)
+    xd::block_init<D>(sh_acc, sh_flags);
+    op.load();
+    double e[D][K];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int k = 0; k < K; ++k) e[d][k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double xa[D], ya[D];
+        op.elem(i, xa, ya);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+    }
+    xd::block_flush<D, K>(e, sh_acc);
+    xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
+    if (!xd::block_is_last(site, &sh_last)) return;
+    xd::last_block_reduce<D>(site, sh_tmp, sh_flags, sh_rng, sh_res);
+    if (threadIdx.x == 0) op.finalize(sh_res);
+}
+
+// Exact SpMV with an epilogue that returns D dot operands for its row.
+// Epi: load(); row(int row, double s, double xa[D], double ya[D]); finalize(const double*)
+template <int L, int D, int K, class VT, class Epi>
+__global__ void __launch_bounds__(256)
+spmv_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                const VT* __restrict__ val, const double* __restrict__ x, Epi epi,
+                xd::Site site, const int* halt) {
+    if (halt && *halt) return;
+    XD_SHARED(D)
+    xd::block_init<D>(sh_acc, sh_flags);
+    epi.load();
+    double e[D][K];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int k = 0; k < K; ++k) e[d][k] = 0.0;
+    const int groups = blockDim.x / L;
+    const int lane = threadIdx.x % L;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int stride = gridDim.x * groups;
+    for (int row = blk * groups + (int)threadIdx.x / L; row < n; row += stride) {
+        const int a = rp[row], b = rp[row + 1];
+        double s = 0.0;
+        for (int k = a + lane; k < b; k += L) {
+            double prod = (double)val[k] * x[ci[k]];
+            s = s + prod;
+        }
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
+        if (lane == 0) {
+            double xa[D], ya[D];
+            epi.row(row, s, xa, ya);
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+        }
+    }
+    xd::block_flush<D, K>(e, sh_acc);
+    xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
+    if (!xd::block_is_last(site, &sh_last)) return;
+    xd::last_block_reduce<D>(site, sh_tmp, sh_flags, sh_rng, sh_res);
+    if (threadIdx.x == 0) epi.finalize(sh_res);
+}
+
+// ----------------------------------------------------------------------------- FP32 plain dots
+struct FSite {
+    float* part;            // [grid][D]
+    unsigned int* counter;
+};
+
+// Plain FP32 dots: per-thread sequential sums in grid-stride order, xor-butterfly
+// within the wave, waves in index order, blocks in index order (deterministic).
+template <int D, class Op>
+__global__ void __launch_bounds__(256)
+ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt) {
+    if (halt && *halt) return;
+    __shared__ float sh_w[D][16];
+    __shared__ int sh_last;
+    __shared__ float sh_res[D];
+    op.load();
+    float a[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) a[d] = 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        float xa[D], ya[D];
+        op.elem(i, xa, ya);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            float p = xa[d] * ya[d];
+            a[d] = a[d] + p;
+        }
+    }
+    const int wid = threadIdx.x / xd::WAVE, nw = blockDim.x / xd::WAVE;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        float v = a[d];
+#pragma unroll
+        for (int o = xd::WAVE / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o);
+        if ((threadIdx.x & (xd::WAVE - 1)) == 0) sh_w[d][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+        float s = 0.0f;
+        for (int w = 0; w < nw; ++w) s = s + sh_w[threadIdx.x][w];
+        site.part[(size_t)blockIdx.x * D + threadIdx.x] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = atomicAdd(site.counter, 1u);
+        sh_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!sh_last) return;
+    __threadfence();
+    if (threadIdx.x < D) {
+        float s = 0.0f;
+        for (unsigned g = 0; g < gridDim.x; ++g) s = s + site.part[(size_t)g * D + threadIdx.x];
+        sh_res[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *site.counter = 0u;
+        op.finalize(sh_res);
+    }
+}
+
+// ----------------------------------------------------------------------------- small kernels
+template <class F>
+__global__ void __launch_bounds__(256) ew_kernel(F f, int64_t n, const int* halt) {
+    if (halt && *halt) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) f(i);
+}
+
+template <class F>
+__global__ void single_kernel(F f) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) f();
+}
+
+// ============================================================================= p-BiCGStab ops
+// Phase A (Algorithm 2, the p, s, z, q, y updates) + (q,y), (y,y), (r_hat,s), (r_hat,z).
+template <class Fin>
+struct PhaseA {
+    const double* r; const double* w; const double* t; const double* v; const double* rhat;
+    double* p; double* s; double* z; double* q; double* y;
+    const double* scal;  // alpha, beta, omega
+    int first;
+    Fin fin;
+    double alpha, beta, omega;
+    __device__ __forceinline__ void load() { alpha = scal[0]; beta = scal[1]; omega = scal[2]; }
+    __device__ __forceinline__ void elem(int64_t i, double (&xa)[4], double (&ya)[4]) {
+        const double ri = r[i], wi = w[i], ti = t[i];
+        double pi, si, zi;
+        if (first) {
+            pi = ri; si = wi; zi = ti;
+        } else {
+            const double pp = p[i], sp = s[i], zp = z[i], vp = v[i];
+            pi = ri + beta * (pp - omega * sp);
+            si = wi + beta * (sp - omega * zp);
+            zi = ti + beta * (zp - omega * vp);
+        }
+        const double qi = ri - alpha * si;
+        const double yi = wi - alpha * zi;
+        p[i] = pi; s[i] = si; z[i] = zi; q[i] = qi; y[i] = yi;
+        const double rh = rhat[i];
+        xa[0] = qi; ya[0] = yi;
+        xa[1] = yi; ya[1] = yi;
+        xa[2] = rh; ya[2] = si;
+        xa[3] = rh; ya[3] = zi;
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
+
+// Phase B (x, r, w updates) + (r_hat,r), (r_hat,w), (r,r).
+template <class Fin>
+struct PhaseB {
+    double* x; const double* p; const double* q; const double* y; const double* t; const double* v;
+    const double* rhat; double* r; double* w;
+    const double* scal;
+    Fin fin;
+    double alpha, omega;
+    __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
+    __device__ __forceinline__ void elem(int64_t i, double (&xa)[3], double (&ya)[3]) {
+        const double qi = q[i], yi = y[i];
+        const double xi = (x[i] + alpha * p[i]) + omega * qi;
+        const double ri = qi - omega * yi;
+        const double wi = yi - omega * (t[i] - alpha * v[i]);
+        x[i] = xi; r[i] = ri; w[i] = wi;
+        const double rh = rhat[i];
+        xa[0] = rh; ya[0] = ri;
+        xa[1] = rh; ya[1] = wi;
+        xa[2] = ri; ya[2] = ri;
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
+
+// Plain dots of given vectors (D <= 4); no updates.
+template <int D, class Fin>
+struct DotsOp {
+    const double* a[4];
+    const double* b[4];
+    Fin fin;
+    __device__ __forceinline__ void load() {}
+    __device__ __forceinline__ void elem(int64_t i, double (&xa)[D], double (&ya)[D]) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) { xa[d] = a[d][i]; ya[d] = b[d][i]; }
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
+
+// finalizers ----------------------------------------------------------------
+struct FinStore {            // write the D results to out[]
+    double* out;
+    int D;
+    __device__ void operator()(const double* d) const {
+        for (int k = 0; k < D; ++k) out[k] = d[k];
+    }
+};
+
+__device__ __forceinline__ bool fin3(double a, double b, double c) { return isfinite(a) && isfinite(b) && isfinite(c); }
+
+// ||b||^2 -> normb
+struct FinNormB {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        double nb2 = d[0];
+        if (!isfinite(nb2)) {
+            st->normb = __longlong_as_double(0x7ff8000000000000ll);
+            st->halt = 1; st->reason |= R_NONFINITE; return;
+        }
+        double nb = sqrt(nb2);
+        st->normb = nb;
+        if (nb == 0.0) { st->halt = 1; st->reason |= R_ZERO_RHS; }
+    }
+};
+
+// initial (r_hat, r0), (r_hat, w0), (r0, r0) -> rho, alpha0, rec
+struct FinInitP {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        double rho = d[0], rw = d[1], rr = d[2];
+        double rec = sqrt(rr) / st->normb;
+        st->rec = rec; st->rho = rho; st->rw = rw;
+        int reason = 0;
+        if (rec <= st->tol) reason |= R_CHECK;
+        if (!isfinite(rho) || !isfinite(rw)) reason |= R_NONFINITE;
+        else if (rw == 0.0) reason |= R_BREAKDOWN;
+        else st->alpha = rho / rw;
+        st->beta = 0.0; st->omega = 0.0;
+        if (reason) { st->halt = 1; st->reason |= reason; }
+    }
+};
+
+// after phase A / after y = A q: omega = (q,y)/(y,y) (+ store (r_hat,s), (r_hat,z))
+struct FinOmega {
+    State* st;
+    int has_rsz;
+    __device__ void operator()(const double* d) const {
+        double qy = d[0], yy = d[1];
+        st->qy = qy; st->yy = yy;
+        bool fin = isfinite(qy) && isfinite(yy);
+        if (has_rsz) {
+            st->rs = d[2]; st->rz = d[3];
+            fin = fin && isfinite(d[2]) && isfinite(d[3]);
+        }
+        if (!fin) { st->halt = 1; st->reason |= R_NONFINITE; return; }
+        if (yy == 0.0) { st->halt = 1; st->reason |= R_YYZERO; return; }
+        double om = qy / yy;
+        st->omega = om;
+        if (om == 0.0) { st->halt = 1; st->reason |= R_BREAKDOWN; }
+    }
+};
+
+// after phase B: rho', beta, alpha', rec, iteration count, halts
+struct FinPhaseB {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        const double rho_new = d[0], rw = d[1], rr = d[2];
+        const double alpha = st->alpha, omega = st->omega, rho = st->rho;
+        const int it = st->iter + 1;
+        st->iter = it;
+        const double rec = sqrt(rr) / st->normb;
+        st->rec = rec; st->rw = rw; st->rr = rr;
+        if (st->hist && it <= st->hist_len) st->hist[it - 1] = rec;
+        const double beta = ((alpha / omega) * rho_new) / rho;
+        const double den = (rw + beta * st->rs) - (beta * omega) * st->rz;
+        const double alpha_new = den != 0.0 ? rho_new / den : __longlong_as_double(0x7ff8000000000000ll);
+        int reason = 0;
+        if (rec <= st->tol) reason |= R_CHECK;
+        bool nonfin = !(isfinite(rho_new) && isfinite(rw) && isfinite(rr) && isfinite(beta)) ||
+                      (den != 0.0 && !isfinite(alpha_new));
+        if (nonfin) reason |= R_NONFINITE;
+        else if (rho_new == 0.0 || den == 0.0) reason |= R_BREAKDOWN;
+        else { st->beta = beta; st->alpha = alpha_new; st->rho = rho_new; }
+        if (it >= st->max_iter) reason |= R_MAXIT;
+        if (reason) { st->halt = 1; st->reason |= reason; }
+    }
+};
+
+// BiCGStab initial (r_hat, r0), (r0, r0) -> rho, rec
+struct FinInitB {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        double rho = d[0], rr = d[1];
+        double rec = sqrt(rr) / st->normb;
+        st->rec = rec; st->rho = rho;
+        st->alpha = 0.0; st->beta = 0.0; st->omega = 0.0;
+        int reason = 0;
+        if (rec <= st->tol) reason |= R_CHECK;
+        if (!isfinite(rho)) reason |= R_NONFINITE;
+        if (reason) { st->halt = 1; st->reason |= reason; }
+    }
+};
+
+// refinement: nu = sqrt((r,r)), rel = nu / ||b||
+struct FinIR {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        double nu = sqrt(d[0]);
+        st->last_dot = nu;
+        st->true_rel = nu / st->normb;
+    }
+};
+
+// true residual: (res,res) -> true_rel
+struct FinTrue {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        st->true_rel = sqrt(d[0]) / st->normb;
+        st->true_checks += 1;
+    }
+};
+
+// epilogue for res = b - A x with the dot (res,res)
+template <class Fin>
+struct EpiResidDot {
+    const double* b;
+    double* res;
+    Fin fin;
+    __device__ __forceinline__ void load() {}
+    __device__ __forceinline__ void row(int i, double s, double (&xa)[1], double (&ya)[1]) {
+        double v = b[i] - s;
+        res[i] = v;
+        xa[0] = v; ya[0] = v;
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
+
+// ============================================================================= BiCGStab ops
+// s = A p with (r_hat, s) -> alpha = rho / (r_hat, s)
+struct FinAlphaB {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        double rs = d[0];
+        st->rs = rs;
+        if (!isfinite(rs)) { st->halt = 1; st->reason |= R_NONFINITE; return; }
+        if (rs == 0.0 || st->rho == 0.0) { st->halt = 1; st->reason |= R_BREAKDOWN; return; }
+        st->alpha = st->rho / rs;
+    }
+};
+
+struct EpiSDot {
+    double* s; const double* rhat; FinAlphaB fin;
+    __device__ __forceinline__ void load() {}
+    __device__ __forceinline__ void row(int i, double v, double (&xa)[1], double (&ya)[1]) {
+        s[i] = v; xa[0] = rhat[i]; ya[0] = v;
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
+
+// y = A q with (q,y), (y,y)
+struct EpiYDot {
+    double* y; const double* q; FinOmega fin;
+    __device__ __forceinline__ void load() {}
+    __device__ __forceinline__ void row(int i, double v, double (&xa)[2], double (&ya)[2]) {
+        y[i] = v;
+        double qi = q[i];
+        xa[0] = qi; ya[0] = v;
+        xa[1] = v; ya[1] = v;
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
+
+// x = (x + alpha p) + omega q; r = q - omega y; (r_hat, r), (r, r)
+struct FinBiCGStabXR {
+    State* st;
+    __device__ void operator()(const double* d) const {
+        const double rho_new = d[0], rr = d[1];
+        const double alpha = st->alpha, omega = st->omega, rho = st->rho;
+        const int it = st->iter + 1;
+        st->iter = it;
+        const double rec = sqrt(rr) / st->normb;
+        st->rec = rec; st->rr = rr;
+        if (st->hist && it <= st->hist_len) st->hist[it - 1] = rec;
+        const double beta = ((alpha / omega) * rho_new) / rho;
+        int reason = 0;
+        if (rec <= st->tol) reason |= R_CHECK;
+        if (!(isfinite(rho_new) && isfinite(rr) && isfinite(beta))) reason |= R_NONFINITE;
+        else if (rho_new == 0.0) reason |= R_BREAKDOWN;
+        else { st->beta = beta; st->rho = rho_new; }
+        if (it >= st->max_iter) reason |= R_MAXIT;
+        if (reason) { st->halt = 1; st->reason |= reason; }
+    }
+};
+
+struct OpBiCGStabXR {
+    double* x; const double* p; const double* q; const double* y; const double* rhat; double* r;
+    const double* scal; FinBiCGStabXR fin;
+    double alpha, omega;
+    __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
+    __device__ __forceinline__ void elem(int64_t i, double (&xa)[2], double (&ya)[2]) {
+        const double qi = q[i];
+        const double xi = (x[i] + alpha * p[i]) + omega * qi;
+        const double ri = qi - omega * y[i];
+        x[i] = xi; r[i] = ri;
+        xa[0] = rhat[i]; ya[0] = ri;
+        xa[1] = ri; ya[1] = ri;
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
+
+// ============================================================================= FP32 inner solver ops
+template <class Fin>
+struct FPhaseA {
+    const float* r; const float* w; const float* t; const float* v; const float* rhat;
+    float* p; float* s; float* z; float* q; float* y;
+    const float* scal; int first; Fin fin;
+    float alpha, beta, omega;
+    __device__ __forceinline__ void load() { alpha = scal[0]; beta = scal[1]; omega = scal[2]; }
+    __device__ __forceinline__ void elem(int64_t i, float (&xa)[4], float (&ya)[4]) {
+        const float ri = r[i], wi = w[i], ti = t[i];
+        float pi, si, zi;
+        if (first) { pi = ri; si = wi; zi = ti; }
+        else {
+            const float pp = p[i], sp = s[i], zp = z[i], vp = v[i];
+            pi = ri + beta * (pp - omega * sp);
+            si = wi + beta * (sp - omega * zp);
+            zi = ti + beta * (zp - omega * vp);
+        }
+        const float qi = ri - alpha * si;
+        const float yi = wi - alpha * zi;
+        p[i] = pi; s[i] = si; z[i] = zi; q[i] = qi; y[i] = yi;
+        const float rh = rhat[i];
+        xa[0] = qi; ya[0] = yi;
+        xa[1] = yi; ya[1] = yi;
+        xa[2] = rh; ya[2] = si;
+        xa[3] = rh; ya[3] = zi;
+    }
+    __device__ __forceinline__ void finalize(const float* d) { fin(d); }
+};
+
+template <class Fin>
+struct FPhaseB {
+    float* x; const float* p; const float* q; const float* y; const float* t; const float* v;
+    const float* rhat; float* r; float* w; const float* scal; Fin fin;
+    float alpha, omega;
+    __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
+    __device__ __forceinline__ void elem(int64_t i, float (&xa)[3], float (&ya)[3]) {
+        const float qi = q[i], yi = y[i];
+        const float xi = (x[i] + alpha * p[i]) + omega * qi;
+        const float ri = qi - omega * yi;
+        const float wi = yi - omega * (t[i] - alpha * v[i]);
+        x[i] = xi; r[i] = ri; w[i] = wi;
+        const float rh = rhat[i];
+        xa[0] = rh; ya[0] = ri;
+        xa[1] = rh; ya[1] = wi;
+        xa[2] = ri; ya[2] = ri;
+    }
+    __device__ __forceinline__ void finalize(const float* d) { fin(d); }
+};
+
+template <int D, class Fin>
+struct FDotsOp {
+    const float* a[4]; const float* b[4]; Fin fin;
+    __device__ __forceinline__ void load() {}
+    __device__ __forceinline__ void elem(int64_t i, float (&xa)[D], float (&ya)[D]) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) { xa[d] = a[d][i]; ya[d] = b[d][i]; }
+    }
+    __device__ __forceinline__ void finalize(const float* d) { fin(d); }
+};
+
+// (b,b), (r_hat,r), (r_hat,w) of the inner solve (r = r_hat = b at x0 = 0)
+struct FFinInit {
+    FState* st;
+    __device__ void operator()(const float* d) const {
+        float nb = sqrtf(d[0]);
+        st->normb = nb; st->rho = d[1];
+        st->beta = 0.0f; st->omega = 0.0f; st->rec = 1.0f;
+        if (nb == 0.0f) { st->halt = 1; st->reason |= R_ZERO_RHS; return; }
+        float rw = d[2];
+        if (rw == 0.0f || !isfinite(rw)) { st->halt = 1; st->reason |= R_BREAKDOWN; return; }
+        st->alpha = d[1] / rw;
+    }
+};
+
+struct FFinOmega {
+    FState* st;
+    __device__ void operator()(const float* d) const {
+        float qy = d[0], yy = d[1];
+        st->rs = d[2]; st->rz = d[3];
+        if (yy == 0.0f || !isfinite(yy)) { st->halt = 1; st->reason |= (yy == 0.0f ? R_YYZERO : R_NONFINITE); return; }
+        float om = qy / yy;
+        st->omega = om;
+        if (om == 0.0f || !isfinite(om)) { st->halt = 1; st->reason |= R_BREAKDOWN; }
+    }
+};
+
+struct FFinPhaseB {
+    FState* st;
+    __device__ void operator()(const float* d) const {
+        const float rho_new = d[0], rw = d[1], rr = d[2];
+        const float alpha = st->alpha, omega = st->omega, rho = st->rho;
+        const int it = st->iter + 1;
+        st->iter = it;
+        const float rec = sqrtf(rr) / st->normb;
+        st->rec = rec;
+        int reason = 0;
+        if (rec <= st->tol) reason |= R_CONVERGED;
+        else {
+            const float beta = ((alpha / omega) * rho_new) / rho;
+            const float den = (rw + beta * st->rs) - (beta * omega) * st->rz;
+            if (rho_new == 0.0f || den == 0.0f || !isfinite(den)) reason |= R_BREAKDOWN;
+            else { st->beta = beta; st->alpha = rho_new / den; st->rho = rho_new; }
+        }
+        if (it >= st->max_iter) reason |= R_MAXIT;
+        if (reason) { st->halt = 1; st->reason |= reason; }
+    }
+};
+
+}  // namespace pbcg

@@ -1,0 +1,39 @@
+// Device-resident solver state shared by the kernels and the host driver.
+#pragma once
+#include <stdint.h>
+
+namespace pbcg {
+
+// halt reasons (bit set)
+enum : int {
+    R_CHECK = 1,        // recursive residual <= tol: host evaluates the true residual
+    R_NONFINITE = 2,    // a non-finite recurrence scalar
+    R_BREAKDOWN = 4,    // zero denominator
+    R_MAXIT = 8,        // iteration limit reached
+    R_YYZERO = 16,      // (y,y) == 0: host tests (q,q) for a lucky breakdown
+    R_ZERO_RHS = 32,    // ||b|| == 0
+    R_CONVERGED = 64,   // (inner FP32 solve) recursive tolerance met
+};
+
+// FP64 solver scalars.  alpha, beta, omega are consecutive: kernels read them
+// through a `const double* scal` = &alpha.
+struct State {
+    double alpha, beta, omega, rho;
+    double rs, rz, qy, yy;
+    double normb, rec, true_rel, tol;
+    double rw, rr, last_dot, pad0;
+    int32_t iter, max_iter, halt, reason;
+    int32_t hist_len, true_checks, pad1, pad2;
+    double* hist;
+    double* pad3;
+};
+
+// FP32 inner-solver scalars.
+struct FState {
+    float alpha, beta, omega, rho;
+    float rs, rz, normb, rec;
+    float tol, pad0, pad1, pad2;
+    int32_t iter, max_iter, halt, reason;
+};
+
+}  // namespace pbcg

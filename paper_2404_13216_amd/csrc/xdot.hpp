@@ -1,0 +1,383 @@
+// Exact dot-product engine for gfx950 (wave64).
+//
+// What it computes: RN_even(sum_i x_i*y_i) with the sum formed exactly, the
+// reproducible-reduction idea the paper borrows from ExBLAS (Section 2, the
+// paragraph on the pure-MPI reproducible BiCGStab): a long fixed-point
+// accumulator plus floating-point expansions, so that the rounded result is
+// independent of partitioning, order and reduction tree.
+//
+// Representation.  Every product of two doubles is an integer multiple of
+// 2^-2148, so the exact sum is S * 2^-2148 for an integer S with |S| < 2^4240.
+// S is held as NCH = 132 signed 64-bit "chunks": chunk c carries weight 2^(32c);
+// a chunk may exceed 32 bits (the upper half is carry headroom), so additions need
+// no carry propagation until the end.
+//
+// Three levels:
+//  1. Per lane: each product p = fl(x*y) and its exact error e = fma(x,y,-p)
+//     (TwoProd, exact whenever 2^-969 <= |p| < 2^980) are added into a K-term
+//     floating-point expansion with Knuth's TwoSum (error-free).  A non-zero
+//     remainder after the K-th term, and every product outside the TwoProd range
+//     (tiny, huge, or underflowed to zero), is deposited into the LDS accumulator
+//     as an exact integer (ds_add_u64 atomics; integer adds commute).
+//  2. Per wave at the end of the loop: each expansion term is summed exactly over
+//     the 64 lanes inside a 4-chunk window (FP64 sums of integers < 2^38 are exact)
+//     and one lane deposits the 4 window chunks; lanes outside the window deposit
+//     their own term.
+//  3. Per block: the LDS accumulator is carry-normalised one step (chunks become
+//     |c| < 2^32 + 2^30) and its non-zero chunk range written to a per-block record;
+//     the last block to finish sums the records chunk by chunk (int64, order-free),
+//     normalises fully and rounds once to nearest-even.
+// Integer addition is associative, so the bits of the result do not depend on the
+// grid, the block size, K, or the order in which blocks finish.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xd {
+
+constexpr int NCH = 132;     // chunks: bits 0 .. 4223 (+ 32 bits headroom in the top chunk)
+constexpr int BIAS = 2148;   // bit k of S has weight 2^(k - 2148)
+constexpr int WAVE = 64;
+
+enum : uint32_t { F_NAN = 1u, F_PINF = 2u, F_NINF = 4u };
+
+// Per-block record in global memory: header + chunk values [lo, hi].
+struct RecHdr {
+    int32_t lo, hi;
+    uint32_t flags;
+    int32_t pad;
+};
+
+// Workspace of one dot "site" (a kernel that produces D dots).
+struct Site {
+    RecHdr* hdr;           // [grid][D]
+    long long* dig;        // [grid][D][NCH]
+    unsigned int* counter; // blocks finished (the last one resets it to 0)
+};
+
+__device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
+
+// value = m * 2^(P - BIAS), m < 2^53
+__device__ __forceinline__ void decompose(double v, uint64_t& m, int& P, bool& neg) {
+    uint64_t b = dbits(v);
+    neg = (b >> 63) != 0;
+    int be = (int)((b >> 52) & 0x7ff);
+    m = b & ((1ull << 52) - 1);
+    if (be) {
+        m |= (1ull << 52);
+        P = be - 1075 + BIAS;
+    } else {
+        P = -1074 + BIAS;
+    }
+}
+
+__device__ __forceinline__ void lds_add(unsigned long long* acc, int c, uint64_t piece, bool neg) {
+    if (piece) {
+        long long v = neg ? -(long long)piece : (long long)piece;
+        atomicAdd(acc + c, (unsigned long long)v);
+    }
+}
+
+// Deposit a finite non-zero double exactly.
+__device__ __noinline__ void deposit_double(unsigned long long* acc, double v) {
+    uint64_t m; int P; bool neg;
+    decompose(v, m, P, neg);
+    int c = P >> 5, s = P & 31;
+    uint64_t lo = m << s;
+    uint64_t hi = s ? (m >> (64 - s)) : 0;
+    lds_add(acc, c, lo & 0xffffffffull, neg);
+    lds_add(acc, c + 1, lo >> 32, neg);
+    lds_add(acc, c + 2, hi, neg);
+}
+
+// Deposit the exact product of two finite non-zero doubles (any magnitudes).
+__device__ __noinline__ void deposit_product(unsigned long long* acc, double x, double y) {
+    uint64_t mx, my; int Px, Py; bool nx, ny;
+    decompose(x, mx, Px, nx);
+    decompose(y, my, Py, ny);
+    uint64_t lo = mx * my;
+    uint64_t hi = __umul64hi(mx, my);       // product < 2^106
+    int P = Px + Py - BIAS;                  // >= 0
+    int c = P >> 5, s = P & 31;
+    uint64_t w0 = lo << s;
+    uint64_t w1 = s ? ((hi << s) | (lo >> (64 - s))) : hi;
+    uint64_t w2 = s ? (hi >> (64 - s)) : 0;
+    bool neg = nx != ny;
+    lds_add(acc, c, w0 & 0xffffffffull, neg);
+    lds_add(acc, c + 1, w0 >> 32, neg);
+    lds_add(acc, c + 2, w1 & 0xffffffffull, neg);
+    lds_add(acc, c + 3, w1 >> 32, neg);
+    lds_add(acc, c + 4, w2, neg);
+}
+
+// Knuth TwoSum: s + err == a + b exactly (no overflow).
+__device__ __forceinline__ double two_sum(double a, double b, double& err) {
+    double s = a + b;
+    double bp = s - a;
+    double ap = s - bp;
+    err = (a - ap) + (b - bp);
+    return s;
+}
+
+// Add v into expansion terms e[start..K-1]; a non-zero remainder goes to LDS.
+template <int K>
+__device__ __forceinline__ void expand(double (&e)[K], double v, int start, unsigned long long* acc) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k >= start) e[k] = two_sum(e[k], v, v);
+    }
+    if (v != 0.0) deposit_double(acc, v);
+}
+
+// Accumulate x*y exactly.  flags: block-shared non-finite flags.
+template <int K>
+__device__ __forceinline__ void accumulate(double (&e)[K], double x, double y,
+                                           unsigned long long* acc, uint32_t* flags) {
+    double p = x * y;
+    int pe = (int)((dbits(p) >> 52) & 0x7ff);
+    if (pe >= 54 && pe <= 2002) {            // 2^-969 <= |p| < 2^980: TwoProd is exact
+        double err = fma(x, y, -p);
+        expand<K>(e, p, 0, acc);
+        expand<K>(e, err, K > 1 ? 1 : 0, acc);
+    } else {
+        bool fx = isfinite(x), fy = isfinite(y);
+        if (!(fx && fy)) {
+            uint32_t f;
+            if (isnan(x) || isnan(y) || x == 0.0 || y == 0.0) f = F_NAN;
+            else f = ((x > 0.0) == (y > 0.0)) ? F_PINF : F_NINF;
+            atomicOr(flags, f);
+        } else if (x != 0.0 && y != 0.0) {
+            deposit_product(acc, x, y);      // tiny, underflowed or huge product
+        }
+    }
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o);
+    return v;
+}
+
+// Exact wave-wide deposit of one double per lane (zeros ignored).  All 64 lanes of
+// the wave must call it together.
+__device__ __forceinline__ void wave_deposit(unsigned long long* acc, double v) {
+    bool nz = v != 0.0;
+    if (__ballot(nz) == 0) return;
+    uint64_t m = 0; int P = 0; bool neg = false;
+    if (nz) decompose(v, m, P, neg);
+    int c = nz ? (P >> 5) : 0x7fffffff;
+    int cmin = wave_min_i(c);
+    bool inwin = nz && (c - cmin) <= 1;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    if (inwin) {
+        int sh = P - 32 * cmin;                 // 0..63
+        uint64_t w0 = m << sh;
+        uint64_t w1 = sh ? (m >> (64 - sh)) : 0;
+        double sg = neg ? -1.0 : 1.0;
+        q0 = sg * (double)(w0 & 0xffffffffull);
+        q1 = sg * (double)(w0 >> 32);
+        q2 = sg * (double)(w1 & 0xffffffffull);
+        q3 = sg * (double)(w1 >> 32);
+    }
+    // sums of <= 64 integers of magnitude < 2^32: exact in FP64
+    q0 = wave_sum_d(q0);
+    q1 = wave_sum_d(q1);
+    q2 = wave_sum_d(q2);
+    q3 = wave_sum_d(q3);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        if (q0 != 0.0) atomicAdd(acc + cmin, (unsigned long long)(long long)q0);
+        if (q1 != 0.0) atomicAdd(acc + cmin + 1, (unsigned long long)(long long)q1);
+        if (q2 != 0.0) atomicAdd(acc + cmin + 2, (unsigned long long)(long long)q2);
+        if (q3 != 0.0 && cmin + 3 < NCH) atomicAdd(acc + cmin + 3, (unsigned long long)(long long)q3);
+    }
+    if (nz && !inwin) deposit_double(acc, v);
+}
+
+// ------------------------------------------------------------------------------
+// Block-level protocol.  `acc` is __shared__ unsigned long long[D*NCH], `flags`
+// __shared__ uint32_t[D]; both zeroed by block_init before the loop.
+template <int D>
+__device__ __forceinline__ void block_init(unsigned long long* acc, uint32_t* flags) {
+    for (int i = threadIdx.x; i < D * NCH; i += blockDim.x) acc[i] = 0ull;
+    if (threadIdx.x < D) flags[threadIdx.x] = 0u;
+    __syncthreads();
+}
+
+// Flush every lane's expansions (all threads of the block call this).
+template <int D, int K>
+__device__ __forceinline__ void block_flush(double (&e)[D][K], unsigned long long* acc) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) wave_deposit(acc + d * NCH, e[d][k]);
+    }
+    __syncthreads();
+}
+
+// Write this block's record (one-step carry normalisation, non-zero range).
+// `tmp` is __shared__ long long[D*NCH] scratch, `rng` __shared__ int[2*D].
+template <int D>
+__device__ void block_write(const Site& site, unsigned long long* acc, uint32_t* flags,
+                            long long* tmp, int* rng) {
+    const int tid = threadIdx.x;
+    if (tid < D) { rng[2 * tid] = NCH; rng[2 * tid + 1] = -1; }
+    // balanced split: a = lo + 2^32 hi with lo in [-2^31, 2^31)
+    for (int i = tid; i < D * NCH; i += blockDim.x) {
+        long long a = (long long)acc[i];
+        int c = i % NCH;
+        long long hi = (c == NCH - 1) ? 0 : ((a - (long long)(int32_t)(uint32_t)a) >> 32);
+        tmp[i] = hi;
+    }
+    __syncthreads();
+    for (int i = tid; i < D * NCH; i += blockDim.x) {
+        long long a = (long long)acc[i];
+        int c = i % NCH, d = i / NCH;
+        long long lo = (c == NCH - 1) ? a : (long long)(int32_t)(uint32_t)a;
+        long long v = lo + (c > 0 ? tmp[i - 1] : 0);
+        acc[i] = (unsigned long long)v;
+        if (v != 0) {
+            atomicMin(&rng[2 * d], c);
+            atomicMax(&rng[2 * d + 1], c);
+        }
+    }
+    __syncthreads();
+    const size_t b = blockIdx.x;
+    for (int i = tid; i < D * NCH; i += blockDim.x) {
+        int c = i % NCH, d = i / NCH;
+        if (c >= rng[2 * d] && c <= rng[2 * d + 1])
+            site.dig[(b * D + d) * NCH + c] = (long long)acc[i];
+    }
+    if (tid < D) {
+        RecHdr h;
+        h.lo = rng[2 * tid];
+        h.hi = rng[2 * tid + 1];
+        h.flags = flags[tid];
+        h.pad = 0;
+        site.hdr[b * D + tid] = h;
+    }
+}
+
+// Returns true in exactly one block (the last to finish); that block may then read
+// every record.  All threads call it.
+__device__ __forceinline__ bool block_is_last(const Site& site, int* sh_flag) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = atomicAdd(site.counter, 1u);
+        *sh_flag = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    bool last = *sh_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Round S * 2^-2148 (chunks in s[0..NCH-1], destroyed) to FP64, nearest-even.
+__device__ double round_chunks(long long* s, uint32_t flags) {
+    if ((flags & F_NAN) || ((flags & F_PINF) && (flags & F_NINF))) return __longlong_as_double(0x7ff8000000000000ll);
+    if (flags & F_PINF) return __longlong_as_double(0x7ff0000000000000ll);
+    if (flags & F_NINF) return __longlong_as_double((long long)0xfff0000000000000ull);
+    // balanced normalisation: digits in [-2^31, 2^31) except the top chunk
+    long long carry = 0;
+    for (int c = 0; c < NCH - 1; ++c) {
+        long long v = s[c] + carry;
+        long long lo = (long long)(int32_t)(uint32_t)v;
+        carry = (v - lo) >> 32;
+        s[c] = lo;
+    }
+    s[NCH - 1] += carry;
+    int top = -1;
+    for (int c = NCH - 1; c >= 0; --c) {
+        if (s[c] != 0) { top = c; break; }
+    }
+    if (top < 0) return 0.0;                       // exact zero -> +0
+    const bool neg = s[top] < 0;
+    // magnitude, standard digits in [0, 2^32) (top chunk keeps the excess)
+    carry = 0;
+    for (int c = 0; c < NCH; ++c) {
+        long long v = (neg ? -s[c] : s[c]) + carry;
+        if (c == NCH - 1) { s[c] = v; break; }
+        long long d = v & 0xffffffffll;
+        carry = (v - d) >> 32;
+        s[c] = d;
+    }
+    int h = -1;
+    for (int c = NCH - 1; c >= 0; --c) {
+        if (s[c] != 0) { h = c; break; }
+    }
+    const uint64_t sign = neg ? 0x8000000000000000ull : 0ull;
+    if (h >= 100) return __longlong_as_double((long long)(sign | 0x7ff0000000000000ull));  // >= 2^1052
+    const int msb = 32 * h + 31 - __clz((unsigned int)s[h]);
+    const int cut = max(msb - 52, 1074);           // bit index of the last place
+    auto get64 = [&](int off) -> uint64_t {
+        int c = off >> 5, sh = off & 31;
+        uint64_t w = (uint64_t)s[c] | ((uint64_t)s[c + 1] << 32);
+        uint64_t r = w >> sh;
+        if (sh) r |= (uint64_t)s[c + 2] << (64 - sh);
+        return r;
+    };
+    uint64_t mant = get64(cut) & ((1ull << 53) - 1);
+    const int g = cut - 1;
+    uint64_t guard = get64(g) & 1ull;
+    bool sticky = false;
+    {
+        int c = g >> 5, sh = g & 31;
+        for (int k = 0; k < c; ++k) sticky |= (s[k] != 0);
+        if (sh) sticky |= ((uint64_t)s[c] & ((1ull << sh) - 1)) != 0;
+    }
+    uint64_t bits = ((uint64_t)(cut - 1074) << 52) + mant;
+    if (guard && (sticky || (mant & 1ull))) bits += 1;
+    if (bits >= 0x7ff0000000000000ull) bits = 0x7ff0000000000000ull;
+    return __longlong_as_double((long long)(sign | bits));
+}
+
+// Last block: sum all records, round each of the D dots; results in out[d] (LDS or
+// registers of thread 0).  `fin` is __shared__ long long[D*NCH], `hdr_s` __shared__
+// int[2] scratch, `fl` __shared__ uint32_t[D].  Returns after a __syncthreads with
+// out[] valid in every thread.
+template <int D>
+__device__ void last_block_reduce(const Site& site, long long* fin, uint32_t* fl, int* rng,
+                                  double* out) {
+    const int tid = threadIdx.x;
+    const int G = gridDim.x;
+    for (int i = tid; i < D * NCH; i += blockDim.x) fin[i] = 0;
+    if (tid < D) { fl[tid] = 0u; rng[2 * tid] = NCH; rng[2 * tid + 1] = -1; }
+    __syncthreads();
+    for (int j = tid; j < G * D; j += blockDim.x) {
+        RecHdr h = site.hdr[j];
+        int d = j % D;
+        if (h.flags) atomicOr(&fl[d], h.flags);
+        if (h.lo <= h.hi) {
+            atomicMin(&rng[2 * d], h.lo);
+            atomicMax(&rng[2 * d + 1], h.hi);
+        }
+    }
+    __syncthreads();
+    for (int d = 0; d < D; ++d) {
+        const int LO = rng[2 * d], HI = rng[2 * d + 1];
+        if (LO > HI) continue;
+        const int W = HI - LO + 1;
+        const long long items = (long long)G * W;
+        for (long long j = tid; j < items; j += blockDim.x) {
+            int g = (int)(j / W);
+            int c = LO + (int)(j % W);
+            RecHdr h = site.hdr[(size_t)g * D + d];
+            if (c >= h.lo && c <= h.hi) {
+                long long v = site.dig[((size_t)g * D + d) * NCH + c];
+                atomicAdd((unsigned long long*)&fin[d * NCH + c], (unsigned long long)v);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < D) out[tid] = round_chunks(fin + tid * NCH, fl[tid]);
+    if (tid == 0) *site.counter = 0u;
+    __syncthreads();
+}
+
+}  // namespace xd
