@@ -50,6 +50,12 @@ typedef enum { PBCG_F64 = 0, PBCG_F32 = 1 } pbcg_dtype;
 typedef enum { PBCG_ALG_PBICGSTAB = 0, PBCG_ALG_BICGSTAB = 1 } pbcg_alg;
 typedef enum { PBCG_PREC_FP64 = 0, PBCG_PREC_FP32_IR = 1 } pbcg_prec;
 
+/* SpMV kernel shape.  SEQ sums every row left to right in storage order (the order of
+ * the plain definition of A.x, so results are reproducible bit for bit by a sequential
+ * CPU loop); VECTOR uses L = 2..32 lanes per row (L from the mean row length) and
+ * WAVE one 64-lane wavefront per row, both with a fixed tree order per matrix. */
+typedef enum { PBCG_SPMV_SEQ = 0, PBCG_SPMV_VECTOR = 1, PBCG_SPMV_WAVE = 2 } pbcg_spmv_kind;
+
 /* Square CSR matrix.  `val` points to nnz values of type `val_type`. */
 typedef struct {
     int32_t n;
@@ -78,6 +84,8 @@ typedef struct {
     int32_t batch;             /* iterations enqueued between status polls (default 16)      */
     int32_t stall_window;      /* with M + fallback: iterations without halving the recursive
                                   residual that count as a stall (default 200)               */
+    int32_t spmv_kind;         /* pbcg_spmv_kind used for every A.v of the solve (default SEQ) */
+    int32_t pad;
 } pbcg_opts;
 
 /* Result summary (host struct). */
@@ -101,12 +109,16 @@ typedef struct {
 /* ---------------------------------------------------------------------------------
  * Sparse matrix-vector product y = A x (paper: the products A p_i, A q_i, A z_i,
  * A w_i of Algorithms 1 and 2).  A: FP64 or FP32 values; x, y: FP64; FP64 accumulation
- * in a fixed per-matrix order (deterministic run to run; not the oracle's sequential
- * order, so agreement is within gamma_len * sum |a x|).  y must not alias x.
+ * with every row summed left to right in storage order (PBCG_SPMV_SEQ).  y must not
+ * alias x.
  */
 int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream);
 
-/* FP32 y = A x with FP32 values, vectors and accumulation (the inner solver's SpMV). */
+/* Same with an explicit kernel shape (pbcg_spmv_kind). */
+int csr_spmv_config(const pbcg_csr* A, const double* x, double* y, int32_t kind, void* stream);
+
+/* FP32 y = A x with FP32 values, vectors and accumulation (the inner solver's SpMV),
+ * rows summed left to right. */
 int csr_spmv_f32(const pbcg_csr* A32, const float* x, float* y, void* stream);
 
 /* ---------------------------------------------------------------------------------

@@ -24,6 +24,7 @@ ERR_INVALID, ERR_HIP, ERR_NONFINITE, ERR_WORKSPACE = -1, -2, -3, -4
 F64, F32 = 0, 1
 ALG_PBICGSTAB, ALG_BICGSTAB = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
+SPMV_SEQ, SPMV_VECTOR, SPMV_WAVE = 0, 1, 2
 
 _P = ctypes.c_void_p
 
@@ -38,7 +39,8 @@ class PbcgOpts(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("M", ctypes.POINTER(PbcgCsr)), ("fallback", ctypes.c_int32),
                 ("history_len", ctypes.c_int32), ("history", _P), ("r_out", _P),
-                ("batch", ctypes.c_int32), ("stall_window", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("stall_window", ctypes.c_int32),
+                ("spmv_kind", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class PbcgInfo(ctypes.Structure):
@@ -57,7 +59,7 @@ class PbcgVectors(ctypes.Structure):
 
 
 EXPORTS = [
-    "csr_spmv", "csr_spmv_f32", "exdot_workspace_bytes", "exdot", "exdot_config",
+    "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "exdot_workspace_bytes", "exdot", "exdot_config",
     "pbcg_phase_workspace_bytes", "pbcg_phase_a", "pbcg_phase_b", "pbicgstab_workspace_bytes",
     "pbicgstab_solve", "pbcg_default_opts", "pbcg_status_string", "pbcg_abi_version",
 ]
@@ -77,6 +79,7 @@ def lib():
     CP = ctypes.POINTER(PbcgCsr)
     sig = {
         "csr_spmv": (ctypes.c_int, [CP, _P, _P, _P]),
+        "csr_spmv_config": (ctypes.c_int, [CP, _P, _P, i32, _P]),
         "csr_spmv_f32": (ctypes.c_int, [CP, _P, _P, _P]),
         "exdot_workspace_bytes": (sz, [i64]),
         "exdot": (ctypes.c_int, [i64, _P, _P, _P, _P, sz, _P]),
@@ -166,11 +169,14 @@ class CSR:
         return ctypes.byref(self._c)
 
 
-def csr_spmv(A: CSR, x, y=None):
+def csr_spmv(A: CSR, x, y=None, kind: int | None = None):
     torch = _torch()
     if y is None:
         y = torch.empty(A.n, dtype=torch.float64, device=x.device)
-    _check(lib().csr_spmv(A.c, _ptr(x), _ptr(y), _stream()), "csr_spmv")
+    if kind is None:
+        _check(lib().csr_spmv(A.c, _ptr(x), _ptr(y), _stream()), "csr_spmv")
+    else:
+        _check(lib().csr_spmv_config(A.c, _ptr(x), _ptr(y), int(kind), _stream()), "csr_spmv_config")
     return y
 
 

@@ -79,14 +79,25 @@ bool csr_ok(const pbcg_csr* A) {
 }
 
 // ---------------------------------------------------------------- launchers
+constexpr int SEQ_CAP = 2048;   // LDS staging entries per chunk of the row-sequential SpMV
+
+// kind: PBCG_SPMV_SEQ (rows summed left to right), PBCG_SPMV_VECTOR (L lanes per row
+// from the mean row length, tree order), PBCG_SPMV_WAVE (one wavefront per row).
 template <class VT, class XT, class AT, class Epi>
-void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hipStream_t s) {
+void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hipStream_t s,
+                   int kind = PBCG_SPMV_SEQ) {
     const int n = A->n;
     if (n == 0) return;
-    const int L = spmv_lanes(A->n, A->nnz);
+    const VT* val = (const VT*)A->val;
+    if (kind == PBCG_SPMV_SEQ) {
+        const int grid = (n + BLOCK - 1) / BLOCK;
+        spmv_seq_kernel<SEQ_CAP, VT, XT, AT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
+                                                                          halt);
+        return;
+    }
+    const int L = kind == PBCG_SPMV_WAVE ? 64 : std::min(spmv_lanes(A->n, A->nnz), 32);
     const int rows = BLOCK / L;
     const int grid = (n + rows - 1) / rows;
-    const VT* val = (const VT*)A->val;
 #define SPMV_CASE(LL) \
     case LL: spmv_kernel<LL, VT, XT, AT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, halt); break;
     switch (L) {
@@ -97,19 +108,26 @@ void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hip
 
 // FP64 accumulation, values FP64 or FP32, x FP64
 template <class Epi>
-void launch_spmv64(const pbcg_csr* A, const double* x, Epi epi, const int* halt, hipStream_t s) {
-    if (A->val_type == PBCG_F64) launch_spmv_t<double, double, double>(A, x, epi, halt, s);
-    else launch_spmv_t<float, double, double>(A, x, epi, halt, s);
+void launch_spmv64(const pbcg_csr* A, const double* x, Epi epi, const int* halt, hipStream_t s,
+                   int kind = PBCG_SPMV_SEQ) {
+    if (A->val_type == PBCG_F64) launch_spmv_t<double, double, double>(A, x, epi, halt, s, kind);
+    else launch_spmv_t<float, double, double>(A, x, epi, halt, s, kind);
 }
 
 template <int D, class VT, class Epi>
 void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site site, const int* halt,
-                       hipStream_t s) {
+                       hipStream_t s, int kind) {
     const int n = A->n;
-    const int L = spmv_lanes(A->n, A->nnz);
+    const VT* val = (const VT*)A->val;
+    if (kind == PBCG_SPMV_SEQ) {
+        int grid = std::max(1, std::min(DOT_GRID_DEFAULT, (n + BLOCK - 1) / BLOCK));
+        spmv_seq_dot_kernel<SEQ_CAP, D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
+                                                                               epi, site, halt);
+        return;
+    }
+    const int L = kind == PBCG_SPMV_WAVE ? 64 : std::min(spmv_lanes(A->n, A->nnz), 32);
     const int rows = BLOCK / L;
     int grid = std::max(1, std::min(DOT_GRID_DEFAULT, (n + rows - 1) / rows));
-    const VT* val = (const VT*)A->val;
 #define SD_CASE(LL) \
     case LL: spmv_dot_kernel<LL, D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, site, halt); break;
     switch (L) {
@@ -120,9 +138,9 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
 
 template <int D, class Epi>
 void launch_spmv_dot(const pbcg_csr* A, const double* x, Epi epi, xd::Site site, const int* halt,
-                     hipStream_t s) {
-    if (A->val_type == PBCG_F64) launch_spmv_dot_t<D, double>(A, x, epi, site, halt, s);
-    else launch_spmv_dot_t<D, float>(A, x, epi, site, halt, s);
+                     hipStream_t s, int kind = PBCG_SPMV_SEQ) {
+    if (A->val_type == PBCG_F64) launch_spmv_dot_t<D, double>(A, x, epi, site, halt, s, kind);
+    else launch_spmv_dot_t<D, float>(A, x, epi, site, halt, s, kind);
 }
 
 template <int D, class Op>
@@ -270,7 +288,7 @@ int pin_init() {
 // ============================================================================ C-ABI
 extern "C" {
 
-int pbcg_abi_version(void) { return 1; }
+int pbcg_abi_version(void) { return 2; }
 
 const char* pbcg_status_string(int status) {
     switch (status) {
@@ -299,13 +317,18 @@ void pbcg_default_opts(pbcg_opts* o) {
     o->stall_window = 200;
 }
 
-int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream) {
+int csr_spmv_config(const pbcg_csr* A, const double* x, double* y, int32_t kind, void* stream) {
     if (!csr_ok(A) || (A->n > 0 && (!x || !y))) return PBCG_ERR_INVALID;
     if (x == y && A->n > 0) return PBCG_ERR_INVALID;
+    if (kind != PBCG_SPMV_SEQ && kind != PBCG_SPMV_VECTOR && kind != PBCG_SPMV_WAVE) return PBCG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    launch_spmv64(A, x, EpiStore<double>{y}, nullptr, s);
+    launch_spmv64(A, x, EpiStore<double>{y}, nullptr, s, kind);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
+}
+
+int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream) {
+    return csr_spmv_config(A, x, y, PBCG_SPMV_SEQ, stream);
 }
 
 int csr_spmv_f32(const pbcg_csr* A, const float* x, float* y, void* stream) {
@@ -444,15 +467,16 @@ struct Driver {
     hipStream_t s;
     int* halt;
     int batch;
+    int kind;              // SpMV kernel shape
     pbcg_csr A32;          // FP32 copy of A (refinement)
 
     // out = A in, or A (M in)
     void op(const double* in, double* out) {
         if (M) {
-            launch_spmv64(M, in, EpiStore<double>{W.tmp2}, halt, s);
-            launch_spmv64(A, W.tmp2, EpiStore<double>{out}, halt, s);
+            launch_spmv64(M, in, EpiStore<double>{W.tmp2}, halt, s, kind);
+            launch_spmv64(A, W.tmp2, EpiStore<double>{out}, halt, s, kind);
         } else {
-            launch_spmv64(A, in, EpiStore<double>{out}, halt, s);
+            launch_spmv64(A, in, EpiStore<double>{out}, halt, s, kind);
         }
     }
 
@@ -466,11 +490,11 @@ struct Driver {
     void true_residual_enqueue() {
         const double* xt = x;
         if (M) {
-            launch_spmv64(M, x, EpiStore<double>{W.tmp2}, nullptr, s);
+            launch_spmv64(M, x, EpiStore<double>{W.tmp2}, nullptr, s, kind);
             xt = W.tmp2;
         }
         EpiResidDot<FinTrue> epi{b, W.tmp, FinTrue{W.st}};
-        launch_spmv_dot<1>(A, xt, epi, W.site, nullptr, s);
+        launch_spmv_dot<1>(A, xt, epi, W.site, nullptr, s, kind);
     }
 
     void dot_enqueue(const double* a, const double* bb, int64_t n) {
@@ -522,9 +546,9 @@ struct Driver {
         const int n = A->n;
         const double* scal = &W.st->alpha;
         launch_ew(FnPUpdate{W.p, W.r, W.s, W.st}, n, halt, s);
-        launch_spmv_dot<1>(A, W.p, EpiSDot{W.s, W.rhat, FinAlphaB{W.st}}, W.site, halt, s);
+        launch_spmv_dot<1>(A, W.p, EpiSDot{W.s, W.rhat, FinAlphaB{W.st}}, W.site, halt, s, kind);
         launch_ew(FnQ{W.q, W.r, W.s, scal}, n, halt, s);
-        launch_spmv_dot<2>(A, W.q, EpiYDot{W.y, W.q, FinOmega{W.st, 0}}, W.site, halt, s);
+        launch_spmv_dot<2>(A, W.q, EpiYDot{W.y, W.q, FinOmega{W.st, 0}}, W.site, halt, s, kind);
         OpBiCGStabXR ox{x, W.p, W.q, W.y, W.rhat, W.r, scal, FinBiCGStabXR{W.st}};
         launch_ew_dot<2>(ox, n, W.site, halt, s);
     }
@@ -547,7 +571,7 @@ struct Driver {
             launch_ew(FnZero{x}, n, nullptr, s);
             launch_ew(FnCopy3{W.r, W.rhat, bicg ? W.p : nullptr, b}, n, nullptr, s);
         } else {
-            launch_spmv64(A, x, EpiResid<double>{b, W.r, W.rhat, bicg ? W.p : nullptr}, nullptr, s);
+            launch_spmv64(A, x, EpiResid<double>{b, W.r, W.rhat, bicg ? W.p : nullptr}, nullptr, s, kind);
         }
         if (!bicg) {
             op(W.r, W.w);
@@ -621,8 +645,8 @@ struct Driver {
         launch_single(FnZeroU32{W.fsite.counter, 1}, s);
         launch_ew(FnZeroF{W.d32}, n, nullptr, s);
         launch_ew(FnCopyF{W.rh32, W.r32}, n, nullptr, s);
-        launch_spmv_t<float, float, float>(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s);
-        launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, nullptr, s);
+        launch_spmv_t<float, float, float>(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s, kind);
+        launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, nullptr, s, kind);
         {
             FDotsOp<3, FFinInit> d{};
             d.a[0] = W.r32;  d.b[0] = W.r32;
@@ -647,11 +671,11 @@ struct Driver {
                 FPhaseA<FFinOmega> pa{W.r32, W.w32, W.t32, W.v32, W.rh32, W.p32, W.s32, W.z32, W.q32, W.y32,
                                       scal, first ? 1 : 0, FFinOmega{fs}};
                 launch_ew_fdot<4>(pa, n, W.fsite, fh, s);
-                launch_spmv_t<float, float, float>(&A32, W.z32, EpiStore<float>{W.v32}, fh, s);
+                launch_spmv_t<float, float, float>(&A32, W.z32, EpiStore<float>{W.v32}, fh, s, kind);
                 FPhaseB<FFinPhaseB> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
                                        FFinPhaseB{fs}};
                 launch_ew_fdot<3>(pb, n, W.fsite, fh, s);
-                launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, fh, s);
+                launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, fh, s, kind);
                 first = false;
             }
             HIPCHK(hipGetLastError());
@@ -704,7 +728,7 @@ struct Driver {
         double nu_prev = INFINITY;
         for (int k = 0; k <= max_outer; ++k) {
             EpiResidDot<FinIR> epi{b, W.r, FinIR{W.st}};
-            launch_spmv_dot<1>(A, x, epi, W.site, nullptr, s);
+            launch_spmv_dot<1>(A, x, epi, W.site, nullptr, s, kind);
             if (sync_state(&h)) return PBCG_ERR_HIP;
             outer = k;
             const double nu = h.last_dot;
@@ -748,6 +772,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     if (opts->prec == PBCG_PREC_FP32_IR && (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || A->val_type != PBCG_F64))
         return PBCG_ERR_INVALID;
     if (opts->history && opts->history_len < 0) return PBCG_ERR_INVALID;
+    if (opts->spmv_kind < PBCG_SPMV_SEQ || opts->spmv_kind > PBCG_SPMV_WAVE) return PBCG_ERR_INVALID;
     if (!ws || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
     Work W = carve_work(ws, ws_bytes, A->n, A->nnz, opts);
     if (!W.ok) return PBCG_ERR_WORKSPACE;
@@ -760,6 +785,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     D.A = A; D.M = opts->M; D.b = b; D.x = x; D.o = opts; D.W = W; D.s = (hipStream_t)stream;
     D.halt = &W.st->halt;
     D.batch = opts->batch > 0 ? opts->batch : 16;
+    D.kind = opts->spmv_kind;
     State h{};
     int status;
     int outer = 0, inner_total = 0;
@@ -775,7 +801,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
             D.true_residual_enqueue();
         }
         if (D.M) {  // x = M y
-            launch_spmv64(D.M, x, EpiStore<double>{W.tmp2}, nullptr, D.s);
+            launch_spmv64(D.M, x, EpiStore<double>{W.tmp2}, nullptr, D.s, D.kind);
             launch_ew(FnCopy{x, W.tmp2}, A->n, nullptr, D.s);
         }
         if (opts->r_out)

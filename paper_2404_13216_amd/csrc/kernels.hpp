@@ -1,10 +1,13 @@
 // HIP kernels of the p-BiCGStab hot path (gfx950, wave64).
 //
-//  * spmv_kernel       vector-CSR SpMV: L lanes per row (L = 2..64, chosen per matrix
-//                      from its mean row length), coalesced val/col reads, x gathers,
-//                      xor-butterfly row reduction (same bits in every lane), one
-//                      row group per L lanes, XCD-aware block -> row-range mapping.
-//  * spmv_dot_kernel   the same row loop, persistent grid, with an epilogue that
+//  * spmv_seq_kernel   row-sequential CSR SpMV: every row is summed left to right by
+//                      one lane (the summation order of the plain definition of A.x),
+//                      with the block's val/col range staged through LDS by coalesced
+//                      loads in chunks; XCD-aware block -> row-range mapping.
+//  * spmv_kernel       vector-CSR SpMV: L lanes per row (L = 2..32 from the mean row
+//                      length, or L = 64: one wavefront per row), coalesced val/col
+//                      reads, xor-butterfly row reduction (same bits in every lane).
+//  * spmv_*dot_kernel  the same row loops, persistent grid, with an epilogue that
 //                      produces D exact dot products (BiCGStab, true residual).
 //  * ew_dot_kernel     one fused element-wise pass (vector updates) with D exact dot
 //                      products accumulated on the fly (p-BiCGStab phases A and B).
@@ -77,6 +80,52 @@ spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ c
     if (lane == 0) epi(row, s);
 }
 
+// Row-sequential sums of rows [r0, r1) (one row per thread, thread i -> row r0+i).
+// val/col of the block's nnz range pass through LDS in chunks of CAP entries, loaded
+// with unit-stride (coalesced) reads; each lane then walks its row in storage order.
+// Every thread of the block must call this (it synchronises).
+template <int CAP, class VT, class XT, class AT>
+__device__ __forceinline__ AT seq_rows(int r0, int r1, const int32_t* __restrict__ rp,
+                                       const int32_t* __restrict__ ci, const VT* __restrict__ val,
+                                       const XT* __restrict__ x, VT* sval, int32_t* scol) {
+    const int row = r0 + (int)threadIdx.x;
+    const int a0 = rp[r0], a1 = rp[r1];
+    int a = 0, b = 0;
+    if (row < r1) { a = rp[row]; b = rp[row + 1]; }
+    AT s = AT(0);
+    for (int cs = a0; cs < a1; cs += CAP) {
+        const int ce = min(cs + CAP, a1);
+        for (int k = cs + (int)threadIdx.x; k < ce; k += blockDim.x) {
+            sval[k - cs] = val[k];
+            scol[k - cs] = ci[k];
+        }
+        __syncthreads();
+        const int lo = max(a, cs), hi = min(b, ce);
+        for (int k = lo; k < hi; ++k) {
+            AT prod = (AT)sval[k - cs] * (AT)x[scol[k - cs]];
+            s = s + prod;
+        }
+        __syncthreads();
+    }
+    return s;
+}
+
+template <int CAP, class VT, class XT, class AT, class Epi>
+__global__ void __launch_bounds__(256)
+spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, const int* halt) {
+    if (halt && *halt) return;
+    __shared__ VT sval[CAP];
+    __shared__ int32_t scol[CAP];
+    const int R = blockDim.x;
+    const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;
+    if (r0 >= n) return;  // uniform over the block
+    const int r1 = min(r0 + R, n);
+    AT s = seq_rows<CAP, VT, XT, AT>(r0, r1, rp, ci, val, x, sval, scol);
+    const int row = r0 + (int)threadIdx.x;
+    if (row < r1) epi(row, s);
+}
+
 // ----------------------------------------------------------------------------- dot sites
 #define XD_SHARED(D)                                   \
     __shared__ unsigned long long sh_acc[(D) * xd::NCH]; \
@@ -147,6 +196,44 @@ spmv_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
 #pragma unroll
         for (int o = L / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
         if (lane == 0) {
+            double xa[D], ya[D];
+            epi.row(row, s, xa, ya);
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+        }
+    }
+    xd::block_flush<D, K>(e, sh_acc);
+    xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
+    if (!xd::block_is_last(site, &sh_last)) return;
+    xd::last_block_reduce<D>(site, sh_tmp, sh_flags, sh_rng, sh_res);
+    if (threadIdx.x == 0) epi.finalize(sh_res);
+}
+
+// Row-sequential SpMV with D exact dots in the epilogue (persistent grid).
+template <int CAP, int D, int K, class VT, class Epi>
+__global__ void __launch_bounds__(256)
+spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                    const VT* __restrict__ val, const double* __restrict__ x, Epi epi,
+                    xd::Site site, const int* halt) {
+    if (halt && *halt) return;
+    XD_SHARED(D)
+    __shared__ VT sval[CAP];
+    __shared__ int32_t scol[CAP];
+    xd::block_init<D>(sh_acc, sh_flags);
+    epi.load();
+    double e[D][K];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int k = 0; k < K; ++k) e[d][k] = 0.0;
+    const int R = blockDim.x;
+    const int nblk = (n + R - 1) / R;
+    for (int bb = blockIdx.x; bb < nblk; bb += gridDim.x) {
+        const int r0 = bb * R, r1 = min(r0 + R, n);
+        double s = seq_rows<CAP, VT, double, double>(r0, r1, rp, ci, val, x, sval, scol);
+        const int row = r0 + (int)threadIdx.x;
+        if (row < r1) {
             double xa[D], ya[D];
             epi.row(row, s, xa, ya);
 #pragma unroll

@@ -1,10 +1,10 @@
 """GPU CSR SpMV vs the oracle.
 
-The GPU sums each row in a fixed tree order (per matrix), so it is not bit-equal to
-the oracle's left-to-right row sums; every row must satisfy the classical bound
-|y_gpu - y_exact| <= gamma_k * sum_j |a_ij x_j| (Higham, Accuracy and Stability of
-Numerical Algorithms, 3.1) with y_exact the exactly rounded row value, and results
-are bitwise identical run to run.
+The default kernel (row-sequential) sums each row left to right exactly like the
+oracle and must be bit-identical to it.  The vector-CSR and wavefront-per-row kernels
+sum in a fixed tree order; every row must satisfy the classical bound
+|y_gpu - y_oracle| <= 2 gamma_k sum_j |a_ij x_j| (Higham, Accuracy and Stability of
+Numerical Algorithms, 3.1), and every kernel is bitwise identical run to run.
 """
 import numpy as np
 import pytest
@@ -41,10 +41,14 @@ def test_spmv_bound_and_determinism(name, scale):
     A = pk.CSR.from_host(p.A)
     x = np.random.default_rng(1).uniform(-1, 1, p.A.n)
     tx = to_dev(x)
-    y1 = pk.csr_spmv(A, tx).cpu().numpy()
-    y2 = pk.csr_spmv(A, tx).cpu().numpy()
-    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
-    check_bound(p.A, x, y1)
+    ref = spmv(p.A, x)
+    y = pk.csr_spmv(A, tx).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
+    for kind in (pk.SPMV_VECTOR, pk.SPMV_WAVE):
+        y1 = pk.csr_spmv(A, tx, kind=kind).cpu().numpy()
+        y2 = pk.csr_spmv(A, tx, kind=kind).cpu().numpy()
+        assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+        check_bound(p.A, x, y1)
 
 
 def test_spmv_exact_on_integers():
@@ -60,8 +64,10 @@ def test_spmv_full_size_128():
     p = g.problem("cd3d_128")
     A = pk.CSR.from_host(p.A)
     x = np.random.default_rng(5).uniform(-1, 1, p.A.n)
-    y = pk.csr_spmv(A, to_dev(x)).cpu().numpy()
     ref = ctier.spmv(p.A, x)
+    y = pk.csr_spmv(A, to_dev(x)).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
+    y = pk.csr_spmv(A, to_dev(x), kind=pk.SPMV_VECTOR).cpu().numpy()
     err = np.abs(y - ref)
     absv = np.abs(p.A.val)
     rows = np.repeat(np.arange(p.A.n), np.diff(p.A.row_ptr))
@@ -82,10 +88,13 @@ def test_spmv_fp32_values_and_f32_path():
     y = pk.csr_spmv(A32, to_dev(x)).cpu().numpy()
     A32h = g.CSR(p.A.n, p.A.row_ptr, p.A.col_idx, p.A.val.astype(np.float32).astype(np.float64))
     check_bound(A32h, x, y)
-    # pure FP32 path
+    assert np.array_equal(y, spmv(A32h, x))  # FP32 values are exact in FP64
+    # pure FP32 path: row-sequential in float32, bit-identical to the oracle's float32 loop
+    from oracle.spmv import spmv_f32
     x32 = x.astype(np.float32)
-    y32 = pk.csr_spmv_f32(A32, to_dev(x32)).cpu().numpy().astype(np.float64)
-    check_bound(A32h, x32.astype(np.float64), y32, u=2.0 ** -24)
+    y32 = pk.csr_spmv_f32(A32, to_dev(x32)).cpu().numpy()
+    A32o = g.CSR(p.A.n, p.A.row_ptr, p.A.col_idx, p.A.val.astype(np.float32))
+    assert np.array_equal(y32.view(np.uint32), spmv_f32(A32o, x32).view(np.uint32))
 
 
 def test_empty_rows_and_ragged():
@@ -98,6 +107,22 @@ def test_empty_rows_and_ragged():
     val = rng.standard_normal(rp[-1])
     A = g.CSR(n, rp, ci, val)
     x = rng.standard_normal(n)
+    for kind in (pk.SPMV_SEQ, pk.SPMV_VECTOR, pk.SPMV_WAVE):
+        y = pk.csr_spmv(pk.CSR.from_host(A), to_dev(x), kind=kind).cpu().numpy()
+        assert np.all(y[lens == 0] == 0.0)
+        check_bound(A, x, y)
+    assert np.array_equal(pk.csr_spmv(pk.CSR.from_host(A), to_dev(x)).cpu().numpy(), spmv(A, x))
+
+
+def test_long_rows_chunked_staging():
+    """Rows longer than one LDS chunk (2048 entries) keep the left-to-right order."""
+    rng = np.random.default_rng(4)
+    n = 3000
+    lens = np.full(n, 3)
+    lens[[0, 7, 255, 256, 2999]] = [2999, 2500, 4000 % n, 2048, 2100]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(n, size=k, replace=False)) for k in lens]).astype(np.int32)
+    A = g.CSR(n, rp, ci, rng.standard_normal(rp[-1]))
+    x = rng.standard_normal(n)
     y = pk.csr_spmv(pk.CSR.from_host(A), to_dev(x)).cpu().numpy()
-    assert np.all(y[lens == 0] == 0.0)
-    check_bound(A, x, y)
+    assert np.array_equal(y.view(np.uint64), spmv(A, x).view(np.uint64))
