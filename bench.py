@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark: time to true relative residual 1e-10, plus SpMV / exact-dot HBM bandwidth.
+
+Workload (the 128^3 configuration): 3D upwind convection-diffusion on a 128^3 grid,
+7-point stencil, velocity (30, 20, 10), n = 2,097,152, nnz = 14,581,760, CSR FP64 with
+int32 indices; x* ~ U[-1, 1] (seed 1), b = A x*, x0 = 0, tol 1e-10 on the true
+relative residual.  One step = one complete FP64 p-BiCGStab solve with exact dot
+products (initialisation, every iteration's phase A / SpMV / phase B / SpMV with their
+fused exact dots, and the true-residual checks), inputs already resident in HBM.
+
+Also reported (outside the timed steps): the BiCGStab comparator and the FP32-inner /
+FP64-refinement form on the same matrix, per-kernel bandwidth of the SpMV kernels,
+phase A / phase B and the standalone exact dot (HIP events on the launch stream), the
+roofline of the dominant kernel, and the CPU oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--solve-only]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+CSRC = os.path.join(ROOT, "paper_2404_13216_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cd3d_128.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_launches(fn, reps, torch):
+    """Average duration of fn() over `reps` launches, HIP events on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / 1e3 / reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--solve-only", action="store_true")
+    ap.add_argument("--reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2404_13216_amd as pk
+    import synthgen as g
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    prob = g.problem("cd3d_128")
+    A = pk.CSR.from_host(prob.A, dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    n, nnz = prob.A.n, prob.A.nnz
+    log(f"workload cd3d_128 n={n} nnz={nnz} built in {time.time() - t0:.1f}s")
+
+    solver = pk.Solver(A, tol=1e-10, max_iter=10000)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+
+    def step():
+        x.zero_()
+        return solver.solve(b, x)
+
+    for _ in range(args.warmup):
+        _, info = step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        _, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    sec = elapsed / args.steps
+    info = infos[-1]
+    assert all(i["status"] == pk.OK and i["iterations"] == info["iterations"] for i in infos), infos
+    xs = torch.from_numpy(prob.xstar).to(dev)
+    err_xstar = (torch.linalg.norm(x - xs) / torch.linalg.norm(xs)).item()
+    log(f"p-BiCGStab: {sec * 1e3:.2f} ms/solve, {info['iterations']} iterations, "
+        f"true relres {info['true_relres']:.3e}")
+
+    out = {
+        "metric": "time to true rel. residual 1e-10 (plain FP64 p-BiCGStab, exact dots)",
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cd3d_128: 3D upwind convection-diffusion 128^3, v=(30,20,10), seed 1",
+                   "n": n, "nnz": nnz, "tol": 1e-10, "x0": "0", "alg": "p-BiCGStab",
+                   "dots": "exact (rounded once)", "spmv": "row-sequential CSR"},
+        "iterations": info["iterations"],
+        "true_relres": info["true_relres"],
+        "rel_err_vs_xstar": err_xstar,
+        "us_per_iteration": sec / max(info["iterations"], 1) * 1e6,
+    }
+
+    if not args.solve_only:
+        forms = {}
+        # BiCGStab comparator (Algorithm 1)
+        sb = pk.Solver(A, tol=1e-10, max_iter=10000, alg=pk.ALG_BICGSTAB)
+        xb = torch.zeros(n, dtype=torch.float64, device=dev)
+        sb.solve(b, xb)
+        xb.zero_()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        _, ib = sb.solve(b, xb)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb
+        forms["bicgstab_fp64"] = {"seconds": tb, "iterations": ib["iterations"], "true_relres": ib["true_relres"],
+                                  "status": ib["status"]}
+        # FP32 inner / FP64 refinement
+        si = pk.Solver(A, tol=1e-10, max_iter=5000, prec=pk.PREC_FP32_IR, inner_tol=1e-5)
+        xi = torch.zeros(n, dtype=torch.float64, device=dev)
+        si.solve(b, xi)
+        xi.zero_()
+        torch.cuda.synchronize()
+        ti = time.perf_counter()
+        _, ii = si.solve(b, xi)
+        torch.cuda.synchronize()
+        ti = time.perf_counter() - ti
+        forms["fp32_ir"] = {"seconds": ti, "inner_iterations": ii["iterations"], "outer": ii["outer_iterations"],
+                            "true_relres": ii["true_relres"], "status": ii["status"],
+                            "rel_diff_vs_fp64_solve": (torch.linalg.norm(xi - x) / torch.linalg.norm(x)).item(),
+                            "rel_err_vs_xstar": (torch.linalg.norm(xi - xs) / torch.linalg.norm(xs)).item()}
+        forms["pbicgstab_fp64"] = {"seconds": sec, "iterations": info["iterations"],
+                                   "true_relres": info["true_relres"]}
+        out["forms"] = forms
+        log("forms:", json.dumps(forms))
+
+        # per-kernel bandwidth (algorithmic bytes / average launch duration)
+        kern = {}
+        reps = args.reps
+        vin = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n)).to(dev)
+        vout = torch.empty(n, dtype=torch.float64, device=dev)
+        spmv_bytes = 12 * nnz + 20 * n
+        for name, kind in (("spmv_seq", pk.SPMV_SEQ), ("spmv_vector", pk.SPMV_VECTOR), ("spmv_wave", pk.SPMV_WAVE)):
+            dt = time_launches(lambda: pk.csr_spmv(A, vin, vout, kind=kind), reps, torch)
+            kern[name] = {"us": dt * 1e6, "bytes": spmv_bytes, "GBs": spmv_bytes / dt / 1e9}
+        # phases on random vectors of the workload size
+        rng = np.random.default_rng(1)
+        V = {k: torch.from_numpy(rng.standard_normal(n)).to(dev) for k in
+             ("x", "r", "rhat", "w", "t", "p", "s", "z", "q", "y", "v")}
+        scal = torch.tensor([0.5, 0.25, 0.75], dtype=torch.float64, device=dev)
+        dots = torch.empty(4, dtype=torch.float64, device=dev)
+        wsp = torch.empty(pk.lib().pbcg_phase_workspace_bytes(n), dtype=torch.uint8, device=dev)
+        dt = time_launches(lambda: pk.pbcg_phase_a(V, scal, False, dots, wsp), reps, torch)
+        kern["phase_a"] = {"us": dt * 1e6, "bytes": 104 * n, "GBs": 104 * n / dt / 1e9}
+        dt = time_launches(lambda: pk.pbcg_phase_b(V, scal, dots, wsp), reps, torch)
+        kern["phase_b"] = {"us": dt * 1e6, "bytes": 80 * n, "GBs": 80 * n / dt / 1e9}
+        for ne in (1 << 21, 1 << 24, 1 << 26):
+            xa = torch.from_numpy(np.random.default_rng(2).uniform(-1, 1, ne)).to(dev)
+            ya = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, ne)).to(dev)
+            o1 = torch.empty(1, dtype=torch.float64, device=dev)
+            wse = torch.empty(pk.lib().exdot_workspace_bytes(ne), dtype=torch.uint8, device=dev)
+            dt = time_launches(lambda: pk.exdot(xa, ya, o1, wse), reps, torch)
+            kern[f"exdot_2^{ne.bit_length() - 1}"] = {"us": dt * 1e6, "bytes": 16 * ne, "GBs": 16 * ne / dt / 1e9}
+            del xa, ya
+        for k, v in kern.items():
+            v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
+        out["kernels"] = kern
+        log("kernels:", json.dumps(kern))
+        # dominant kernel per iteration: SpMV runs twice per iteration
+        per_iter = {"spmv_seq": 2 * kern["spmv_seq"]["us"], "phase_a": kern["phase_a"]["us"],
+                    "phase_b": kern["phase_b"]["us"]}
+        dom = max(per_iter, key=per_iter.get)
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
+                traffic = tr["kernels"][dom]["bytes_per_launch"]
+        out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": kern[dom]["GBs"], "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                           "algorithmic_bytes_per_launch": kern[dom]["bytes"],
+                           "avg_launch_us": kern[dom]["us"]}
+
+    if not args.no_cpu:
+        from oracle import ctier
+        cores = ctier.num_threads()
+        gi = info["iterations"]
+        t = time.perf_counter()
+        ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=0)
+        t_init = time.perf_counter() - t
+        t = time.perf_counter()
+        ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=4)
+        per_it = max(time.perf_counter() - t - t_init, 1e-9) / 4
+        k = int(max(4, min(gi, 20.0 / per_it)))  # bounded sample: about 20 s of CPU work
+        t = time.perf_counter()
+        rk = ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=k)
+        tk = time.perf_counter() - t
+        per_it = max(tk - t_init, 1e-9) / max(rk["iterations"], 1)
+        est = tk + max(gi - rk["iterations"], 0) * per_it
+        full = rk["iterations"] == gi and rk["status"] == 0
+        out["cpu_baseline"] = {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
+                               "sample": (f"C oracle p-BiCGStab (exact dots, OpenMP, {cores} threads) on the same "
+                                          f"workload: {rk['iterations']} of the GPU's {gi} iterations timed "
+                                          f"({tk:.2f}s)" + ("; complete solve, same iterates" if full else
+                                                            ", remainder extrapolated per iteration")),
+                               "seconds_per_iteration": per_it}
+        log("cpu baseline:", json.dumps(out["cpu_baseline"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
