@@ -163,34 +163,75 @@ def main():
         out["forms"] = forms
         log("forms:", json.dumps(forms))
 
-        # per-kernel bandwidth (algorithmic bytes / average launch duration)
+        # per-kernel bandwidth (algorithmic bytes / average launch duration), measured by
+        # replaying one p-BiCGStab iteration (phase A, v = A z, phase B, t = A w) on
+        # workload-sized vectors with HIP events around every launch on the launch stream;
+        # the iteration's working set (~400 MB) exceeds the 256 MB Infinity Cache.
         kern = {}
         reps = args.reps
-        vin = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n)).to(dev)
-        vout = torch.empty(n, dtype=torch.float64, device=dev)
-        spmv_bytes = 12 * nnz + 20 * n
-        for name, kind in (("spmv_seq", pk.SPMV_SEQ), ("spmv_vector", pk.SPMV_VECTOR), ("spmv_wave", pk.SPMV_WAVE)):
-            dt = time_launches(lambda: pk.csr_spmv(A, vin, vout, kind=kind), reps, torch)
-            kern[name] = {"us": dt * 1e6, "bytes": spmv_bytes, "GBs": spmv_bytes / dt / 1e9}
-        # phases on random vectors of the workload size
         rng = np.random.default_rng(1)
-        V = {k: torch.from_numpy(rng.standard_normal(n)).to(dev) for k in
+        V = {k: torch.from_numpy(rng.standard_normal(n) * 1e-3).to(dev) for k in
              ("x", "r", "rhat", "w", "t", "p", "s", "z", "q", "y", "v")}
         scal = torch.tensor([0.5, 0.25, 0.75], dtype=torch.float64, device=dev)
         dots = torch.empty(4, dtype=torch.float64, device=dev)
         wsp = torch.empty(pk.lib().pbcg_phase_workspace_bytes(n), dtype=torch.uint8, device=dev)
-        dt = time_launches(lambda: pk.pbcg_phase_a(V, scal, False, dots, wsp), reps, torch)
-        kern["phase_a"] = {"us": dt * 1e6, "bytes": 104 * n, "GBs": 104 * n / dt / 1e9}
-        dt = time_launches(lambda: pk.pbcg_phase_b(V, scal, dots, wsp), reps, torch)
-        kern["phase_b"] = {"us": dt * 1e6, "bytes": 80 * n, "GBs": 80 * n / dt / 1e9}
+        spmv_bytes = 12 * nnz + 20 * n
+        seq = [("phase_a", lambda: pk.pbcg_phase_a(V, scal, False, dots, wsp), 104 * n),
+               ("spmv_seq", lambda: pk.csr_spmv(A, V["z"], V["v"]), spmv_bytes),
+               ("phase_b", lambda: pk.pbcg_phase_b(V, scal, dots, wsp), 80 * n),
+               ("spmv_seq", lambda: pk.csr_spmv(A, V["w"], V["t"]), spmv_bytes)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)]
+        acc = {}
+        for it in range(reps + 2):
+            ev[0].record()
+            for k, (name, fn, nb) in enumerate(seq):
+                fn()
+                ev[k + 1].record()
+            ev[-1].synchronize()
+            if it < 2:
+                continue
+            for k, (name, fn, nb) in enumerate(seq):
+                acc.setdefault(name, [0.0, 0, nb])
+                acc[name][0] += ev[k].elapsed_time(ev[k + 1]) / 1e3
+                acc[name][1] += 1
+        for name, (tsum, cnt, nb) in acc.items():
+            dt = tsum / cnt
+            kern[name] = {"us": dt * 1e6, "bytes": nb, "GBs": nb / dt / 1e9, "launches": cnt}
+        # SpMV kernel shapes, each launch preceded by a 512 MB write that evicts the cache
+        flush = torch.empty(64 << 20, dtype=torch.float64, device=dev)
+        vin, vout = V["z"], V["v"]
+        for name, kind in (("spmv_seq_cold", pk.SPMV_SEQ), ("spmv_vector_cold", pk.SPMV_VECTOR),
+                           ("spmv_wave_cold", pk.SPMV_WAVE)):
+            tsum = 0.0
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            for it in range(min(reps, 20) + 1):
+                flush.zero_()
+                e0.record()
+                pk.csr_spmv(A, vin, vout, kind=kind)
+                e1.record()
+                e1.synchronize()
+                if it:
+                    tsum += e0.elapsed_time(e1) / 1e3
+            dt = tsum / min(reps, 20)
+            kern[name] = {"us": dt * 1e6, "bytes": spmv_bytes, "GBs": spmv_bytes / dt / 1e9}
+        del flush
+        # standalone exact dot, rotating over buffers larger than the cache
         for ne in (1 << 21, 1 << 24, 1 << 26):
-            xa = torch.from_numpy(np.random.default_rng(2).uniform(-1, 1, ne)).to(dev)
-            ya = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, ne)).to(dev)
+            nbuf = max(2, int((768 << 20) // (16 * ne)))
+            bufs = [(torch.from_numpy(np.random.default_rng(10 + i).uniform(-1, 1, ne)).to(dev),
+                     torch.from_numpy(np.random.default_rng(20 + i).uniform(-1, 1, ne)).to(dev))
+                    for i in range(nbuf)]
             o1 = torch.empty(1, dtype=torch.float64, device=dev)
             wse = torch.empty(pk.lib().exdot_workspace_bytes(ne), dtype=torch.uint8, device=dev)
-            dt = time_launches(lambda: pk.exdot(xa, ya, o1, wse), reps, torch)
+            cnt = [0]
+
+            def f():
+                xa, ya = bufs[cnt[0] % nbuf]
+                cnt[0] += 1
+                pk.exdot(xa, ya, o1, wse)
+            dt = time_launches(f, reps, torch)
             kern[f"exdot_2^{ne.bit_length() - 1}"] = {"us": dt * 1e6, "bytes": 16 * ne, "GBs": 16 * ne / dt / 1e9}
-            del xa, ya
+            del bufs
         for k, v in kern.items():
             v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
         out["kernels"] = kern
@@ -198,6 +239,7 @@ def main():
         # dominant kernel per iteration: SpMV runs twice per iteration
         per_iter = {"spmv_seq": 2 * kern["spmv_seq"]["us"], "phase_a": kern["phase_a"]["us"],
                     "phase_b": kern["phase_b"]["us"]}
+        out["iteration_kernel_us"] = per_iter
         dom = max(per_iter, key=per_iter.get)
         traffic = None
         if os.path.exists(TRAFFIC_FILE):

@@ -46,16 +46,14 @@ struct Carver {
 };
 
 size_t site_bytes(int grid_max) {
-    return 256 + align_up((size_t)grid_max * 4 * sizeof(xd::RecHdr), 256) +
-           align_up((size_t)grid_max * 4 * xd::NCH * sizeof(long long), 256) + 3 * 256;
+    return align_up((size_t)grid_max * 4 * sizeof(xd::RecHdr), 256) +
+           align_up((size_t)grid_max * 4 * xd::NCH * sizeof(long long), 256) + 2 * 256;
 }
 
-xd::Site carve_site(Carver& c, int grid_max, unsigned int** counter_out) {
+xd::Site carve_site(Carver& c, int grid_max) {
     xd::Site s;
-    s.counter = c.take<unsigned int>(64);
     s.hdr = c.take<xd::RecHdr>((size_t)grid_max * 4);
     s.dig = c.take<long long>((size_t)grid_max * 4 * xd::NCH);
-    if (counter_out) *counter_out = s.counter;
     return s;
 }
 
@@ -123,6 +121,7 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
         int grid = std::max(1, std::min(DOT_GRID_DEFAULT, (n + BLOCK - 1) / BLOCK));
         spmv_seq_dot_kernel<SEQ_CAP, D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
                                                                                epi, site, halt);
+        dot_finalize_kernel<D, Epi><<<1, 1024, 0, s>>>(epi, grid, site, halt);
         return;
     }
     const int L = kind == PBCG_SPMV_WAVE ? 64 : std::min(spmv_lanes(A->n, A->nnz), 32);
@@ -134,6 +133,7 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
         SD_CASE(2) SD_CASE(4) SD_CASE(8) SD_CASE(16) SD_CASE(32) SD_CASE(64)
     }
 #undef SD_CASE
+    dot_finalize_kernel<D, Epi><<<1, 1024, 0, s>>>(epi, grid, site, halt);
 }
 
 template <int D, class Epi>
@@ -154,12 +154,14 @@ void launch_ew_dot(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t
         default: ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt);
     }
 #undef EW_CASE
+    dot_finalize_kernel<D, Op><<<1, 1024, 0, s>>>(op, grid, site, halt);
 }
 
 template <int D, class Op>
 void launch_ew_fdot(Op op, int64_t n, FSite site, const int* halt, hipStream_t s) {
     int grid = dot_grid(n);
     ew_fdot_kernel<D, Op><<<grid, BLOCK, 0, s>>>(op, n, site, halt);
+    fdot_finalize_kernel<D, Op><<<1, 256, 0, s>>>(op, grid, site, halt);
 }
 
 template <class F>
@@ -355,8 +357,7 @@ int exdot_config(int64_t n, const double* x, const double* y, double* out, int32
     if (((uintptr_t)ws & 255) != 0) return PBCG_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws, ws_bytes);
-    xd::Site site = carve_site(c, DOT_GRID_MAX, nullptr);
-    launch_single(FnZeroU32{site.counter, 1}, s);
+    xd::Site site = carve_site(c, DOT_GRID_MAX);
     DotsOp<1, FinStore> op{};
     op.a[0] = x; op.b[0] = y;
     op.fin = FinStore{out, 1};
@@ -386,8 +387,7 @@ int pbcg_phase_a(int32_t n, const pbcg_vectors* V, const double* scal, int32_t f
     if (!ws || ws_bytes < pbcg_phase_workspace_bytes(n) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws, ws_bytes);
-    xd::Site site = carve_site(c, DOT_GRID_MAX, nullptr);
-    launch_single(FnZeroU32{site.counter, 1}, s);
+    xd::Site site = carve_site(c, DOT_GRID_MAX);
     PhaseA<FinStore> op{V->r, V->w, V->t, V->v, V->rhat, V->p, V->s, V->z, V->q, V->y, scal, first ? 1 : 0,
                         FinStore{dots_out, 4}};
     launch_ew_dot<4>(op, n, site, nullptr, s);
@@ -401,8 +401,7 @@ int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal, double* d
     if (!ws || ws_bytes < pbcg_phase_workspace_bytes(n) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws, ws_bytes);
-    xd::Site site = carve_site(c, DOT_GRID_MAX, nullptr);
-    launch_single(FnZeroU32{site.counter, 1}, s);
+    xd::Site site = carve_site(c, DOT_GRID_MAX);
     PhaseB<FinStore> op{V->x, V->p, V->q, V->y, V->t, V->v, V->rhat, V->r, V->w, scal, FinStore{dots_out, 3}};
     launch_ew_dot<3>(op, n, site, nullptr, s);
     HIPCHK(hipGetLastError());
@@ -436,8 +435,7 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
     Work W{};
     W.st = c.take<State>(1);
     W.fst = c.take<FState>(1);
-    W.site = carve_site(c, DOT_GRID_MAX, nullptr);
-    W.fsite.counter = c.take<unsigned int>(64);
+    W.site = carve_site(c, DOT_GRID_MAX);
     W.fsite.part = c.take<float>((size_t)DOT_GRID_MAX * 4);
     const size_t N = (size_t)std::max(n, 1);
     double** v64[] = {&W.rhat, &W.r, &W.w, &W.t, &W.p, &W.s, &W.z, &W.q, &W.y, &W.v, &W.tmp, &W.tmp2};
@@ -561,7 +559,6 @@ struct Driver {
         int hist_len = hist ? o->history_len : 0;
         if (!hist && W.hist) { hist = W.hist; hist_len = o->max_iter; }
         launch_single(FnInitState{W.st, o->tol, o->max_iter, hist, hist_len}, s);
-        launch_single(FnZeroU32{W.site.counter, 1}, s);
         {
             DotsOp<1, FinNormB> nb{};
             nb.a[0] = b; nb.b[0] = b; nb.fin = FinNormB{W.st};
@@ -642,7 +639,6 @@ struct Driver {
         int* fh = &fs->halt;
         const float* scal = &fs->alpha;
         launch_single(FnInitFState{fs, (float)o->inner_tol, std::max(o->max_iter, 1)}, s);
-        launch_single(FnZeroU32{W.fsite.counter, 1}, s);
         launch_ew(FnZeroF{W.d32}, n, nullptr, s);
         launch_ew(FnCopyF{W.rh32, W.r32}, n, nullptr, s);
         launch_spmv_t<float, float, float>(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s, kind);
@@ -705,7 +701,6 @@ struct Driver {
     int run_ir(State& h, int& outer, int& inner_total) {
         const int n = A->n;
         launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0}, s);
-        launch_single(FnZeroU32{W.site.counter, 1}, s);
         launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
         A32 = *A;
         A32.val = W.val32;

@@ -131,14 +131,12 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
     __shared__ unsigned long long sh_acc[(D) * xd::NCH]; \
     __shared__ long long sh_tmp[(D) * xd::NCH];          \
     __shared__ uint32_t sh_flags[(D)];                   \
-    __shared__ int sh_rng[2 * (D)];                      \
-    __shared__ int sh_last;                              \
-    __shared__ double sh_res[(D)];
+    __shared__ int sh_rng[2 * (D)];
 
 // Exact element-wise fused kernel.  Op provides:
 //   load()                      read device scalars
 //   elem(i, xa[D], ya[D])       updates for element i; dot operands
-//   finalize(const double* d)   run by one thread of the last block
+//   finalize(const double* d)   run by dot_finalize_kernel once the records are summed
 template <int D, int K, class Op>
 __global__ void __launch_bounds__(1024)
 ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt) {
@@ -161,9 +159,6 @@ ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt) {
     }
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
-    if (!xd::block_is_last(site, &sh_last)) return;
-    xd::last_block_reduce<D>(site, sh_tmp, sh_flags, sh_rng, sh_res);
-    if (threadIdx.x == 0) op.finalize(sh_res);
 }
 
 // Exact SpMV with an epilogue that returns D dot operands for its row.
@@ -205,9 +200,6 @@ spmv_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
     }
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
-    if (!xd::block_is_last(site, &sh_last)) return;
-    xd::last_block_reduce<D>(site, sh_tmp, sh_flags, sh_rng, sh_res);
-    if (threadIdx.x == 0) epi.finalize(sh_res);
 }
 
 // Row-sequential SpMV with D exact dots in the epilogue (persistent grid).
@@ -243,26 +235,21 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
     }
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
-    if (!xd::block_is_last(site, &sh_last)) return;
-    xd::last_block_reduce<D>(site, sh_tmp, sh_flags, sh_rng, sh_res);
-    if (threadIdx.x == 0) epi.finalize(sh_res);
 }
 
 // ----------------------------------------------------------------------------- FP32 plain dots
 struct FSite {
     float* part;            // [grid][D]
-    unsigned int* counter;
 };
 
 // Plain FP32 dots: per-thread sequential sums in grid-stride order, xor-butterfly
-// within the wave, waves in index order, blocks in index order (deterministic).
+// within the wave, waves in index order; the per-block partials are summed in a fixed
+// tree by fdot_finalize_kernel (deterministic for a given launch shape).
 template <int D, class Op>
 __global__ void __launch_bounds__(256)
 ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt) {
     if (halt && *halt) return;
     __shared__ float sh_w[D][16];
-    __shared__ int sh_last;
-    __shared__ float sh_res[D];
     op.load();
     float a[D];
 #pragma unroll
@@ -291,25 +278,49 @@ ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt) {
         for (int w = 0; w < nw; ++w) s = s + sh_w[threadIdx.x][w];
         site.part[(size_t)blockIdx.x * D + threadIdx.x] = s;
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int prev = atomicAdd(site.counter, 1u);
-        sh_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!sh_last) return;
-    __threadfence();
-    if (threadIdx.x < D) {
+}
+
+// One block: the D results are the block partials summed in a fixed tree order.
+template <int D, class Op>
+__global__ void __launch_bounds__(256)
+fdot_finalize_kernel(Op op, int G, FSite site, const int* halt) {
+    if (halt && *halt) return;
+    __shared__ float sh[D][256];
+    __shared__ float sh_res[D];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
         float s = 0.0f;
-        for (unsigned g = 0; g < gridDim.x; ++g) s = s + site.part[(size_t)g * D + threadIdx.x];
-        sh_res[threadIdx.x] = s;
+        for (int g = t; g < G; g += 256) s = s + site.part[(size_t)g * D + d];
+        sh[d][t] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        *site.counter = 0u;
-        op.finalize(sh_res);
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) sh[d][t] = sh[d][t] + sh[d][t + w];
+        }
+        __syncthreads();
     }
+    if (t < D) sh_res[t] = sh[t][0];
+    __syncthreads();
+    if (t == 0) op.finalize(sh_res);
+}
+
+// One block: sum the per-block exact records of a dot site and round (G <= GMAX).
+constexpr int DOT_GMAX = 1024;
+template <int D, class Op>
+__global__ void __launch_bounds__(1024)
+dot_finalize_kernel(Op op, int G, xd::Site site, const int* halt) {
+    if (halt && *halt) return;
+    __shared__ long long sh_fin[D * xd::NCH];
+    __shared__ short sh_lo[DOT_GMAX * D];
+    __shared__ short sh_hi[DOT_GMAX * D];
+    __shared__ uint32_t sh_fl[D];
+    __shared__ int sh_rng[2 * D];
+    __shared__ double sh_res[D];
+    xd::reduce_records<D, DOT_GMAX>(site, G, sh_fin, sh_lo, sh_hi, sh_fl, sh_rng, sh_res);
+    if (threadIdx.x == 0) op.finalize(sh_res);
 }
 
 // ----------------------------------------------------------------------------- small kernels

@@ -25,8 +25,8 @@
 //     their own term.
 //  3. Per block: the LDS accumulator is carry-normalised one step (chunks become
 //     |c| < 2^32 + 2^30) and its non-zero chunk range written to a per-block record;
-//     the last block to finish sums the records chunk by chunk (int64, order-free),
-//     normalises fully and rounds once to nearest-even.
+//     a one-block finalize kernel, launched after the producer, sums the records
+//     chunk by chunk (int64, order-free), normalises and rounds once to nearest-even.
 // Integer addition is associative, so the bits of the result do not depend on the
 // grid, the block size, K, or the order in which blocks finish.
 #pragma once
@@ -52,7 +52,6 @@ struct RecHdr {
 struct Site {
     RecHdr* hdr;           // [grid][D]
     long long* dig;        // [grid][D][NCH]
-    unsigned int* counter; // blocks finished (the last one resets it to 0)
 };
 
 __device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
@@ -263,63 +262,52 @@ __device__ void block_write(const Site& site, unsigned long long* acc, uint32_t*
     }
 }
 
-// Returns true in exactly one block (the last to finish); that block may then read
-// every record.  All threads call it.
-__device__ __forceinline__ bool block_is_last(const Site& site, int* sh_flag) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int prev = atomicAdd(site.counter, 1u);
-        *sh_flag = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    bool last = *sh_flag != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-// Round S * 2^-2148 (chunks in s[0..NCH-1], destroyed) to FP64, nearest-even.
-__device__ double round_chunks(long long* s, uint32_t flags) {
+// Round S * 2^-2148 to FP64, nearest-even.  s[0..NCH-1] holds chunk sums (destroyed);
+// only chunks in [lo, hi] are non-zero on entry (lo > hi: S = 0).
+__device__ double round_chunks(long long* s, uint32_t flags, int lo, int hi) {
     if ((flags & F_NAN) || ((flags & F_PINF) && (flags & F_NINF))) return __longlong_as_double(0x7ff8000000000000ll);
     if (flags & F_PINF) return __longlong_as_double(0x7ff0000000000000ll);
     if (flags & F_NINF) return __longlong_as_double((long long)0xfff0000000000000ull);
-    // balanced normalisation: digits in [-2^31, 2^31) except the top chunk
+    if (lo > hi) return 0.0;
+    // balanced normalisation: digits in [-2^31, 2^31); carries stop a few chunks above hi
     long long carry = 0;
-    for (int c = 0; c < NCH - 1; ++c) {
+    int c = lo;
+    for (; c < NCH - 1 && (c <= hi || carry != 0); ++c) {
         long long v = s[c] + carry;
-        long long lo = (long long)(int32_t)(uint32_t)v;
-        carry = (v - lo) >> 32;
-        s[c] = lo;
-    }
-    s[NCH - 1] += carry;
-    int top = -1;
-    for (int c = NCH - 1; c >= 0; --c) {
-        if (s[c] != 0) { top = c; break; }
-    }
-    if (top < 0) return 0.0;                       // exact zero -> +0
-    const bool neg = s[top] < 0;
-    // magnitude, standard digits in [0, 2^32) (top chunk keeps the excess)
-    carry = 0;
-    for (int c = 0; c < NCH; ++c) {
-        long long v = (neg ? -s[c] : s[c]) + carry;
-        if (c == NCH - 1) { s[c] = v; break; }
-        long long d = v & 0xffffffffll;
+        long long d = (long long)(int32_t)(uint32_t)v;
         carry = (v - d) >> 32;
         s[c] = d;
     }
+    if (carry != 0) s[c] += carry;      // c == NCH - 1: the top chunk keeps the excess
+    int top = -1;
+    for (int k = c; k >= lo; --k) {
+        if (s[k] != 0) { top = k; break; }
+    }
+    if (top < 0) return 0.0;            // exact zero -> +0
+    const bool neg = s[top] < 0;
+    // magnitude in standard digits [0, 2^32) (a borrow can only shrink the top)
+    carry = 0;
+    for (int k = lo; k <= top; ++k) {
+        long long v = (neg ? -s[k] : s[k]) + carry;
+        if (k == NCH - 1) { s[k] = v; break; }
+        long long d = v & 0xffffffffll;
+        carry = (v - d) >> 32;
+        s[k] = d;
+    }
     int h = -1;
-    for (int c = NCH - 1; c >= 0; --c) {
-        if (s[c] != 0) { h = c; break; }
+    for (int k = top; k >= lo; --k) {
+        if (s[k] != 0) { h = k; break; }
     }
     const uint64_t sign = neg ? 0x8000000000000000ull : 0ull;
     if (h >= 100) return __longlong_as_double((long long)(sign | 0x7ff0000000000000ull));  // >= 2^1052
     const int msb = 32 * h + 31 - __clz((unsigned int)s[h]);
     const int cut = max(msb - 52, 1074);           // bit index of the last place
+    auto dig = [&](int k) -> uint64_t { return (k >= lo && k <= h) ? (uint64_t)s[k] : 0ull; };
     auto get64 = [&](int off) -> uint64_t {
-        int c = off >> 5, sh = off & 31;
-        uint64_t w = (uint64_t)s[c] | ((uint64_t)s[c + 1] << 32);
+        int k = off >> 5, sh = off & 31;
+        uint64_t w = dig(k) | (dig(k + 1) << 32);
         uint64_t r = w >> sh;
-        if (sh) r |= (uint64_t)s[c + 2] << (64 - sh);
+        if (sh) r |= dig(k + 2) << (64 - sh);
         return r;
     };
     uint64_t mant = get64(cut) & ((1ull << 53) - 1);
@@ -327,9 +315,9 @@ __device__ double round_chunks(long long* s, uint32_t flags) {
     uint64_t guard = get64(g) & 1ull;
     bool sticky = false;
     {
-        int c = g >> 5, sh = g & 31;
-        for (int k = 0; k < c; ++k) sticky |= (s[k] != 0);
-        if (sh) sticky |= ((uint64_t)s[c] & ((1ull << sh) - 1)) != 0;
+        int k = g >> 5, sh = g & 31;
+        for (int j = lo; j < k && j <= h; ++j) sticky |= (s[j] != 0);
+        if (sh) sticky |= (dig(k) & ((1ull << sh) - 1)) != 0;
     }
     uint64_t bits = ((uint64_t)(cut - 1074) << 52) + mant;
     if (guard && (sticky || (mant & 1ull))) bits += 1;
@@ -337,21 +325,22 @@ __device__ double round_chunks(long long* s, uint32_t flags) {
     return __longlong_as_double((long long)(sign | bits));
 }
 
-// Last block: sum all records, round each of the D dots; results in out[d] (LDS or
-// registers of thread 0).  `fin` is __shared__ long long[D*NCH], `hdr_s` __shared__
-// int[2] scratch, `fl` __shared__ uint32_t[D].  Returns after a __syncthreads with
-// out[] valid in every thread.
-template <int D>
-__device__ void last_block_reduce(const Site& site, long long* fin, uint32_t* fl, int* rng,
-                                  double* out) {
+// Sum the G per-block records of D dots and round each (one block, run by the
+// finalize kernel after the producer kernel has completed).  `fin` is __shared__
+// long long[D*NCH], `hlo/hhi` __shared__ short[G_MAX*D], `fl` uint32_t[D], `rng`
+// int[2D]; the D results land in out[] (shared), valid after the final barrier.
+template <int D, int GMAX>
+__device__ void reduce_records(const Site& site, int G, long long* fin, short* hlo, short* hhi,
+                               uint32_t* fl, int* rng, double* out) {
     const int tid = threadIdx.x;
-    const int G = gridDim.x;
     for (int i = tid; i < D * NCH; i += blockDim.x) fin[i] = 0;
     if (tid < D) { fl[tid] = 0u; rng[2 * tid] = NCH; rng[2 * tid + 1] = -1; }
     __syncthreads();
     for (int j = tid; j < G * D; j += blockDim.x) {
         RecHdr h = site.hdr[j];
-        int d = j % D;
+        hlo[j] = (short)h.lo;
+        hhi[j] = (short)h.hi;
+        const int d = j % D;
         if (h.flags) atomicOr(&fl[d], h.flags);
         if (h.lo <= h.hi) {
             atomicMin(&rng[2 * d], h.lo);
@@ -363,20 +352,32 @@ __device__ void last_block_reduce(const Site& site, long long* fin, uint32_t* fl
         const int LO = rng[2 * d], HI = rng[2 * d + 1];
         if (LO > HI) continue;
         const int W = HI - LO + 1;
-        const long long items = (long long)G * W;
-        for (long long j = tid; j < items; j += blockDim.x) {
-            int g = (int)(j / W);
-            int c = LO + (int)(j % W);
-            RecHdr h = site.hdr[(size_t)g * D + d];
-            if (c >= h.lo && c <= h.hi) {
-                long long v = site.dig[((size_t)g * D + d) * NCH + c];
-                atomicAdd((unsigned long long*)&fin[d * NCH + c], (unsigned long long)v);
+        const int items = G * W;
+        constexpr int U = 4;
+        for (int j0 = tid; j0 < items; j0 += U * blockDim.x) {
+            long long v[U];
+            int cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * blockDim.x;
+                v[u] = 0;
+                cc[u] = -1;
+                if (j < items) {
+                    const int gg = j / W, c = LO + j % W;
+                    const int hj = gg * D + d;
+                    if (c >= hlo[hj] && c <= hhi[hj]) {
+                        v[u] = site.dig[(size_t)hj * NCH + c];
+                        cc[u] = c;
+                    }
+                }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (cc[u] >= 0 && v[u] != 0) atomicAdd((unsigned long long*)&fin[d * NCH + cc[u]], (unsigned long long)v[u]);
         }
     }
     __syncthreads();
-    if (tid < D) out[tid] = round_chunks(fin + tid * NCH, fl[tid]);
-    if (tid == 0) *site.counter = 0u;
+    if (tid < D) out[tid] = round_chunks(fin + tid * NCH, fl[tid], rng[2 * tid], rng[2 * tid + 1]);
     __syncthreads();
 }
 
