@@ -81,35 +81,38 @@ constexpr int SEQ_CAP = 2048;   // LDS staging entries per chunk of the row-sequ
 
 // kind: PBCG_SPMV_SEQ (rows summed left to right), PBCG_SPMV_VECTOR (L lanes per row
 // from the mean row length, tree order), PBCG_SPMV_WAVE (one wavefront per row).
-template <class VT, class XT, class AT, class Epi>
+template <class VT, class XT, class AT, class Epi, class Fin = NoFin>
 void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hipStream_t s,
-                   int kind = PBCG_SPMV_SEQ) {
+                   int kind = PBCG_SPMV_SEQ, Fin fin = Fin{}) {
     const int n = A->n;
-    if (n == 0) return;
     const VT* val = (const VT*)A->val;
     if (kind == PBCG_SPMV_SEQ) {
-        const int grid = (n + BLOCK - 1) / BLOCK;
-        spmv_seq_kernel<SEQ_CAP, VT, XT, AT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
-                                                                          halt);
+        const int grid = (n + BLOCK - 1) / BLOCK + (Fin::D > 0 ? 1 : 0);
+        if (grid > 0)
+            spmv_seq_kernel<SEQ_CAP, VT, XT, AT, Epi, Fin><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
+                                                                                   epi, fin, halt);
         return;
     }
-    const int L = kind == PBCG_SPMV_WAVE ? 64 : std::min(spmv_lanes(A->n, A->nnz), 32);
-    const int rows = BLOCK / L;
-    const int grid = (n + rows - 1) / rows;
+    if (n > 0) {
+        const int L = kind == PBCG_SPMV_WAVE ? 64 : std::min(spmv_lanes(A->n, A->nnz), 32);
+        const int rows = BLOCK / L;
+        const int grid = (n + rows - 1) / rows;
 #define SPMV_CASE(LL) \
     case LL: spmv_kernel<LL, VT, XT, AT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, halt); break;
-    switch (L) {
-        SPMV_CASE(2) SPMV_CASE(4) SPMV_CASE(8) SPMV_CASE(16) SPMV_CASE(32) SPMV_CASE(64)
-    }
+        switch (L) {
+            SPMV_CASE(2) SPMV_CASE(4) SPMV_CASE(8) SPMV_CASE(16) SPMV_CASE(32) SPMV_CASE(64)
+        }
 #undef SPMV_CASE
+    }
+    if constexpr (Fin::D > 0) fin_kernel<Fin><<<1, BLOCK, 0, s>>>(fin);
 }
 
 // FP64 accumulation, values FP64 or FP32, x FP64
-template <class Epi>
+template <class Epi, class Fin = NoFin>
 void launch_spmv64(const pbcg_csr* A, const double* x, Epi epi, const int* halt, hipStream_t s,
-                   int kind = PBCG_SPMV_SEQ) {
-    if (A->val_type == PBCG_F64) launch_spmv_t<double, double, double>(A, x, epi, halt, s, kind);
-    else launch_spmv_t<float, double, double>(A, x, epi, halt, s, kind);
+                   int kind = PBCG_SPMV_SEQ, Fin fin = Fin{}) {
+    if (A->val_type == PBCG_F64) launch_spmv_t<double, double, double>(A, x, epi, halt, s, kind, fin);
+    else launch_spmv_t<float, double, double>(A, x, epi, halt, s, kind, fin);
 }
 
 template <int D, class VT, class Epi>
@@ -121,7 +124,7 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
         int grid = std::max(1, std::min(DOT_GRID_DEFAULT, (n + BLOCK - 1) / BLOCK));
         spmv_seq_dot_kernel<SEQ_CAP, D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
                                                                                epi, site, halt);
-        dot_finalize_kernel<D, Epi><<<1, 1024, 0, s>>>(epi, grid, site, halt);
+        fin_kernel<XFin<D, Epi>><<<1, BLOCK, 0, s>>>(XFin<D, Epi>{epi, site, grid, halt});
         return;
     }
     const int L = kind == PBCG_SPMV_WAVE ? 64 : std::min(spmv_lanes(A->n, A->nnz), 32);
@@ -133,7 +136,7 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
         SD_CASE(2) SD_CASE(4) SD_CASE(8) SD_CASE(16) SD_CASE(32) SD_CASE(64)
     }
 #undef SD_CASE
-    dot_finalize_kernel<D, Epi><<<1, 1024, 0, s>>>(epi, grid, site, halt);
+    fin_kernel<XFin<D, Epi>><<<1, BLOCK, 0, s>>>(XFin<D, Epi>{epi, site, grid, halt});
 }
 
 template <int D, class Epi>
@@ -143,25 +146,41 @@ void launch_spmv_dot(const pbcg_csr* A, const double* x, Epi epi, xd::Site site,
     else launch_spmv_dot_t<D, float>(A, x, epi, site, halt, s, kind);
 }
 
+// Producer only: returns the finalize role, to be run by fin_kernel or by block 0 of
+// the next SpMV.
+template <int D, class Op>
+XFin<D, Op> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
+                                   int grid = 0, int block = BLOCK, int K = KEXP, int* seen = nullptr) {
+    if (grid <= 0) grid = dot_grid(n);
+#define EW_CASE(KK) \
+    case KK: ew_dot_kernel<D, KK, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen); break;
+    switch (K) {
+        EW_CASE(2) EW_CASE(3) EW_CASE(4) EW_CASE(6) EW_CASE(8)
+        default: ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen);
+    }
+#undef EW_CASE
+    return XFin<D, Op>{op, site, grid, halt};
+}
+
 template <int D, class Op>
 void launch_ew_dot(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
                    int grid = 0, int block = BLOCK, int K = KEXP) {
-    if (grid <= 0) grid = dot_grid(n);
-#define EW_CASE(KK) \
-    case KK: ew_dot_kernel<D, KK, Op><<<grid, block, 0, s>>>(op, n, site, halt); break;
-    switch (K) {
-        EW_CASE(2) EW_CASE(3) EW_CASE(4) EW_CASE(6) EW_CASE(8)
-        default: ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt);
-    }
-#undef EW_CASE
-    dot_finalize_kernel<D, Op><<<1, 1024, 0, s>>>(op, grid, site, halt);
+    XFin<D, Op> f = launch_ew_dot_deferred<D>(op, n, site, halt, s, grid, block, K);
+    fin_kernel<XFin<D, Op>><<<1, BLOCK, 0, s>>>(f);
+}
+
+template <int D, class Op>
+FFin<D, Op> launch_ew_fdot_deferred(Op op, int64_t n, FSite site, const int* halt, hipStream_t s,
+                                    int* seen = nullptr) {
+    int grid = dot_grid(n);
+    ew_fdot_kernel<D, Op><<<grid, BLOCK, 0, s>>>(op, n, site, halt, seen);
+    return FFin<D, Op>{op, site, grid, halt};
 }
 
 template <int D, class Op>
 void launch_ew_fdot(Op op, int64_t n, FSite site, const int* halt, hipStream_t s) {
-    int grid = dot_grid(n);
-    ew_fdot_kernel<D, Op><<<grid, BLOCK, 0, s>>>(op, n, site, halt);
-    fdot_finalize_kernel<D, Op><<<1, 256, 0, s>>>(op, grid, site, halt);
+    FFin<D, Op> f = launch_ew_fdot_deferred<D>(op, n, site, halt, s);
+    fin_kernel<FFin<D, Op>><<<1, BLOCK, 0, s>>>(f);
 }
 
 template <class F>
@@ -248,7 +267,7 @@ struct FnInitFState {
 };
 struct FnResume {          // clear halt flags (host decided to continue)
     State* st;
-    __device__ void operator()() const { st->halt = 0; st->reason = 0; }
+    __device__ void operator()() const { st->halt = 0; st->reason = 0; st->halt_seen = 0; }
 };
 struct FnSqrtLastDot {     // last_dot = sqrt(last_dot)
     State* st;
@@ -464,17 +483,19 @@ struct Driver {
     Work W;
     hipStream_t s;
     int* halt;
+    int* seen;             // &st->halt_seen: checked by the SpMVs of the iteration loop
     int batch;
     int kind;              // SpMV kernel shape
     pbcg_csr A32;          // FP32 copy of A (refinement)
 
-    // out = A in, or A (M in)
-    void op(const double* in, double* out) {
+    // out = A in, or A (M in); `fin` (a pending dot-site finalize) rides on the first SpMV
+    template <class Fin = NoFin>
+    void op(const double* in, double* out, Fin fin = Fin{}, const int* skip = nullptr) {
         if (M) {
-            launch_spmv64(M, in, EpiStore<double>{W.tmp2}, halt, s, kind);
-            launch_spmv64(A, W.tmp2, EpiStore<double>{out}, halt, s, kind);
+            launch_spmv64(M, in, EpiStore<double>{W.tmp2}, skip, s, kind, fin);
+            launch_spmv64(A, W.tmp2, EpiStore<double>{out}, skip, s, kind);
         } else {
-            launch_spmv64(A, in, EpiStore<double>{out}, halt, s, kind);
+            launch_spmv64(A, in, EpiStore<double>{out}, skip, s, kind, fin);
         }
     }
 
@@ -533,11 +554,11 @@ struct Driver {
         const double* scal = &W.st->alpha;
         PhaseA<FinOmega> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
                             FinOmega{W.st, 1}};
-        launch_ew_dot<4>(pa, n, W.site, halt, s);
-        op(W.z, W.v);
+        auto fa = launch_ew_dot_deferred<4>(pa, n, W.site, halt, s, 0, BLOCK, KEXP, seen);
+        op(W.z, W.v, fa, seen);           // v = A z; omega is finalized by its block 0
         PhaseB<FinPhaseB> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
-        launch_ew_dot<3>(pb, n, W.site, halt, s);
-        op(W.w, W.t);
+        auto fb = launch_ew_dot_deferred<3>(pb, n, W.site, halt, s, 0, BLOCK, KEXP, seen);
+        op(W.w, W.t, fb, seen);           // t = A w; beta, alpha finalized by its block 0
     }
 
     void enqueue_iteration_b() {
@@ -571,8 +592,8 @@ struct Driver {
             launch_spmv64(A, x, EpiResid<double>{b, W.r, W.rhat, bicg ? W.p : nullptr}, nullptr, s, kind);
         }
         if (!bicg) {
-            op(W.r, W.w);
-            op(W.w, W.t);
+            op(W.r, W.w, NoFin{}, halt);
+            op(W.w, W.t, NoFin{}, halt);
             DotsOp<3, FinInitP> d3{};
             d3.a[0] = W.rhat; d3.b[0] = W.r;
             d3.a[1] = W.rhat; d3.b[1] = W.w;
@@ -637,6 +658,7 @@ struct Driver {
         const int n = A->n;
         FState* fs = W.fst;
         int* fh = &fs->halt;
+        int* fseen = &fs->halt_seen;
         const float* scal = &fs->alpha;
         launch_single(FnInitFState{fs, (float)o->inner_tol, std::max(o->max_iter, 1)}, s);
         launch_ew(FnZeroF{W.d32}, n, nullptr, s);
@@ -666,12 +688,12 @@ struct Driver {
             for (int k = 0; k < batch; ++k) {
                 FPhaseA<FFinOmega> pa{W.r32, W.w32, W.t32, W.v32, W.rh32, W.p32, W.s32, W.z32, W.q32, W.y32,
                                       scal, first ? 1 : 0, FFinOmega{fs}};
-                launch_ew_fdot<4>(pa, n, W.fsite, fh, s);
-                launch_spmv_t<float, float, float>(&A32, W.z32, EpiStore<float>{W.v32}, fh, s, kind);
+                auto fa = launch_ew_fdot_deferred<4>(pa, n, W.fsite, fh, s, fseen);
+                launch_spmv_t<float, float, float>(&A32, W.z32, EpiStore<float>{W.v32}, fseen, s, kind, fa);
                 FPhaseB<FFinPhaseB> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
                                        FFinPhaseB{fs}};
-                launch_ew_fdot<3>(pb, n, W.fsite, fh, s);
-                launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, fh, s, kind);
+                auto fb = launch_ew_fdot_deferred<3>(pb, n, W.fsite, fh, s, fseen);
+                launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, fseen, s, kind, fb);
                 first = false;
             }
             HIPCHK(hipGetLastError());
@@ -779,6 +801,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     Driver D{};
     D.A = A; D.M = opts->M; D.b = b; D.x = x; D.o = opts; D.W = W; D.s = (hipStream_t)stream;
     D.halt = &W.st->halt;
+    D.seen = &W.st->halt_seen;
     D.batch = opts->batch > 0 ? opts->batch : 16;
     D.kind = opts->spmv_kind;
     State h{};

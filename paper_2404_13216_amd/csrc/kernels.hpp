@@ -37,6 +37,87 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return xcd * base + min(xcd, rem) + idx;
 }
 
+// per-block FP32 partials of a plain-dot site
+struct FSite {
+    float* part;            // [grid][D]
+};
+
+// Fixed-order tree over the G per-block partials (blockDim.x == 256).
+template <int D>
+__device__ void fdot_reduce(const FSite& site, int G, float* sh /* D*256 */, float* res /* D */) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        float s = 0.0f;
+        for (int g = t; g < G; g += 256) s = s + site.part[(size_t)g * D + d];
+        sh[d * 256 + t] = s;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) sh[d * 256 + t] = sh[d * 256 + t] + sh[d * 256 + t + w];
+        }
+        __syncthreads();
+    }
+    if (t < D) res[t] = sh[t * 256];
+    __syncthreads();
+}
+
+// "Finalize roles": the cross-block reduction of a dot site plus the scalar work that
+// follows it, run by one 256-thread block -- either a block of its own kernel, or block 0
+// of the next kernel in the stream when that kernel does not consume the results (the
+// SpMV after each p-BiCGStab phase), which hides its latency behind the SpMV.
+constexpr int DOT_GMAX = 1024;
+constexpr int FIN_SMEM = 32 + 4 * xd::NCH * 8 + 16 + 32 + 2 * DOT_GMAX * 4 * 2;
+
+struct NoFin {
+    static constexpr int D = 0;
+    __device__ void run(unsigned char*) {}
+};
+
+template <int D_, class Op>
+struct XFin {                       // exact dots
+    static constexpr int D = D_;
+    Op op;
+    xd::Site site;
+    int G;
+    const int* halt;
+    __device__ void run(unsigned char* smem) {
+        if (halt && *halt) return;
+        double* res = (double*)smem;                              // 4 doubles
+        long long* fin = (long long*)(smem + 32);                 // D*NCH
+        uint32_t* fl = (uint32_t*)(smem + 32 + 4 * xd::NCH * 8);  // 4
+        int* rng = (int*)(fl + 4);                                // 8
+        short* hlo = (short*)(rng + 8);                           // DOT_GMAX*4
+        short* hhi = hlo + DOT_GMAX * 4;
+        xd::reduce_records<D, DOT_GMAX>(site, G, fin, hlo, hhi, fl, rng, res);
+        if (threadIdx.x == 0) op.finalize(res);
+    }
+};
+
+template <int D_, class Op>
+struct FFin {                       // plain FP32 dots
+    static constexpr int D = D_;
+    Op op;
+    FSite site;
+    int G;
+    const int* halt;
+    __device__ void run(unsigned char* smem) {
+        if (halt && *halt) return;
+        float* res = (float*)smem;
+        float* sh = res + 4;
+        fdot_reduce<D>(site, G, sh, res);
+        if (threadIdx.x == 0) op.finalize(res);
+    }
+};
+
+template <class Fin>
+__global__ void __launch_bounds__(256) fin_kernel(Fin fin) {
+    __shared__ __align__(16) unsigned char smem[FIN_SMEM];
+    fin.run(smem);
+}
+
 // ----------------------------------------------------------------------------- SpMV
 template <class T>
 struct EpiStore {
@@ -110,15 +191,27 @@ __device__ __forceinline__ AT seq_rows(int r0, int r1, const int32_t* __restrict
     return s;
 }
 
-template <int CAP, class VT, class XT, class AT, class Epi>
+template <int CAP, class VT, class XT, class AT, class Epi, class Fin>
 __global__ void __launch_bounds__(256)
 spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, const int* halt) {
+                const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt) {
     if (halt && *halt) return;
-    __shared__ VT sval[CAP];
-    __shared__ int32_t scol[CAP];
+    constexpr int STAGE = CAP * (int)(sizeof(VT) + sizeof(int32_t));
+    constexpr int SMEM = (Fin::D > 0 && FIN_SMEM > STAGE) ? FIN_SMEM : STAGE;
+    __shared__ __align__(16) unsigned char smem[SMEM];
+    int b = blockIdx.x, G = gridDim.x;
+    if constexpr (Fin::D > 0) {
+        if (b == 0) {      // finalize role of the previous kernel's dot site
+            fin.run(smem);
+            return;
+        }
+        b -= 1;
+        G -= 1;
+    }
+    VT* sval = (VT*)smem;
+    int32_t* scol = (int32_t*)(smem + CAP * sizeof(VT));
     const int R = blockDim.x;
-    const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;
+    const int r0 = xcd_remap(b, G) * R;
     if (r0 >= n) return;  // uniform over the block
     const int r1 = min(r0 + R, n);
     AT s = seq_rows<CAP, VT, XT, AT>(r0, r1, rp, ci, val, x, sval, scol);
@@ -135,12 +228,16 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
 
 // Exact element-wise fused kernel.  Op provides:
 //   load()                      read device scalars
-//   elem(i, xa[D], ya[D])       updates for element i; dot operands
-//   finalize(const double* d)   run by dot_finalize_kernel once the records are summed
+//   ld(i, in[NIN])              global loads of element i
+//   st(i, in, xa[D], ya[D])     updates and stores of element i; dot operands
+//   finalize(const double* d)   run by a finalize role (XFin) once the records are summed
 template <int D, int K, class Op>
 __global__ void __launch_bounds__(1024)
-ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt) {
-    if (halt && *halt) return;
+ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt, int* seen) {
+    if (halt && *halt) {
+        if (seen && blockIdx.x == 0 && threadIdx.x == 0) *seen = 1;
+        return;
+    }
     XD_SHARED(D)
     xd::block_init<D>(sh_acc, sh_flags);
     op.load();
@@ -149,10 +246,29 @@ ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt) {
     for (int d = 0; d < D; ++d)
 #pragma unroll
         for (int k = 0; k < K; ++k) e[d][k] = 0.0;
+    // grid-stride loop, two elements per trip: both elements' loads are issued before
+    // the dependent exact-accumulation work of the first
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + stride < n; i += 2 * stride) {
+        double ia[Op::NIN], ib[Op::NIN];
+        op.ld(i, ia);
+        op.ld(i + stride, ib);
         double xa[D], ya[D];
-        op.elem(i, xa, ya);
+        op.st(i, ia, xa, ya);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+        op.st(i + stride, ib, xa, ya);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+    }
+    if (i < n) {
+        double ia[Op::NIN];
+        op.ld(i, ia);
+        double xa[D], ya[D];
+        op.st(i, ia, xa, ya);
 #pragma unroll
         for (int d = 0; d < D; ++d)
             xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
@@ -238,17 +354,17 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 }
 
 // ----------------------------------------------------------------------------- FP32 plain dots
-struct FSite {
-    float* part;            // [grid][D]
-};
 
 // Plain FP32 dots: per-thread sequential sums in grid-stride order, xor-butterfly
 // within the wave, waves in index order; the per-block partials are summed in a fixed
-// tree by fdot_finalize_kernel (deterministic for a given launch shape).
+// tree by a finalize role (FFin; deterministic for a given launch shape).
 template <int D, class Op>
 __global__ void __launch_bounds__(256)
-ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt) {
-    if (halt && *halt) return;
+ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt, int* seen) {
+    if (halt && *halt) {
+        if (seen && blockIdx.x == 0 && threadIdx.x == 0) *seen = 1;
+        return;
+    }
     __shared__ float sh_w[D][16];
     op.load();
     float a[D];
@@ -280,49 +396,6 @@ ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt) {
     }
 }
 
-// One block: the D results are the block partials summed in a fixed tree order.
-template <int D, class Op>
-__global__ void __launch_bounds__(256)
-fdot_finalize_kernel(Op op, int G, FSite site, const int* halt) {
-    if (halt && *halt) return;
-    __shared__ float sh[D][256];
-    __shared__ float sh_res[D];
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        float s = 0.0f;
-        for (int g = t; g < G; g += 256) s = s + site.part[(size_t)g * D + d];
-        sh[d][t] = s;
-    }
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) sh[d][t] = sh[d][t] + sh[d][t + w];
-        }
-        __syncthreads();
-    }
-    if (t < D) sh_res[t] = sh[t][0];
-    __syncthreads();
-    if (t == 0) op.finalize(sh_res);
-}
-
-// One block: sum the per-block exact records of a dot site and round (G <= GMAX).
-constexpr int DOT_GMAX = 1024;
-template <int D, class Op>
-__global__ void __launch_bounds__(1024)
-dot_finalize_kernel(Op op, int G, xd::Site site, const int* halt) {
-    if (halt && *halt) return;
-    __shared__ long long sh_fin[D * xd::NCH];
-    __shared__ short sh_lo[DOT_GMAX * D];
-    __shared__ short sh_hi[DOT_GMAX * D];
-    __shared__ uint32_t sh_fl[D];
-    __shared__ int sh_rng[2 * D];
-    __shared__ double sh_res[D];
-    xd::reduce_records<D, DOT_GMAX>(site, G, sh_fin, sh_lo, sh_hi, sh_fl, sh_rng, sh_res);
-    if (threadIdx.x == 0) op.finalize(sh_res);
-}
-
 // ----------------------------------------------------------------------------- small kernels
 template <class F>
 __global__ void __launch_bounds__(256) ew_kernel(F f, int64_t n, const int* halt) {
@@ -346,22 +419,26 @@ struct PhaseA {
     int first;
     Fin fin;
     double alpha, beta, omega;
+    static constexpr int NIN = 8;
     __device__ __forceinline__ void load() { alpha = scal[0]; beta = scal[1]; omega = scal[2]; }
-    __device__ __forceinline__ void elem(int64_t i, double (&xa)[4], double (&ya)[4]) {
-        const double ri = r[i], wi = w[i], ti = t[i];
+    __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
+        in[0] = r[i]; in[1] = w[i]; in[2] = t[i]; in[3] = rhat[i];
+        if (!first) { in[4] = p[i]; in[5] = s[i]; in[6] = z[i]; in[7] = v[i]; }
+    }
+    __device__ __forceinline__ void st(int64_t i, const double (&in)[NIN], double (&xa)[4], double (&ya)[4]) {
+        const double ri = in[0], wi = in[1], ti = in[2];
         double pi, si, zi;
         if (first) {
             pi = ri; si = wi; zi = ti;
         } else {
-            const double pp = p[i], sp = s[i], zp = z[i], vp = v[i];
-            pi = ri + beta * (pp - omega * sp);
-            si = wi + beta * (sp - omega * zp);
-            zi = ti + beta * (zp - omega * vp);
+            pi = ri + beta * (in[4] - omega * in[5]);
+            si = wi + beta * (in[5] - omega * in[6]);
+            zi = ti + beta * (in[6] - omega * in[7]);
         }
         const double qi = ri - alpha * si;
         const double yi = wi - alpha * zi;
         p[i] = pi; s[i] = si; z[i] = zi; q[i] = qi; y[i] = yi;
-        const double rh = rhat[i];
+        const double rh = in[3];
         xa[0] = qi; ya[0] = yi;
         xa[1] = yi; ya[1] = yi;
         xa[2] = rh; ya[2] = si;
@@ -378,14 +455,18 @@ struct PhaseB {
     const double* scal;
     Fin fin;
     double alpha, omega;
+    static constexpr int NIN = 7;
     __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
-    __device__ __forceinline__ void elem(int64_t i, double (&xa)[3], double (&ya)[3]) {
-        const double qi = q[i], yi = y[i];
-        const double xi = (x[i] + alpha * p[i]) + omega * qi;
+    __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
+        in[0] = x[i]; in[1] = p[i]; in[2] = q[i]; in[3] = y[i]; in[4] = t[i]; in[5] = v[i]; in[6] = rhat[i];
+    }
+    __device__ __forceinline__ void st(int64_t i, const double (&in)[NIN], double (&xa)[3], double (&ya)[3]) {
+        const double qi = in[2], yi = in[3];
+        const double xi = (in[0] + alpha * in[1]) + omega * qi;
         const double ri = qi - omega * yi;
-        const double wi = yi - omega * (t[i] - alpha * v[i]);
+        const double wi = yi - omega * (in[4] - alpha * in[5]);
         x[i] = xi; r[i] = ri; w[i] = wi;
-        const double rh = rhat[i];
+        const double rh = in[6];
         xa[0] = rh; ya[0] = ri;
         xa[1] = rh; ya[1] = wi;
         xa[2] = ri; ya[2] = ri;
@@ -399,10 +480,15 @@ struct DotsOp {
     const double* a[4];
     const double* b[4];
     Fin fin;
+    static constexpr int NIN = 2 * D;
     __device__ __forceinline__ void load() {}
-    __device__ __forceinline__ void elem(int64_t i, double (&xa)[D], double (&ya)[D]) {
+    __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
 #pragma unroll
-        for (int d = 0; d < D; ++d) { xa[d] = a[d][i]; ya[d] = b[d][i]; }
+        for (int d = 0; d < D; ++d) { in[2 * d] = a[d][i]; in[2 * d + 1] = b[d][i]; }
+    }
+    __device__ __forceinline__ void st(int64_t, const double (&in)[NIN], double (&xa)[D], double (&ya)[D]) const {
+#pragma unroll
+        for (int d = 0; d < D; ++d) { xa[d] = in[2 * d]; ya[d] = in[2 * d + 1]; }
     }
     __device__ __forceinline__ void finalize(const double* d) { fin(d); }
 };
@@ -606,13 +692,17 @@ struct OpBiCGStabXR {
     double* x; const double* p; const double* q; const double* y; const double* rhat; double* r;
     const double* scal; FinBiCGStabXR fin;
     double alpha, omega;
+    static constexpr int NIN = 5;
     __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
-    __device__ __forceinline__ void elem(int64_t i, double (&xa)[2], double (&ya)[2]) {
-        const double qi = q[i];
-        const double xi = (x[i] + alpha * p[i]) + omega * qi;
-        const double ri = qi - omega * y[i];
+    __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
+        in[0] = x[i]; in[1] = p[i]; in[2] = q[i]; in[3] = y[i]; in[4] = rhat[i];
+    }
+    __device__ __forceinline__ void st(int64_t i, const double (&in)[NIN], double (&xa)[2], double (&ya)[2]) {
+        const double qi = in[2];
+        const double xi = (in[0] + alpha * in[1]) + omega * qi;
+        const double ri = qi - omega * in[3];
         x[i] = xi; r[i] = ri;
-        xa[0] = rhat[i]; ya[0] = ri;
+        xa[0] = in[4]; ya[0] = ri;
         xa[1] = ri; ya[1] = ri;
     }
     __device__ __forceinline__ void finalize(const double* d) { fin(d); }

@@ -17,13 +17,19 @@ enum : int {
 
 // FP64 solver scalars.  alpha, beta, omega are consecutive: kernels read them
 // through a `const double* scal` = &alpha.
+//
+// Halting: finalize roles set `halt`; phase kernels skip when `halt` is set and then
+// raise `halt_seen`; SpMV kernels of the iteration loop skip only on `halt_seen`.  An
+// SpMV whose block 0 carries a finalize that halts therefore still completes all of its
+// rows (a resumed solve needs its output), and SpMVs queued after a halt recompute
+// nothing new (their inputs are frozen) or are skipped.
 struct State {
     double alpha, beta, omega, rho;
     double rs, rz, qy, yy;
     double normb, rec, true_rel, tol;
     double rw, rr, last_dot, pad0;
     int32_t iter, max_iter, halt, reason;
-    int32_t hist_len, true_checks, pad1, pad2;
+    int32_t hist_len, true_checks, halt_seen, pad2;
     double* hist;
     double* pad3;
 };
@@ -34,6 +40,7 @@ struct FState {
     float rs, rz, normb, rec;
     float tol, pad0, pad1, pad2;
     int32_t iter, max_iter, halt, reason;
+    int32_t halt_seen, fpad0, fpad1, fpad2;
 };
 
 }  // namespace pbcg

@@ -348,33 +348,41 @@ __device__ void reduce_records(const Site& site, int G, long long* fin, short* h
         }
     }
     __syncthreads();
-    for (int d = 0; d < D; ++d) {
-        const int LO = rng[2 * d], HI = rng[2 * d + 1];
-        if (LO > HI) continue;
-        const int W = HI - LO + 1;
-        const int items = G * W;
-        constexpr int U = 4;
-        for (int j0 = tid; j0 < items; j0 += U * blockDim.x) {
-            long long v[U];
-            int cc[U];
+    // all dots in one pass: item j -> (dot d, record g, chunk c) over the union of windows
+    int off[D + 1], LOd[D], Wd[D];
+    off[0] = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * blockDim.x;
-                v[u] = 0;
-                cc[u] = -1;
-                if (j < items) {
-                    const int gg = j / W, c = LO + j % W;
-                    const int hj = gg * D + d;
-                    if (c >= hlo[hj] && c <= hhi[hj]) {
-                        v[u] = site.dig[(size_t)hj * NCH + c];
-                        cc[u] = c;
-                    }
+    for (int d = 0; d < D; ++d) {
+        LOd[d] = rng[2 * d];
+        Wd[d] = rng[2 * d + 1] >= rng[2 * d] ? rng[2 * d + 1] - rng[2 * d] + 1 : 0;
+        off[d + 1] = off[d] + G * Wd[d];
+    }
+    const int items = off[D];
+    constexpr int U = 8;
+    for (int j0 = tid; j0 < items; j0 += U * blockDim.x) {
+        long long v[U];
+        int slot[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * blockDim.x;
+            v[u] = 0;
+            slot[u] = -1;
+            if (j < items) {
+                int d = 0;
+#pragma unroll
+                for (int e = 1; e < D; ++e) d += (j >= off[e]) ? 1 : 0;
+                const int jj = j - off[d];
+                const int gg = jj / Wd[d], c = LOd[d] + jj % Wd[d];
+                const int hj = gg * D + d;
+                if (c >= hlo[hj] && c <= hhi[hj]) {
+                    v[u] = site.dig[(size_t)hj * NCH + c];
+                    slot[u] = d * NCH + c;
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (cc[u] >= 0 && v[u] != 0) atomicAdd((unsigned long long*)&fin[d * NCH + cc[u]], (unsigned long long)v[u]);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (slot[u] >= 0 && v[u] != 0) atomicAdd((unsigned long long*)&fin[slot[u]], (unsigned long long)v[u]);
     }
     __syncthreads();
     if (tid < D) out[tid] = round_chunks(fin + tid * NCH, fl[tid], rng[2 * tid], rng[2 * tid + 1]);
