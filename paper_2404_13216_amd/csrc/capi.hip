@@ -16,9 +16,10 @@ using namespace pbcg;
 namespace {
 
 constexpr int BLOCK = 256;
+constexpr int DOT_BLOCK = 512;       // fused element-wise kernels with exact dots
 constexpr int DOT_GRID_MAX = 1024;   // records available in a dot site
-constexpr int DOT_GRID_DEFAULT = 512;
-constexpr int KEXP = 4;              // expansion terms per lane in the solver kernels
+constexpr int DOT_GRID_DEFAULT = 256;
+constexpr int KEXP = 3;              // expansion terms per lane in the solver kernels
 
 #define HIPCHK(expr)                              \
     do {                                          \
@@ -57,8 +58,9 @@ xd::Site carve_site(Carver& c, int grid_max) {
     return s;
 }
 
+// blocks of DOT_BLOCK threads, >= 8 elements per lane, at most one block per CU
 int dot_grid(int64_t n) {
-    int64_t g = (n + (int64_t)BLOCK * 8 - 1) / ((int64_t)BLOCK * 8);
+    int64_t g = (n + (int64_t)DOT_BLOCK * 8 - 1) / ((int64_t)DOT_BLOCK * 8);
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, DOT_GRID_DEFAULT));
 }
 
@@ -77,7 +79,7 @@ bool csr_ok(const pbcg_csr* A) {
 }
 
 // ---------------------------------------------------------------- launchers
-constexpr int SEQ_CAP = 2048;   // LDS staging entries per chunk of the row-sequential SpMV
+constexpr int SEQ_WORKERS = 6 * 256;   // persistent SpMV blocks: 6 resident per CU (24 KB LDS each)
 
 // kind: PBCG_SPMV_SEQ (rows summed left to right), PBCG_SPMV_VECTOR (L lanes per row
 // from the mean row length, tree order), PBCG_SPMV_WAVE (one wavefront per row).
@@ -87,10 +89,11 @@ void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hip
     const int n = A->n;
     const VT* val = (const VT*)A->val;
     if (kind == PBCG_SPMV_SEQ) {
-        const int grid = (n + BLOCK - 1) / BLOCK + (Fin::D > 0 ? 1 : 0);
+        const int workers = std::min((n + BLOCK - 1) / BLOCK, SEQ_WORKERS);
+        const int grid = workers + (Fin::D > 0 ? 1 : 0);
         if (grid > 0)
-            spmv_seq_kernel<SEQ_CAP, VT, XT, AT, Epi, Fin><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
-                                                                                   epi, fin, halt);
+            spmv_seq_kernel<VT, XT, AT, Epi, Fin><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
+                                                                          fin, halt);
         return;
     }
     if (n > 0) {
@@ -122,8 +125,8 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
     const VT* val = (const VT*)A->val;
     if (kind == PBCG_SPMV_SEQ) {
         int grid = std::max(1, std::min(DOT_GRID_DEFAULT, (n + BLOCK - 1) / BLOCK));
-        spmv_seq_dot_kernel<SEQ_CAP, D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
-                                                                               epi, site, halt);
+        spmv_seq_dot_kernel<D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, site,
+                                                                      halt);
         fin_kernel<XFin<D, Epi>><<<1, BLOCK, 0, s>>>(XFin<D, Epi>{epi, site, grid, halt});
         return;
     }
@@ -150,21 +153,25 @@ void launch_spmv_dot(const pbcg_csr* A, const double* x, Epi epi, xd::Site site,
 // the next SpMV.
 template <int D, class Op>
 XFin<D, Op> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
-                                   int grid = 0, int block = BLOCK, int K = KEXP, int* seen = nullptr) {
+                                   int grid = 0, int block = DOT_BLOCK, int K = KEXP, int* seen = nullptr) {
     if (grid <= 0) grid = dot_grid(n);
+    if constexpr (D == 1) {  // the standalone dot exposes the expansion length
 #define EW_CASE(KK) \
     case KK: ew_dot_kernel<D, KK, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen); break;
-    switch (K) {
-        EW_CASE(2) EW_CASE(3) EW_CASE(4) EW_CASE(6) EW_CASE(8)
-        default: ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen);
-    }
+        switch (K) {
+            EW_CASE(2) EW_CASE(3) EW_CASE(4) EW_CASE(6) EW_CASE(8)
+            default: ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen);
+        }
 #undef EW_CASE
+    } else {
+        ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen);
+    }
     return XFin<D, Op>{op, site, grid, halt};
 }
 
 template <int D, class Op>
 void launch_ew_dot(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
-                   int grid = 0, int block = BLOCK, int K = KEXP) {
+                   int grid = 0, int block = DOT_BLOCK, int K = KEXP) {
     XFin<D, Op> f = launch_ew_dot_deferred<D>(op, n, site, halt, s, grid, block, K);
     fin_kernel<XFin<D, Op>><<<1, BLOCK, 0, s>>>(f);
 }
@@ -173,7 +180,7 @@ template <int D, class Op>
 FFin<D, Op> launch_ew_fdot_deferred(Op op, int64_t n, FSite site, const int* halt, hipStream_t s,
                                     int* seen = nullptr) {
     int grid = dot_grid(n);
-    ew_fdot_kernel<D, Op><<<grid, BLOCK, 0, s>>>(op, n, site, halt, seen);
+    ew_fdot_kernel<D, Op><<<grid, DOT_BLOCK, 0, s>>>(op, n, site, halt, seen);
     return FFin<D, Op>{op, site, grid, halt};
 }
 
@@ -386,7 +393,7 @@ int exdot_config(int64_t n, const double* x, const double* y, double* out, int32
 }
 
 int exdot(int64_t n, const double* x, const double* y, double* out, void* ws, size_t ws_bytes, void* stream) {
-    return exdot_config(n, x, y, out, dot_grid(n), BLOCK, KEXP, ws, ws_bytes, stream);
+    return exdot_config(n, x, y, out, dot_grid(n), DOT_BLOCK, KEXP, ws, ws_bytes, stream);
 }
 
 size_t pbcg_phase_workspace_bytes(int32_t n) {
@@ -554,10 +561,10 @@ struct Driver {
         const double* scal = &W.st->alpha;
         PhaseA<FinOmega> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
                             FinOmega{W.st, 1}};
-        auto fa = launch_ew_dot_deferred<4>(pa, n, W.site, halt, s, 0, BLOCK, KEXP, seen);
+        auto fa = launch_ew_dot_deferred<4>(pa, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
         op(W.z, W.v, fa, seen);           // v = A z; omega is finalized by its block 0
         PhaseB<FinPhaseB> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
-        auto fb = launch_ew_dot_deferred<3>(pb, n, W.site, halt, s, 0, BLOCK, KEXP, seen);
+        auto fb = launch_ew_dot_deferred<3>(pb, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
         op(W.w, W.t, fb, seen);           // t = A w; beta, alpha finalized by its block 0
     }
 

@@ -161,62 +161,121 @@ spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ c
     if (lane == 0) epi(row, s);
 }
 
-// Row-sequential sums of rows [r0, r1) (one row per thread, thread i -> row r0+i).
-// val/col of the block's nnz range pass through LDS in chunks of CAP entries, loaded
-// with unit-stride (coalesced) reads; each lane then walks its row in storage order.
-// Every thread of the block must call this (it synchronises).
-template <int CAP, class VT, class XT, class AT>
-__device__ __forceinline__ AT seq_rows(int r0, int r1, const int32_t* __restrict__ rp,
-                                       const int32_t* __restrict__ ci, const VT* __restrict__ val,
-                                       const XT* __restrict__ x, VT* sval, int32_t* scol) {
-    const int row = r0 + (int)threadIdx.x;
-    const int a0 = rp[r0], a1 = rp[r1];
-    int a = 0, b = 0;
-    if (row < r1) { a = rp[row]; b = rp[row + 1]; }
-    AT s = AT(0);
-    for (int cs = a0; cs < a1; cs += CAP) {
-        const int ce = min(cs + CAP, a1);
-        for (int k = cs + (int)threadIdx.x; k < ce; k += blockDim.x) {
-            sval[k - cs] = val[k];
-            scol[k - cs] = ci[k];
+// Row-sequential SpMV engine (persistent, software-pipelined).
+//
+// Rows are taken in chunks of R = blockDim.x rows, one row per lane, and every row is
+// summed left to right in storage order.  The chunk's val/col range is loaded with
+// unit-stride (coalesced) reads into registers, parked in LDS, and each lane then walks
+// its row from LDS while gathering x.  The loads of the block's next chunk are issued
+// before the current chunk is summed, so HBM traffic overlaps the gather/sum phase.
+// Chunks are dealt to the worker blocks of each XCD from a contiguous range of rows
+// (hardware block b runs on XCD b % 8), so the x planes a stencil row touches are
+// shared in that XCD's L2.  A chunk whose nnz exceed the staging capacity falls back
+// to direct reads (same order, same bits).
+template <int PER, class VT, class XT, class AT, class Body>
+__device__ __forceinline__ void seq_pipe(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                         const VT* __restrict__ val, const XT* __restrict__ x,
+                                         int bfirst, int G, VT* sval, int32_t* scol, Body& body) {
+    const int R = blockDim.x;
+    const int CAP = R * PER;
+    const int nchunk = (n + R - 1) / R;
+    const int hb = blockIdx.x;
+    int cbeg, cend, gper, bi;
+    if (G >= NUM_XCD) {
+        const int xcd = hb % NUM_XCD;
+        auto cnt = [&](int m) { return (m + NUM_XCD - 1 - xcd) / NUM_XCD; };  // #h in [0,m), h%8==xcd
+        gper = cnt(bfirst + G) - cnt(bfirst);
+        bi = cnt(hb) - cnt(bfirst);
+        cbeg = (int)((long long)nchunk * xcd / NUM_XCD);
+        cend = (int)((long long)nchunk * (xcd + 1) / NUM_XCD);
+    } else {
+        gper = G;
+        bi = hb - bfirst;
+        cbeg = 0;
+        cend = nchunk;
+    }
+    const int t = threadIdx.x;
+    VT pv[PER];
+    int32_t pc[PER];
+    int a0 = 0, a1 = 0, ra = 0, rb = 0;
+    auto fetch = [&](int cc) {
+        const int r0 = cc * R, r1 = min(r0 + R, n);
+        a0 = rp[r0];
+        a1 = rp[r1];
+        const int row = r0 + t;
+        ra = 0;
+        rb = 0;
+        if (row < r1) { ra = rp[row]; rb = rp[row + 1]; }
+        if (a1 - a0 <= CAP) {
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int k = a0 + t + j * R;
+                if (k < a1) { pv[j] = val[k]; pc[j] = ci[k]; }
+            }
+        }
+    };
+    int c = cbeg + bi;
+    if (c < cend) fetch(c);
+    for (; c < cend; c += gper) {
+        const int r0 = c * R, r1 = min(r0 + R, n), row = r0 + t;
+        const int A0 = a0, A1 = a1, RA = ra, RB = rb;
+        const bool staged = A1 - A0 <= CAP;
+        if (staged) {
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int k = A0 + t + j * R;
+                if (k < A1) { sval[k - A0] = pv[j]; scol[k - A0] = pc[j]; }
+            }
         }
         __syncthreads();
-        const int lo = max(a, cs), hi = min(b, ce);
-        for (int k = lo; k < hi; ++k) {
-            AT prod = (AT)sval[k - cs] * (AT)x[scol[k - cs]];
-            s = s + prod;
+        if (c + gper < cend) fetch(c + gper);  // next chunk in flight during the sums
+        AT s = AT(0);
+        if (staged) {
+            for (int k = RA; k < RB; ++k) {
+                AT prod = (AT)sval[k - A0] * (AT)x[scol[k - A0]];
+                s = s + prod;
+            }
+        } else {
+            for (int k = RA; k < RB; ++k) {
+                AT prod = (AT)val[k] * (AT)x[ci[k]];
+                s = s + prod;
+            }
         }
+        if (row < r1) body(row, s);
         __syncthreads();
     }
-    return s;
 }
 
-template <int CAP, class VT, class XT, class AT, class Epi, class Fin>
+constexpr int SEQ_PER = 8;      // staged entries per lane: 8 x 256 = 2048 per chunk
+
+template <class Epi>
+struct StoreBody {
+    Epi& epi;
+    template <class AT>
+    __device__ __forceinline__ void operator()(int row, AT s) { epi(row, s); }
+};
+
+// grid = worker blocks (+1 when block 0 carries a finalize role)
+template <class VT, class XT, class AT, class Epi, class Fin>
 __global__ void __launch_bounds__(256)
 spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                 const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt) {
     if (halt && *halt) return;
-    constexpr int STAGE = CAP * (int)(sizeof(VT) + sizeof(int32_t));
+    constexpr int STAGE = 256 * SEQ_PER * (int)(sizeof(VT) + sizeof(int32_t));
     constexpr int SMEM = (Fin::D > 0 && FIN_SMEM > STAGE) ? FIN_SMEM : STAGE;
     __shared__ __align__(16) unsigned char smem[SMEM];
-    int b = blockIdx.x, G = gridDim.x;
+    int bfirst = 0;
     if constexpr (Fin::D > 0) {
-        if (b == 0) {      // finalize role of the previous kernel's dot site
+        if (blockIdx.x == 0) {      // finalize role of the previous kernel's dot site
             fin.run(smem);
             return;
         }
-        b -= 1;
-        G -= 1;
+        bfirst = 1;
     }
     VT* sval = (VT*)smem;
-    int32_t* scol = (int32_t*)(smem + CAP * sizeof(VT));
-    const int R = blockDim.x;
-    const int r0 = xcd_remap(b, G) * R;
-    if (r0 >= n) return;  // uniform over the block
-    const int r1 = min(r0 + R, n);
-    AT s = seq_rows<CAP, VT, XT, AT>(r0, r1, rp, ci, val, x, sval, scol);
-    const int row = r0 + (int)threadIdx.x;
-    if (row < r1) epi(row, s);
+    int32_t* scol = (int32_t*)(smem + 256 * SEQ_PER * sizeof(VT));
+    StoreBody<Epi> body{epi};
+    seq_pipe<SEQ_PER, VT, XT, AT>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst, sval, scol, body);
 }
 
 // ----------------------------------------------------------------------------- dot sites
@@ -319,15 +378,28 @@ spmv_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
 }
 
 // Row-sequential SpMV with D exact dots in the epilogue (persistent grid).
-template <int CAP, int D, int K, class VT, class Epi>
+template <int D, int K, class Epi>
+struct DotBody {
+    Epi& epi;
+    double (&e)[D][K];
+    unsigned long long* acc;
+    uint32_t* flags;
+    __device__ __forceinline__ void operator()(int row, double s) {
+        double xa[D], ya[D];
+        epi.row(row, s, xa, ya);
+#pragma unroll
+        for (int d = 0; d < D; ++d) xd::accumulate<K>(e[d], xa[d], ya[d], acc + d * xd::NCH, &flags[d]);
+    }
+};
+
+template <int D, int K, class VT, class Epi>
 __global__ void __launch_bounds__(256)
 spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const VT* __restrict__ val, const double* __restrict__ x, Epi epi,
                     xd::Site site, const int* halt) {
     if (halt && *halt) return;
     XD_SHARED(D)
-    __shared__ VT sval[CAP];
-    __shared__ int32_t scol[CAP];
+    __shared__ __align__(16) unsigned char smem[256 * SEQ_PER * (sizeof(VT) + sizeof(int32_t))];
     xd::block_init<D>(sh_acc, sh_flags);
     epi.load();
     double e[D][K];
@@ -335,20 +407,9 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
     for (int d = 0; d < D; ++d)
 #pragma unroll
         for (int k = 0; k < K; ++k) e[d][k] = 0.0;
-    const int R = blockDim.x;
-    const int nblk = (n + R - 1) / R;
-    for (int bb = blockIdx.x; bb < nblk; bb += gridDim.x) {
-        const int r0 = bb * R, r1 = min(r0 + R, n);
-        double s = seq_rows<CAP, VT, double, double>(r0, r1, rp, ci, val, x, sval, scol);
-        const int row = r0 + (int)threadIdx.x;
-        if (row < r1) {
-            double xa[D], ya[D];
-            epi.row(row, s, xa, ya);
-#pragma unroll
-            for (int d = 0; d < D; ++d)
-                xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
-        }
-    }
+    DotBody<D, K, Epi> body{epi, e, sh_acc, sh_flags};
+    seq_pipe<SEQ_PER, VT, double, double>(n, rp, ci, val, x, 0, (int)gridDim.x, (VT*)smem,
+                                          (int32_t*)(smem + 256 * SEQ_PER * sizeof(VT)), body);
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
 }
@@ -359,7 +420,7 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 // within the wave, waves in index order; the per-block partials are summed in a fixed
 // tree by a finalize role (FFin; deterministic for a given launch shape).
 template <int D, class Op>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt, int* seen) {
     if (halt && *halt) {
         if (seen && blockIdx.x == 0 && threadIdx.x == 0) *seen = 1;
