@@ -73,7 +73,7 @@ typedef struct {
     int32_t alg;               /* pbcg_alg                                                    */
     int32_t prec;              /* pbcg_prec                                                   */
     int32_t max_outer;         /* FP32-IR: outer refinement steps (default 30 if 0)           */
-    double inner_tol;          /* FP32-IR: inner recursive tolerance (default 1e-5 if 0)      */
+    double inner_tol;          /* FP32-IR: inner recursive tolerance (default 1e-3 if 0)      */
     const pbcg_csr* M;         /* right preconditioner on the same n (NULL = none): the
                                   solver runs on A.M and returns x = M y                      */
     int32_t fallback;          /* with M: on breakdown / non-finite / stall restart the

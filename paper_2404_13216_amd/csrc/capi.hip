@@ -255,11 +255,12 @@ struct FnFAxpyState {
     __device__ void operator()(int64_t i) const { x[i] = x[i] + st->alpha * p[i]; }
 };
 struct FnInitState {
-    State* st; double tol; int max_iter; double* hist; int hist_len;
+    State* st; double tol; int max_iter; double* hist; int hist_len; int stall_window; double* stall_hist;
     __device__ void operator()() const {
         State z;
         memset(&z, 0, sizeof(z));
         z.tol = tol; z.max_iter = max_iter; z.hist = hist; z.hist_len = hist_len;
+        z.stall_window = stall_window; z.stall_hist = stall_hist;
         *st = z;
     }
 };
@@ -340,7 +341,7 @@ void pbcg_default_opts(pbcg_opts* o) {
     o->alg = PBCG_ALG_PBICGSTAB;
     o->prec = PBCG_PREC_FP64;
     o->max_outer = 30;
-    o->inner_tol = 1e-5;
+    o->inner_tol = 1e-3;
     o->batch = 16;
     o->stall_window = 200;
 }
@@ -480,6 +481,7 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
 }
 
 constexpr int CONTINUE = -100;
+constexpr int STALLED = 4;   // internal status of a stalled preconditioned solve
 
 struct Driver {
     const pbcg_csr* A;
@@ -492,6 +494,7 @@ struct Driver {
     int* halt;
     int* seen;             // &st->halt_seen: checked by the SpMVs of the iteration loop
     int batch;
+    int max_iter;          // iteration limit of the current run
     int kind;              // SpMV kernel shape
     pbcg_csr A32;          // FP32 copy of A (refinement)
 
@@ -552,6 +555,7 @@ struct Driver {
             return PBCG_BREAKDOWN;
         }
         if (reason & R_BREAKDOWN) return PBCG_BREAKDOWN;
+        if (reason & R_STALL) return STALLED;
         if (reason & R_MAXIT) return PBCG_NOT_CONVERGED;
         return CONTINUE;
     }
@@ -584,9 +588,11 @@ struct Driver {
         const int n = A->n;
         const bool bicg = o->alg == PBCG_ALG_BICGSTAB;
         double* hist = o->history;
-        int hist_len = hist ? o->history_len : 0;
-        if (!hist && W.hist) { hist = W.hist; hist_len = o->max_iter; }
-        launch_single(FnInitState{W.st, o->tol, o->max_iter, hist, hist_len}, s);
+        const int hist_len = hist ? o->history_len : 0;
+        const bool stall_on = M && o->fallback && W.hist;
+        const int window = o->stall_window > 0 ? o->stall_window : 200;
+        launch_single(FnInitState{W.st, o->tol, max_iter, hist, hist_len, stall_on ? window : 0,
+                                  stall_on ? W.hist : nullptr}, s);
         {
             DotsOp<1, FinNormB> nb{};
             nb.a[0] = b; nb.b[0] = b; nb.fin = FinNormB{W.st};
@@ -625,11 +631,11 @@ struct Driver {
             if (r != CONTINUE) return r;
             launch_single(FnResume{W.st}, s);
         }
-        if (o->max_iter == 0) return PBCG_NOT_CONVERGED;
+        if (max_iter == 0) return PBCG_NOT_CONVERGED;
         bool first = true;
         int polled = 0, batches = 0;
         // device-side halts end the loop; this bound only guards against a broken state
-        const long long limit = (long long)o->max_iter + 4LL * batch + 64;
+        const long long limit = (long long)max_iter + 4LL * batch + 64;
         long long enqueued = 0;
         while (true) {
             if (enqueued > limit) return PBCG_ERR_HIP;
@@ -667,7 +673,8 @@ struct Driver {
         int* fh = &fs->halt;
         int* fseen = &fs->halt_seen;
         const float* scal = &fs->alpha;
-        launch_single(FnInitFState{fs, (float)o->inner_tol, std::max(o->max_iter, 1)}, s);
+        const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-3;
+        launch_single(FnInitFState{fs, (float)itol, std::max(o->max_iter, 1)}, s);
         launch_ew(FnZeroF{W.d32}, n, nullptr, s);
         launch_ew(FnCopyF{W.rh32, W.r32}, n, nullptr, s);
         launch_spmv_t<float, float, float>(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s, kind);
@@ -729,7 +736,7 @@ struct Driver {
     // FP64 iterative refinement around the FP32 inner solver.
     int run_ir(State& h, int& outer, int& inner_total) {
         const int n = A->n;
-        launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0}, s);
+        launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0, 0, nullptr}, s);
         launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
         A32 = *A;
         A32.val = W.val32;
@@ -811,14 +818,30 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     D.seen = &W.st->halt_seen;
     D.batch = opts->batch > 0 ? opts->batch : 16;
     D.kind = opts->spmv_kind;
+    D.max_iter = opts->max_iter;
     State h{};
     int status;
     int outer = 0, inner_total = 0;
+    int fell_back = 0, iters_before = 0;
     if (opts->prec == PBCG_PREC_FP32_IR) {
         status = D.run_ir(h, outer, inner_total);
     } else {
         status = D.run_fp64(h);
+        if (D.M && opts->fallback &&
+            (status == PBCG_BREAKDOWN || status == PBCG_ERR_NONFINITE || status == STALLED)) {
+            // the true residual judges between x0 = 0 and x = M y; restart unpreconditioned
+            D.true_residual_enqueue();          // x = M y lands in tmp2
+            if (D.sync_state(&h)) return PBCG_ERR_HIP;
+            if (std::isfinite(h.true_rel) && h.true_rel < 1.0) launch_ew(FnCopy{x, W.tmp2}, A->n, nullptr, D.s);
+            else launch_ew(FnZero{x}, A->n, nullptr, D.s);
+            iters_before = h.iter;
+            D.M = nullptr;
+            D.max_iter = std::max(opts->max_iter - iters_before, 0);
+            fell_back = 1;
+            status = D.run_fp64(h);
+        }
     }
+    if (status == STALLED) status = PBCG_BREAKDOWN;  // only reachable without a fallback
     if (status != PBCG_ERR_HIP) {
         const bool have_true = (opts->prec == PBCG_PREC_FP32_IR) ||
                                (status == PBCG_OK && (h.reason & (R_CHECK | R_YYZERO)));
@@ -837,7 +860,8 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     if (info) {
         const bool zr = (h.reason & R_ZERO_RHS) != 0;
         info->status = status;
-        info->iterations = opts->prec == PBCG_PREC_FP32_IR ? inner_total : h.iter;
+        info->iterations = opts->prec == PBCG_PREC_FP32_IR ? inner_total : h.iter + iters_before;
+        info->fell_back = fell_back;
         info->outer_iterations = outer;
         info->true_checks = h.true_checks;
         info->true_relres = zr ? 0.0 : h.true_rel;

@@ -628,6 +628,12 @@ struct FinPhaseB {
         const double rec = sqrt(rr) / st->normb;
         st->rec = rec; st->rw = rw; st->rr = rr;
         if (st->hist && it <= st->hist_len) st->hist[it - 1] = rec;
+        bool stall = false;
+        if (st->stall_hist) {
+            st->stall_hist[it - 1] = rec;
+            const int W = st->stall_window;
+            stall = W > 0 && it > W && rec > 0.5 * st->stall_hist[it - 1 - W];
+        }
         const double beta = ((alpha / omega) * rho_new) / rho;
         const double den = (rw + beta * st->rs) - (beta * omega) * st->rz;
         const double alpha_new = den != 0.0 ? rho_new / den : __longlong_as_double(0x7ff8000000000000ll);
@@ -638,6 +644,7 @@ struct FinPhaseB {
         if (nonfin) reason |= R_NONFINITE;
         else if (rho_new == 0.0 || den == 0.0) reason |= R_BREAKDOWN;
         else { st->beta = beta; st->alpha = alpha_new; st->rho = rho_new; }
+        if (stall) reason |= R_STALL;
         if (it >= st->max_iter) reason |= R_MAXIT;
         if (reason) { st->halt = 1; st->reason |= reason; }
     }

@@ -13,6 +13,7 @@ enum : int {
     R_YYZERO = 16,      // (y,y) == 0: host tests (q,q) for a lucky breakdown
     R_ZERO_RHS = 32,    // ||b|| == 0
     R_CONVERGED = 64,   // (inner FP32 solve) recursive tolerance met
+    R_STALL = 128,      // recursive residual not halved over stall_window iterations
 };
 
 // FP64 solver scalars.  alpha, beta, omega are consecutive: kernels read them
@@ -29,9 +30,9 @@ struct State {
     double normb, rec, true_rel, tol;
     double rw, rr, last_dot, pad0;
     int32_t iter, max_iter, halt, reason;
-    int32_t hist_len, true_checks, halt_seen, pad2;
+    int32_t hist_len, true_checks, halt_seen, stall_window;
     double* hist;
-    double* pad3;
+    double* stall_hist;     // full per-iteration history for stall detection (or null)
 };
 
 // FP32 inner-solver scalars.
