@@ -298,12 +298,12 @@ def dot_f32_seq(a: np.ndarray, b: np.ndarray) -> np.float32:
     return np.float32(np.add.accumulate(prod, dtype=np.float32)[-1])
 
 
-def pbicgstab_f32(A32, b32, tol=1e-5, max_iter=5000, dot=None) -> tuple[np.ndarray, int, float]:
+def pbicgstab_f32(A32, b32, tol=1e-5, max_iter=5000, dot=None, stall=100) -> tuple[np.ndarray, int, float]:
     """Algorithm 2 entirely in float32 (values, vectors, SpMV, dots, scalars), x0 = 0.
 
-    Stops on the recursive residual only: sqrt((r, r)) / ||b|| <= tol, or on
-    breakdown / non-finite scalars, returning the current iterate.
-    Returns (x, iterations, rec).
+    Stops on the recursive residual only: sqrt((r, r)) / ||b|| <= tol, or when it has
+    not set a new minimum for ``stall`` iterations, or on breakdown / non-finite
+    scalars, returning the current iterate.  Returns (x, iterations, rec).
     """
     f = np.float32
     dot = dot or dot_f32_seq
@@ -323,6 +323,7 @@ def pbicgstab_f32(A32, b32, tol=1e-5, max_iter=5000, dot=None) -> tuple[np.ndarr
     alpha = f(rho / rw)
     beta = omega = f(0)
     rec = 1.0
+    best, it_best = math.inf, 0
     for i in range(max_iter):
         if i == 0:
             p, s, z = r.copy(), w.copy(), t.copy()
@@ -354,6 +355,10 @@ def pbicgstab_f32(A32, b32, tol=1e-5, max_iter=5000, dot=None) -> tuple[np.ndarr
         rec = float(f(np.sqrt(rr)) / nb)
         if rec <= tol:
             return x, i + 1, rec
+        if rec < best:
+            best, it_best = rec, i + 1
+        elif stall and (i + 1) - it_best >= stall:
+            return x, i + 1, rec
         beta = f(f(f(alpha / omega) * rho_new) / rho)
         den = f(f(rw + f(beta * rs)) - f(f(beta * omega) * rz))
         if rho_new == 0 or den == 0 or not np.isfinite(den):
@@ -384,7 +389,7 @@ def pbicgstab_fallback(A, b, M, tol=1e-10, max_iter=10000, stall_window=200, dot
 
 
 def ir_solve(A, b, tol=1e-10, inner_tol=1e-3, max_outer=30, max_inner=5000, dot=None,
-             dot32=None, spmv=None) -> Result:
+             dot32=None, spmv=None, inner_stall=100, max_fp64=10000) -> Result:
     """FP64 iterative refinement around an FP32 inner p-BiCGStab.
 
     outer k:  r = b - A x (FP64 SpMV), nu = sqrt(exdot(r, r));
@@ -395,7 +400,10 @@ def ir_solve(A, b, tol=1e-10, inner_tol=1e-3, max_outer=30, max_inner=5000, dot=
               ends in inner iteration caps or outer stagnation)
               d = p-BiCGStab_fp32(fp32(A), r32, x0 = 0, tol = inner_tol);
               x = x + nu * fp64(d).
-    STAGNATED when nu_{k+1} > 0.9 nu_k.  x starts at 0.
+    When nu_{k+1} > 0.9 nu_k (stagnation) or after max_outer steps, the solve finishes
+    with FP64 p-BiCGStab from the iterate with the smallest outer residual
+    (``fell_back`` = 1).  The inner solve also stops when its recursive residual has
+    not set a new minimum for ``inner_stall`` iterations.  x starts at 0.
     """
     from synthgen import CSR
     spmv = spmv or _spmv
@@ -408,21 +416,23 @@ def ir_solve(A, b, tol=1e-10, inner_tol=1e-3, max_outer=30, max_inner=5000, dot=
     if normb == 0.0:
         return Result(x, OK, 0, 0.0, 0.0)
     total_inner = 0
-    nu_prev = math.inf
-    rel = math.inf
+    nu_prev = nu_best = math.inf
+    x_best = x
     for k in range(max_outer + 1):
         r = b - spmv(A, x)
         nu = math.sqrt(dot(r, r))
         rel = nu / normb
         if rel <= tol:
             return Result(x, OK, total_inner, rel, rel, outer_iterations=k)
-        if nu > 0.9 * nu_prev:
-            return Result(x, STAGNATED, total_inner, rel, rel, outer_iterations=k)
-        if k == max_outer:
-            break
+        if nu < nu_best:
+            nu_best, x_best = nu, x
+        if nu > 0.9 * nu_prev or k == max_outer:
+            # stagnation or budget: finish in FP64 from the best iterate (true residual judges)
+            fin = pbicgstab(A, b, x0=x_best, tol=tol, max_iter=max_fp64, dot=dot, spmv=spmv)
+            return Result(fin.x, fin.status, total_inner + fin.iterations, fin.true_relres, fin.rec_relres,
+                          fin.true_checks, outer_iterations=k, fell_back=1)
         nu_prev = nu
         r32 = (r / nu).astype(np.float32)
-        d, its, _ = pbicgstab_f32(A32, r32, inner_tol, max_inner, dot32)
+        d, its, _ = pbicgstab_f32(A32, r32, inner_tol, max_inner, dot32, inner_stall)
         total_inner += its
         x = x + nu * d.astype(np.float64)
-    return Result(x, NOT_CONVERGED, total_inner, rel, rel, outer_iterations=max_outer)

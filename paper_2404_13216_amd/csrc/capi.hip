@@ -265,11 +265,12 @@ struct FnInitState {
     }
 };
 struct FnInitFState {
-    FState* st; float tol; int max_iter;
+    FState* st; float tol; int max_iter; int stall;
     __device__ void operator()() const {
         FState z;
         memset(&z, 0, sizeof(z));
-        z.tol = tol; z.max_iter = max_iter;
+        z.tol = tol; z.max_iter = max_iter; z.stall = stall;
+        z.best = __int_as_float(0x7f800000);   // +inf
         *st = z;
     }
 };
@@ -482,6 +483,8 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
 
 constexpr int CONTINUE = -100;
 constexpr int STALLED = 4;   // internal status of a stalled preconditioned solve
+constexpr int IR_INNER_STALL = 100;   // inner FP32 solve: iterations without a new best residual
+constexpr int IR_FP64_FINISH = 10000; // iteration limit of the FP64 finish after stagnation
 
 struct Driver {
     const pbcg_csr* A;
@@ -495,6 +498,7 @@ struct Driver {
     int* seen;             // &st->halt_seen: checked by the SpMVs of the iteration loop
     int batch;
     int max_iter;          // iteration limit of the current run
+    int fell_back = 0;     // a fallback (preconditioned) or an FP64 finish (refinement) ran
     int kind;              // SpMV kernel shape
     pbcg_csr A32;          // FP32 copy of A (refinement)
 
@@ -674,7 +678,7 @@ struct Driver {
         int* fseen = &fs->halt_seen;
         const float* scal = &fs->alpha;
         const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-3;
-        launch_single(FnInitFState{fs, (float)itol, std::max(o->max_iter, 1)}, s);
+        launch_single(FnInitFState{fs, (float)itol, std::max(o->max_iter, 1), IR_INNER_STALL}, s);
         launch_ew(FnZeroF{W.d32}, n, nullptr, s);
         launch_ew(FnCopyF{W.rh32, W.r32}, n, nullptr, s);
         launch_spmv_t<float, float, float>(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s, kind);
@@ -756,7 +760,8 @@ struct Driver {
         }
         if (h.reason & R_NONFINITE) return PBCG_ERR_NONFINITE;
         const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
-        double nu_prev = INFINITY;
+        double nu_prev = INFINITY, nu_best = INFINITY;
+        double* x_best = W.p;   // free during the outer loop
         for (int k = 0; k <= max_outer; ++k) {
             EpiResidDot<FinIR> epi{b, W.r, FinIR{W.st}};
             launch_spmv_dot<1>(A, x, epi, W.site, nullptr, s, kind);
@@ -765,8 +770,19 @@ struct Driver {
             const double nu = h.last_dot;
             if (h.true_rel <= o->tol) return PBCG_OK;
             if (!std::isfinite(nu)) return PBCG_ERR_NONFINITE;
-            if (nu > 0.9 * nu_prev) return PBCG_STAGNATED;
-            if (k == max_outer) break;
+            if (nu < nu_best) {
+                nu_best = nu;
+                launch_ew(FnCopy{x_best, x}, n, nullptr, s);
+            }
+            if (nu > 0.9 * nu_prev || k == max_outer) {
+                // stagnation or budget: finish in FP64 from the best iterate
+                launch_ew(FnCopy{x, x_best}, n, nullptr, s);
+                fell_back = 1;
+                max_iter = IR_FP64_FINISH;
+                int st = run_fp64(h);
+                inner_total += h.iter;
+                return st;
+            }
             nu_prev = nu;
             launch_ew(FnCastScaled{W.r32, W.r, W.st}, n, nullptr, s);
             int its = 0;
@@ -825,6 +841,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     int fell_back = 0, iters_before = 0;
     if (opts->prec == PBCG_PREC_FP32_IR) {
         status = D.run_ir(h, outer, inner_total);
+        fell_back = D.fell_back;
     } else {
         status = D.run_fp64(h);
         if (D.M && opts->fallback &&
@@ -843,7 +860,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     }
     if (status == STALLED) status = PBCG_BREAKDOWN;  // only reachable without a fallback
     if (status != PBCG_ERR_HIP) {
-        const bool have_true = (opts->prec == PBCG_PREC_FP32_IR) ||
+        const bool have_true = (opts->prec == PBCG_PREC_FP32_IR && !fell_back) ||
                                (status == PBCG_OK && (h.reason & (R_CHECK | R_YYZERO)));
         if (!have_true && !(h.reason & R_ZERO_RHS)) {
             D.true_residual_enqueue();
@@ -865,7 +882,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         info->outer_iterations = outer;
         info->true_checks = h.true_checks;
         info->true_relres = zr ? 0.0 : h.true_rel;
-        info->rec_relres = zr ? 0.0 : (opts->prec == PBCG_PREC_FP32_IR ? h.true_rel : h.rec);
+        info->rec_relres = zr ? 0.0 : ((opts->prec == PBCG_PREC_FP32_IR && !fell_back) ? h.true_rel : h.rec);
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;

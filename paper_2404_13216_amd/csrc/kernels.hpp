@@ -875,6 +875,8 @@ struct FFinPhaseB {
         int reason = 0;
         if (rec <= st->tol) reason |= R_CONVERGED;
         else {
+            if (rec < st->best) { st->best = rec; st->it_best = it; }
+            else if (st->stall > 0 && it - st->it_best >= st->stall) reason |= R_STALL;
             const float beta = ((alpha / omega) * rho_new) / rho;
             const float den = (rw + beta * st->rs) - (beta * omega) * st->rz;
             if (rho_new == 0.0f || den == 0.0f || !isfinite(den)) reason |= R_BREAKDOWN;

@@ -39,9 +39,9 @@ struct State {
 struct FState {
     float alpha, beta, omega, rho;
     float rs, rz, normb, rec;
-    float tol, pad0, pad1, pad2;
+    float tol, best, pad1, pad2;     // best: smallest recursive residual so far
     int32_t iter, max_iter, halt, reason;
-    int32_t halt_seen, fpad0, fpad1, fpad2;
+    int32_t halt_seen, it_best, stall, fpad2;   // stall: iterations without a new best that stop
 };
 
 }  // namespace pbcg
