@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 CSRC = os.path.join(ROOT, "paper_2404_13216_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cd3d_128.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cd3d_128.md")
 
 
 def log(*a):
@@ -57,6 +57,37 @@ def time_launches(fn, reps, torch):
     return s.elapsed_time(e) / 1e3 / reps
 
 
+def traffic_run(pk, torch, A, n, nnz, dev):
+    """Kernels whose HBM bytes rocprofv3 counters measure: a 256 MiB device copy (the
+    calibration: 256 MiB read, 256 MiB written), the SpMV, phase A / phase B and the
+    standalone exact dot on the 128^3 workload; each launched 10 times, with a 1 GiB read
+    between launches so that no launch is served from the Infinity Cache."""
+    rng = np.random.default_rng(1)
+    V = {k: torch.from_numpy(rng.standard_normal(n) * 1e-3).to(dev) for k in
+         ("x", "r", "rhat", "w", "t", "p", "s", "z", "q", "y", "v")}
+    scal = torch.tensor([0.5, 0.25, 0.75], dtype=torch.float64, device=dev)
+    dots = torch.empty(4, dtype=torch.float64, device=dev)
+    wsp = torch.empty(pk.lib().pbcg_phase_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    flush = torch.ones(128 << 20, dtype=torch.float64, device=dev)
+    o1 = torch.empty(1, dtype=torch.float64, device=dev)
+    wse = torch.empty(pk.lib().exdot_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    for _ in range(10):
+        flush.sum()
+        dst.copy_(src)
+        flush.sum()
+        pk.csr_spmv(A, V["z"], V["v"])
+        flush.sum()
+        pk.pbcg_phase_a(V, scal, False, dots, wsp)
+        flush.sum()
+        pk.pbcg_phase_b(V, scal, dots, wsp)
+        flush.sum()
+        pk.exdot(V["r"], V["w"], o1, wse)
+    torch.cuda.synchronize()
+    log("traffic run done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-only", action="store_true")
     ap.add_argument("--reps", type=int, default=50)
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="launch each measured kernel 10 times (for rocprofv3 --pmc runs) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -82,6 +115,10 @@ def main():
     b = torch.from_numpy(prob.b).to(dev)
     n, nnz = prob.A.n, prob.A.nnz
     log(f"workload cd3d_128 n={n} nnz={nnz} built in {time.time() - t0:.1f}s")
+
+    if args.traffic_run:
+        traffic_run(pk, torch, A, n, nnz, dev)
+        return
 
     solver = pk.Solver(A, tol=1e-10, max_iter=10000)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -243,7 +280,9 @@ def main():
         dom = max(per_iter, key=per_iter.get)
         traffic = None
         if os.path.exists(TRAFFIC_FILE):
-            tr = json.load(open(TRAFFIC_FILE))
+            txt = open(TRAFFIC_FILE).read()
+            blob = txt[txt.index("```json") + 7: txt.index("```", txt.index("```json") + 7)]
+            tr = json.loads(blob)
             if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
                 traffic = tr["kernels"][dom]["bytes_per_launch"]
         out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": kern[dom]["GBs"], "peak": HBM_PEAK_GBS,
