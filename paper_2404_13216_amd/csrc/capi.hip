@@ -124,7 +124,8 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
     const int n = A->n;
     const VT* val = (const VT*)A->val;
     if (kind == PBCG_SPMV_SEQ) {
-        int grid = std::max(1, std::min(DOT_GRID_DEFAULT, (n + BLOCK - 1) / BLOCK));
+        // persistent: up to 4 blocks per CU (one dot record each)
+        int grid = std::max(1, std::min(DOT_GRID_MAX, (n + BLOCK - 1) / BLOCK));
         spmv_seq_dot_kernel<D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, site,
                                                                       halt);
         fin_kernel<XFin<D, Epi>><<<1, BLOCK, 0, s>>>(XFin<D, Epi>{epi, site, grid, halt});
