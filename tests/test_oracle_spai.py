@@ -1,0 +1,105 @@
+"""Pins of the learned-preconditioner oracle.
+
+Central finite differences of the loss in float64 pin the whole analytic gradient
+chain (SDDMM, skip connection, both GELU layers, biases); the untrained net (zero
+last layer) is exactly Jacobi; the features are invariant under A -> cA and the
+m values scale as 1/c; the bf16 rounding matches its definition on hand-picked
+values; Adam matches its closed form on the first step (lr * sign(g)).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthgen as g
+from oracle import spai
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = g.problem("spai_eval_128", scale=5)
+    V = g.rademacher(p.A.n, 3, 7) * 0.5 + np.random.default_rng(0).standard_normal((p.A.n, 3)) * 0.1
+    return p.A, np.asfortranarray(V)
+
+
+def test_param_count():
+    assert spai.NPARAM == 5057
+
+
+def test_untrained_is_jacobi(small):
+    A, _ = small
+    th = spai.init_params(0)
+    m = spai.m_values(A, th)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    expect = np.where(rows == A.col_idx, 1.0 / A.diag()[rows], 0.0)
+    assert np.allclose(m, expect, rtol=0, atol=0)
+
+
+def test_features_scale_invariant(small):
+    A, _ = small
+    phi = spai.features(A)
+    A3 = g.CSR(A.n, A.row_ptr, A.col_idx, A.val * 3.0)
+    assert np.allclose(spai.features(A3), phi, rtol=1e-14, atol=1e-15)
+    th = spai.init_params(1)
+    th[-65:-1] = np.random.default_rng(2).standard_normal(64) * 0.1
+    assert np.allclose(spai.m_values(A3, th) * 3.0, spai.m_values(A, th), rtol=1e-13)
+
+
+def test_features_closed_form_entries():
+    A = g.cd_stencil(4, 2, (0.0, 0.0))  # symmetric Laplacian: diag 4, off -1
+    phi = spai.features(A)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    off = rows != A.col_idx
+    assert np.allclose(phi[off, 0], -0.25) and np.allclose(phi[off, 1], -0.25)
+    assert np.allclose(phi[:, 2], 1.0) and np.allclose(phi[:, 3], 1.0)
+    assert np.allclose(phi[off, 11], 0.0)  # symmetric: zero local Peclet number
+    assert np.allclose(phi[~off, 10], 1.0) and np.allclose(phi[off, 10], 0.0)
+
+
+def test_gradient_matches_finite_differences(small):
+    A, V = small
+    rng = np.random.default_rng(3)
+    th = spai.init_params(4)
+    th += rng.standard_normal(th.size) * 0.05
+    L, grad = spai.loss_and_grad(A, th, V)
+    idx = np.concatenate([rng.choice(768, 6, replace=False),                    # W1
+                          768 + rng.choice(64, 3, replace=False),              # b1
+                          832 + rng.choice(4096, 6, replace=False),            # W2
+                          4928 + rng.choice(64, 3, replace=False),             # b2
+                          4992 + rng.choice(64, 4, replace=False), [5056]])    # w3, b3
+    for k in idx:
+        h = 1e-6 * max(1.0, abs(th[k]))
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (spai.loss_and_grad(A, tp, V)[0] - spai.loss_and_grad(A, tm, V)[0]) / (2 * h)
+        assert abs(fd - grad[k]) <= 1e-6 * max(1e-8, abs(grad).max()), (k, fd, grad[k])
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -2.5, 1e-30], dtype=np.float32)
+    out = spai.to_bf16(vals)
+    assert out[0] == 1.0
+    assert out[1] == 1.0                     # tie -> even (mantissa ...0)
+    assert out[2] == 1.0 + 2 ** -7           # exactly representable
+    assert out[3] == 1.0 + 2 ** -6           # tie -> even (mantissa ...10)
+    assert out[4] == -2.5
+    assert abs(out[5] - 1e-30) <= 1e-30 * 2 ** -8
+
+
+def test_adam_first_step_is_signed_lr():
+    g0 = np.array([0.3, -2.0, 1e-3])
+    th, m, v = spai.adam_step(np.zeros(3), g0, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
+    assert np.allclose(th, -0.01 * np.sign(g0))
+
+
+def test_training_reduces_loss(small):
+    A, V = small
+    th = spai.init_params(5)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    L0 = spai.loss_and_grad(A, th, V)[0]
+    for t in range(1, 41):
+        L, gr = spai.loss_and_grad(A, th, V)
+        th, m, v = spai.adam_step(th, gr, m, v, t, lr=3e-3)
+    assert spai.loss_and_grad(A, th, V)[0] < 0.9 * L0
