@@ -171,6 +171,45 @@ size_t pbicgstab_workspace_bytes(int32_t n, int64_t nnz, const pbcg_opts* opts);
 int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_opts* opts,
                     pbcg_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------
+ * Learned sparse approximate inverse M on A's pattern (right preconditioner for
+ * pbicgstab_solve via opts->M).  m_ij = ([i == j] + f(phi_ij)) / a_ii with f an MLP
+ * 12 -> 64 -> 64 -> 1 (GELU, erf form) over 12 per-nonzero features phi_ij; with the
+ * last layer zero M is Jacobi.  Parameters: 5057 FP32 values, flat layout
+ * W1[64x12] row-major, b1[64], W2[64x64] row-major, b2[64], w3[64], b3.
+ * A must have FP64 values and n, nnz > 0.  No call allocates device memory.
+ */
+int spai_param_count(void);
+size_t spai_workspace_bytes(int32_t n, int64_t nnz, int32_t k);
+
+/* Features (nnz x 12 FP32, row-major per nonzero), the row index of every nonzero
+ * and diag[i] = a_ii (FP64, 0 if absent).  Column sums of |A| use exact fixed-point
+ * integer accumulation (order independent). */
+int spai_features(const pbcg_csr* A, float* feat, int32_t* rowidx, double* diag,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* FP32 MLP forward: f_out (nnz, may be NULL) and m_out (nnz) = M values. */
+int spai_forward(int64_t nnz, const float* feat, const float* params, const int32_t* rowidx,
+                 const int32_t* col_idx, const double* diag, float* f_out, float* m_out, void* stream);
+
+/* bf16 inference with MFMA: weights and layer inputs rounded to bf16 (nearest even),
+ * FP32 accumulation and GELU, M values stored FP32. */
+int spai_infer_bf16(int64_t nnz, const float* feat, const float* params, const int32_t* rowidx,
+                    const double* diag, float* m_out, void* stream);
+
+/* U = A V for a probe block V (n x k, column-major FP32); FP64 row sums stored FP32. */
+int spai_probe_product(const pbcg_csr* A, const float* V, int32_t k, float* U, void* stream);
+
+/* Loss L = ||M U - V||_F^2 / (k n) (M from the FP32 forward, written to m_tmp) and its
+ * gradient with respect to the 5057 parameters; every reduction in a fixed order. */
+int spai_loss_grad(const pbcg_csr* A, const float* feat, const int32_t* rowidx, const double* diag,
+                   const float* params, const float* V, const float* U, int32_t k, float* m_tmp,
+                   float* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba) on the parameters, t >= 1. */
+int spai_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr,
+              float b1, float b2, float eps, void* stream);
+
 /* Fill `opts` (host) with defaults: tol 1e-10, max_iter 10000, p-BiCGStab, FP64. */
 void pbcg_default_opts(pbcg_opts* opts);
 

@@ -62,6 +62,8 @@ EXPORTS = [
     "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "exdot_workspace_bytes", "exdot", "exdot_config",
     "pbcg_phase_workspace_bytes", "pbcg_phase_a", "pbcg_phase_b", "pbicgstab_workspace_bytes",
     "pbicgstab_solve", "pbcg_default_opts", "pbcg_status_string", "pbcg_abi_version",
+    "spai_param_count", "spai_workspace_bytes", "spai_features", "spai_forward", "spai_infer_bf16",
+    "spai_probe_product", "spai_loss_grad", "spai_adam",
 ]
 
 _lib = None
@@ -93,6 +95,15 @@ def lib():
         "pbcg_default_opts": (None, [ctypes.POINTER(PbcgOpts)]),
         "pbcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pbcg_abi_version": (ctypes.c_int, []),
+        "spai_param_count": (ctypes.c_int, []),
+        "spai_workspace_bytes": (sz, [i32, i64, i32]),
+        "spai_features": (ctypes.c_int, [CP, _P, _P, _P, _P, sz, _P]),
+        "spai_forward": (ctypes.c_int, [i64, _P, _P, _P, _P, _P, _P, _P, _P]),
+        "spai_infer_bf16": (ctypes.c_int, [i64, _P, _P, _P, _P, _P, _P]),
+        "spai_probe_product": (ctypes.c_int, [CP, _P, i32, _P, _P]),
+        "spai_loss_grad": (ctypes.c_int, [CP, _P, _P, _P, _P, _P, _P, i32, _P, _P, _P, _P, sz, _P]),
+        "spai_adam": (ctypes.c_int, [_P, _P, _P, _P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -12,7 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libpbicgstab.so")
-SOURCES = [os.path.join(HERE, "csrc", "capi.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "capi.hip"), os.path.join(HERE, "csrc", "spai.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

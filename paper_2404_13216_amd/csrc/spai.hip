@@ -1,0 +1,596 @@
+// Learned sparse approximate inverse on A's pattern: feature, MLP (FP32 training and
+// bf16-MFMA inference), probe products, loss / gradient and Adam kernels (gfx950).
+//
+// m_ij = ([i = j] + f(phi_ij)) / a_ii,  f: 12 -> 64 -> 64 -> 1 with GELU (erf form);
+// loss L = ||M U - V||_F^2 / (k n) with U = A V for probe blocks V (n x k).
+// Deterministic by construction: no floating-point atomics; every reduction runs in a
+// fixed order (column sums of |A| use exact fixed-point integer atomics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/pbicgstab.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+constexpr int NF = 12, HID = 64;
+constexpr int NPARAM = HID * NF + HID + HID * HID + HID + HID + 1;  // 5057
+constexpr int OFF_W1 = 0, OFF_B1 = HID * NF, OFF_W2 = OFF_B1 + HID, OFF_B2 = OFF_W2 + HID * HID,
+              OFF_W3 = OFF_B2 + HID, OFF_B3 = OFF_W3 + HID;
+constexpr int BLOCK = 256;
+constexpr int GRAD_BLOCKS = 256;   // fixed partition of the weight-gradient reduction
+constexpr int ACT = 4 * HID + 1;   // per-nonzero saved values: dz1, h1, dz2, h2, g_f
+
+#define HIPCHK(expr)                              \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return PBCG_ERR_HIP; \
+    } while (0)
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+    const float pdf = expf(-0.5f * x * x) * 0.39894228040143268f;
+    return cdf + x * pdf;
+}
+
+// ------------------------------------------------------------------ matrix statistics
+__global__ void k_zero64(unsigned long long* p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// maximum |a| as its bit pattern (positive doubles order like their bits)
+__global__ void __launch_bounds__(BLOCK) k_maxabs(int64_t nnz, const double* __restrict__ val,
+                                                  unsigned long long* out) {
+    unsigned long long m = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (unsigned long long)__double_as_longlong(fabs(val[k])));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor((long long)m, o));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
+struct Stats {
+    double* diag;              // a_ii (0 if absent)
+    double* rsum;              // sum_j |a_ij|, left to right
+    unsigned long long* cfix;  // sum_i |a_ij| as a fixed-point integer (scale 2^cshift)
+    float* maxoff;             // max_{j in row i} |j - i|
+    int* maxlen;               // max row length
+    int* rowidx;               // row of every nonzero
+};
+
+__global__ void __launch_bounds__(BLOCK) k_row_stats(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                     const double* __restrict__ val, const unsigned long long* maxabs_bits,
+                                                     Stats st) {
+    // fixed-point scale: n * max|a| * 2^s < 2^62
+    const double maxabs = __longlong_as_double((long long)*maxabs_bits);
+    int e = 0;
+    frexp(maxabs * (double)max(n, 1), &e);
+    const int cshift = 61 - e;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = rp[i], b = rp[i + 1];
+    double r = 0.0, d = 0.0;
+    int mo = 0;
+    for (int k = a; k < b; ++k) {
+        const int j = ci[k];
+        const double v = val[k];
+        r = r + fabs(v);
+        if (j == i) d = v;
+        mo = max(mo, abs(j - i));
+        st.rowidx[k] = i;
+        const unsigned long long q = (unsigned long long)llrint(ldexp(fabs(v), cshift));
+        atomicAdd(st.cfix + j, q);   // integer sums commute: deterministic
+    }
+    st.diag[i] = d;
+    st.rsum[i] = r;
+    st.maxoff[i] = (float)mo;
+    atomicMax(st.maxlen, b - a);
+}
+
+__device__ __forceinline__ double col_sum(const Stats& st, int j, int cshift) {
+    return ldexp((double)st.cfix[j], -cshift);
+}
+
+// a_ji by binary search in row j (columns ascending); 0 if absent
+__device__ __forceinline__ double lookup(const int32_t* rp, const int32_t* ci, const double* val, int j, int i) {
+    int lo = rp[j], hi = rp[j + 1] - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = ci[mid];
+        if (c == i) return val[mid];
+        if (c < i) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return 0.0;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_features(int n, int64_t nnz, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                    Stats st, const unsigned long long* maxabs_bits,
+                                                    float* __restrict__ feat) {
+    const double maxabs = __longlong_as_double((long long)*maxabs_bits);
+    int e = 0;
+    frexp(maxabs * (double)max(n, 1), &e);
+    const int cshift = 61 - e;
+    const double maxlen = (double)*st.maxlen;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = st.rowidx[k], j = ci[k];
+        const double aij = val[k];
+        const double aji = lookup(rp, ci, val, j, i);
+        const double dii = st.diag[i], djj = st.diag[j];
+        const double adi = fabs(dii), adj = fabs(djj);
+        const double mo = (double)st.maxoff[i];
+        float* f = feat + k * NF;
+        f[0] = (float)(aij / adi);
+        f[1] = (float)(aji / adi);
+        f[2] = (float)(djj / adi);
+        f[3] = (float)((dii > 0.0) - (dii < 0.0));
+        f[4] = (float)(st.rsum[i] / adi);
+        f[5] = (float)(st.rsum[j] / adj);
+        f[6] = (float)(col_sum(st, i, cshift) / adi);
+        f[7] = (float)(col_sum(st, j, cshift) / adj);
+        f[8] = (float)((double)(rp[i + 1] - rp[i]) / maxlen);
+        f[9] = mo > 0.0 ? (float)((double)(j - i) / mo) : 0.0f;
+        f[10] = i == j ? 1.0f : 0.0f;
+        const double den = fmax(fabs(aij + aji), 0x1p-126);
+        f[11] = i == j ? 0.0f : (float)(fabs(aij - aji) / den);
+    }
+}
+
+// ------------------------------------------------------------------ FP32 MLP
+struct SmemW {
+    float W1[HID * NF], b1[HID], W2[HID * HID], b2[HID], w3[HID], b3;
+};
+
+__device__ __forceinline__ void load_weights(SmemW& s, const float* p) {
+    for (int t = threadIdx.x; t < NPARAM; t += blockDim.x) ((float*)&s)[t] = p[t];
+    __syncthreads();
+}
+
+// forward of one nonzero; keeps z1 and z2 (pre-activations) for the backward
+__device__ __forceinline__ float mlp_forward(const SmemW& s, const float* x, float* z1, float* z2) {
+    float h1[HID];
+#pragma unroll 4
+    for (int a = 0; a < HID; ++a) {
+        float acc = s.b1[a];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) acc = acc + s.W1[a * NF + c] * x[c];
+        z1[a] = acc;
+        h1[a] = gelu(acc);
+    }
+    float f = s.b3;
+    for (int a = 0; a < HID; ++a) {
+        float acc = s.b2[a];
+#pragma unroll 8
+        for (int b = 0; b < HID; ++b) acc = acc + s.W2[a * HID + b] * h1[b];
+        z2[a] = acc;
+        f = f + s.w3[a] * gelu(acc);
+    }
+    return f;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_forward(int64_t nnz, const float* __restrict__ feat, const float* __restrict__ params,
+                                                   const int* __restrict__ rowidx, const int32_t* __restrict__ ci,
+                                                   const double* __restrict__ diag, float* __restrict__ fout,
+                                                   float* __restrict__ mout) {
+    __shared__ SmemW s;
+    load_weights(s, params);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
+        float x[NF], z1[HID], z2[HID];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) x[c] = feat[k * NF + c];
+        const float f = mlp_forward(s, x, z1, z2);
+        if (fout) fout[k] = f;
+        const int i = rowidx[k];
+        mout[k] = (x[10] + f) / (float)diag[i];
+    }
+}
+
+// ------------------------------------------------------------------ probe products
+// U = A V  (FP64 values, FP32 probes; row sums left to right in FP64, stored FP32)
+__global__ void __launch_bounds__(BLOCK) k_probe_product(int n, int k, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                         const float* __restrict__ V, float* __restrict__ U) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (int q = rp[i]; q < rp[i + 1]; ++q) {
+            double prod = val[q] * (double)V[(size_t)c * n + ci[q]];
+            s = s + prod;
+        }
+        U[(size_t)c * n + i] = (float)s;
+    }
+}
+
+// R = M U - V (FP32, M values on A's pattern), plus per-block partial sums of R^2
+__global__ void __launch_bounds__(BLOCK) k_residual(int n, int k, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const float* __restrict__ m,
+                                                    const float* __restrict__ U, const float* __restrict__ V,
+                                                    float* __restrict__ R, float* __restrict__ part) {
+    __shared__ float red[BLOCK];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float sq = 0.0f;
+    if (i < n) {
+        for (int c = 0; c < k; ++c) {
+            float s = 0.0f;
+            for (int q = rp[i]; q < rp[i + 1]; ++q) {
+                float prod = m[q] * U[(size_t)c * n + ci[q]];
+                s = s + prod;
+            }
+            const float r = s - V[(size_t)c * n + i];
+            R[(size_t)c * n + i] = r;
+            float r2 = r * r;
+            sq = sq + r2;
+        }
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// loss = (sum of block partials in block order) / (k n)
+__global__ void k_loss(int nb, const float* part, float scale, float* loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.0f;
+        for (int b = 0; b < nb; ++b) s = s + part[b];
+        *loss = s * scale;
+    }
+}
+
+// per nonzero: g_m = scale * sum_c R_ic U_jc (SDDMM), g_f = g_m / a_ii, then the MLP
+// backward; saves dz1, h1, dz2, h2, g_f for the weight-gradient reduction
+__global__ void __launch_bounds__(BLOCK) k_backward(int n, int64_t nnz, int k, const float* __restrict__ feat,
+                                                    const float* __restrict__ params, const int* __restrict__ rowidx,
+                                                    const int32_t* __restrict__ ci, const double* __restrict__ diag,
+                                                    const float* __restrict__ R, const float* __restrict__ U, float scale,
+                                                    float* __restrict__ act) {
+    __shared__ SmemW s;
+    load_weights(s, params);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = rowidx[q], j = ci[q];
+        float gm = 0.0f;
+        for (int c = 0; c < k; ++c) {
+            float prod = R[(size_t)c * n + i] * U[(size_t)c * n + j];
+            gm = gm + prod;
+        }
+        gm = gm * scale;
+        const float gf = gm / (float)diag[i];
+        float x[NF], z1[HID], z2[HID];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) x[c] = feat[q * NF + c];
+        (void)mlp_forward(s, x, z1, z2);
+        float* o = act + q * ACT;
+        float dz2[HID];
+        for (int a = 0; a < HID; ++a) {
+            float t = gf * s.w3[a];
+            dz2[a] = t * gelu_grad(z2[a]);
+            o[2 * HID + a] = dz2[a];
+            o[3 * HID + a] = gelu(z2[a]);
+        }
+        for (int b = 0; b < HID; ++b) {
+            float dh = 0.0f;
+#pragma unroll 8
+            for (int a = 0; a < HID; ++a) dh = dh + s.W2[a * HID + b] * dz2[a];
+            o[b] = dh * gelu_grad(z1[b]);
+            o[HID + b] = gelu(z1[b]);
+        }
+        o[4 * HID] = gf;
+    }
+}
+
+// gradient entry e of a nonzero's contribution (x = features, saved activations a)
+__device__ __forceinline__ float grad_term(int e, const float* x, const float* a) {
+    if (e < OFF_B1) return a[e / NF] * x[e % NF];                         // dW1 = dz1 (x) phi
+    if (e < OFF_W2) return a[e - OFF_B1];                                  // db1 = dz1
+    if (e < OFF_B2) { int t = e - OFF_W2; return a[2 * HID + t / HID] * a[HID + t % HID]; }  // dW2 = dz2 (x) h1
+    if (e < OFF_W3) return a[2 * HID + (e - OFF_B2)];                      // db2 = dz2
+    if (e < OFF_B3) return a[4 * HID] * a[3 * HID + (e - OFF_W3)];         // dw3 = g_f h2
+    return a[4 * HID];                                                     // db3 = g_f
+}
+
+// block b sums the contributions of nonzeros [b*C, (b+1)*C) in order; tiles of 16
+// nonzeros are staged in LDS
+constexpr int TILE = 16;
+__global__ void __launch_bounds__(BLOCK) k_grad_partial(int64_t nnz, const float* __restrict__ feat,
+                                                        const float* __restrict__ act, float* __restrict__ part) {
+    __shared__ float sx[TILE][NF];
+    __shared__ float sa[TILE][ACT];
+    constexpr int PER = (NPARAM + BLOCK - 1) / BLOCK;   // 20 entries per thread
+    float acc[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc[u] = 0.0f;
+    const int64_t C = (nnz + gridDim.x - 1) / gridDim.x;
+    const int64_t k0 = (int64_t)blockIdx.x * C, k1 = min(nnz, k0 + C);
+    for (int64_t t0 = k0; t0 < k1; t0 += TILE) {
+        const int cnt = (int)min((int64_t)TILE, k1 - t0);
+        for (int z = threadIdx.x; z < TILE * NF; z += blockDim.x) {
+            const int r = z / NF, c = z % NF;
+            sx[r][c] = r < cnt ? feat[(t0 + r) * NF + c] : 0.0f;
+        }
+        for (int z = threadIdx.x; z < TILE * ACT; z += blockDim.x) {
+            const int r = z / ACT, c = z % ACT;
+            sa[r][c] = r < cnt ? act[(t0 + r) * ACT + c] : 0.0f;
+        }
+        __syncthreads();
+        for (int r = 0; r < cnt; ++r) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = threadIdx.x + u * BLOCK;
+                if (e < NPARAM) {
+                    float v = grad_term(e, sx[r], sa[r]);
+                    acc[u] = acc[u] + v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * BLOCK;
+        if (e < NPARAM) part[(size_t)blockIdx.x * NPARAM + e] = acc[u];
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_grad_sum(int nb, const float* __restrict__ part, float* __restrict__ grad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NPARAM) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; ++b) s = s + part[(size_t)b * NPARAM + e];
+    grad[e] = s;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                                const float* __restrict__ g, int t, float lr, float b1, float b2,
+                                                float eps) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NPARAM) return;
+    const float ge = g[e];
+    const float me = b1 * m[e] + (1.0f - b1) * ge;
+    const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
+    m[e] = me;
+    v[e] = ve;
+    const float mh = me / (1.0f - powf(b1, (float)t));
+    const float vh = ve / (1.0f - powf(b2, (float)t));
+    p[e] = p[e] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// ------------------------------------------------------------------ bf16 MFMA inference
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest even
+    unsigned int u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (unsigned short)((u >> 16) | 0x40);
+    u = u + 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+// One wave handles tiles of 16 nonzeros.  v_mfma_f32_16x16x16bf16: lane l holds
+// A[l%16][4(l/16)+j], B[4(l/16)+j][l%16] (j = 0..3) and C[4(l/16)+j][l%16].
+__global__ void __launch_bounds__(256) k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
+                                                    const float* __restrict__ params, const int* __restrict__ rowidx,
+                                                    const double* __restrict__ diag, float* __restrict__ mout) {
+    __shared__ unsigned short sh[4][16][HID + 4];      // per wave: h1 tile (bf16), row padded
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    // B operands in registers: W1 (4 n-tiles, K = 16 with 12 used) and W2 (4 n-tiles x 4 k-steps)
+    bf16x4 bw1[4], bw2[4][4];
+    for (int nt = 0; nt < 4; ++nt) {
+        for (int j = 0; j < 4; ++j) {
+            const int kk = 4 * lk + j, col = nt * 16 + lr;
+            bw1[nt][j] = (short)(kk < NF ? f2bf(params[OFF_W1 + col * NF + kk]) : 0);
+        }
+        for (int ks = 0; ks < 4; ++ks)
+            for (int j = 0; j < 4; ++j) {
+                const int kk = 16 * ks + 4 * lk + j, col = nt * 16 + lr;
+                bw2[nt][ks][j] = (short)f2bf(params[OFF_W2 + col * HID + kk]);
+            }
+    }
+    float b1v[4], b2v[4], w3v[4];
+    for (int nt = 0; nt < 4; ++nt) {
+        b1v[nt] = params[OFF_B1 + nt * 16 + lr];
+        b2v[nt] = params[OFF_B2 + nt * 16 + lr];
+        w3v[nt] = bf2f(f2bf(params[OFF_W3 + nt * 16 + lr]));
+    }
+    const float b3 = params[OFF_B3];
+    const int64_t ntiles = (nnz + 15) / 16;
+    const int64_t wstride = (int64_t)gridDim.x * 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wid; tile < ntiles; tile += wstride) {
+        const int64_t base = tile * 16;
+        // layer 1: A = features of rows base..base+15 (bf16), K padded to 16
+        bf16x4 ax;
+        {
+            const int64_t q = base + lr;
+            for (int j = 0; j < 4; ++j) {
+                const int kk = 4 * lk + j;
+                float v = (q < nnz && kk < NF) ? feat[q * NF + kk] : 0.0f;
+                ax[j] = (short)f2bf(v);
+            }
+        }
+        for (int nt = 0; nt < 4; ++nt) {
+            floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax, bw1[nt], c, 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+                float z = c[j] + b1v[nt];
+                sh[wid][4 * lk + j][nt * 16 + lr] = f2bf(gelu(z));   // h1[row][col]
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        // layer 2: A = h1 (16 x 64) in 4 k-steps
+        floatx4 acc2[4];
+        for (int nt = 0; nt < 4; ++nt) acc2[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int ks = 0; ks < 4; ++ks) {
+            bf16x4 ah;
+            for (int j = 0; j < 4; ++j) ah[j] = (short)sh[wid][lr][16 * ks + 4 * lk + j];
+            for (int nt = 0; nt < 4; ++nt)
+                acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bw2[nt][ks], acc2[nt], 0, 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // layer 3: f[row] = sum_col bf16(gelu(z2[row][col])) * w3[col] + b3
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int nt = 0; nt < 4; ++nt)
+            for (int j = 0; j < 4; ++j) {
+                float h2 = bf2f(f2bf(gelu(acc2[nt][j] + b2v[nt])));
+                float prod = h2 * w3v[nt];
+                part[j] = part[j] + prod;
+            }
+        for (int o = 1; o < 16; o <<= 1)
+            for (int j = 0; j < 4; ++j) part[j] = part[j] + __shfl_xor(part[j], o);
+        if (lr == 0) {
+            for (int j = 0; j < 4; ++j) {
+                const int64_t q = base + 4 * lk + j;
+                if (q < nnz) {
+                    const float f = part[j] + b3;
+                    const float isd = feat[q * NF + 10];
+                    mout[q] = (isd + f) / (float)diag[rowidx[q]];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ workspace
+struct SpaiWs {
+    unsigned long long* maxabs;
+    int* maxlen;
+    double* diag;
+    double* rsum;
+    unsigned long long* cfix;
+    float* maxoff;
+    float* part;      // loss partials [ceil(n/BLOCK)]
+    float* gpart;     // gradient partials [GRAD_BLOCKS][NPARAM]
+    float* R;         // n x k
+    float* act;       // nnz x ACT
+    size_t need;
+};
+
+inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+SpaiWs carve(void* ws, int32_t n, int64_t nnz, int32_t k) {
+    SpaiWs w{};
+    char* b = (char*)ws;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char* p = b ? b + o : nullptr; o += al(bytes); return p; };
+    w.maxabs = (unsigned long long*)take(8);
+    w.maxlen = (int*)take(8);
+    w.diag = (double*)take(sizeof(double) * (size_t)std::max(n, 1));
+    w.rsum = (double*)take(sizeof(double) * (size_t)std::max(n, 1));
+    w.cfix = (unsigned long long*)take(8 * (size_t)std::max(n, 1));
+    w.maxoff = (float*)take(4 * (size_t)std::max(n, 1));
+    w.part = (float*)take(4 * (size_t)((n + BLOCK - 1) / BLOCK + 1));
+    w.gpart = (float*)take(4 * (size_t)GRAD_BLOCKS * NPARAM);
+    w.R = (float*)take(4 * (size_t)std::max(n, 1) * std::max(k, 1));
+    w.act = (float*)take(4 * (size_t)std::max<int64_t>(nnz, 1) * ACT);
+    w.need = o;
+    return w;
+}
+
+bool csr_f64_ok(const pbcg_csr* A) {
+    return A && A->n > 0 && A->nnz > 0 && A->nnz < (int64_t(1) << 31) && A->row_ptr && A->col_idx && A->val &&
+           A->val_type == PBCG_F64;
+}
+
+int grid_for(int64_t items) { return (int)std::max<int64_t>(1, std::min<int64_t>((items + BLOCK - 1) / BLOCK, 8192)); }
+
+}  // namespace
+
+extern "C" {
+
+int spai_param_count(void) { return NPARAM; }
+
+size_t spai_workspace_bytes(int32_t n, int64_t nnz, int32_t k) { return carve(nullptr, n, nnz, k).need + 256; }
+
+int spai_features(const pbcg_csr* A, float* feat, int32_t* rowidx, double* diag, void* ws, size_t ws_bytes,
+                  void* stream) {
+    if (!csr_f64_ok(A) || !feat || !rowidx || !diag) return PBCG_ERR_INVALID;
+    if (!ws || ws_bytes < spai_workspace_bytes(A->n, A->nnz, 1) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    SpaiWs w = carve(ws, A->n, A->nnz, 1);
+    k_zero64<<<1, 64, 0, s>>>(w.maxabs, 1);
+    k_zero64<<<1, 64, 0, s>>>((unsigned long long*)w.maxlen, 1);
+    k_zero64<<<grid_for(A->n), BLOCK, 0, s>>>(w.cfix, A->n);
+    const double* val = (const double*)A->val;
+    k_maxabs<<<grid_for(A->nnz), BLOCK, 0, s>>>(A->nnz, val, w.maxabs);
+    Stats st{diag, w.rsum, w.cfix, w.maxoff, w.maxlen, rowidx};
+    k_row_stats<<<(A->n + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(A->n, A->row_ptr, A->col_idx, val, w.maxabs, st);
+    k_features<<<grid_for(A->nnz), BLOCK, 0, s>>>(A->n, A->nnz, A->row_ptr, A->col_idx, val, st, w.maxabs, feat);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int spai_forward(int64_t nnz, const float* feat, const float* params, const int32_t* rowidx, const int32_t* col_idx,
+                 const double* diag, float* f_out, float* m_out, void* stream) {
+    if (nnz <= 0 || !feat || !params || !rowidx || !col_idx || !diag || !m_out) return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    k_forward<<<grid_for(nnz), BLOCK, 0, s>>>(nnz, feat, params, rowidx, col_idx, diag, f_out, m_out);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int spai_infer_bf16(int64_t nnz, const float* feat, const float* params, const int32_t* rowidx, const double* diag,
+                    float* m_out, void* stream) {
+    if (nnz <= 0 || !feat || !params || !rowidx || !diag || !m_out) return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t tiles = (nnz + 15) / 16;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
+    k_infer_bf16<<<grid, 256, 0, s>>>(nnz, feat, params, rowidx, diag, m_out);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int spai_probe_product(const pbcg_csr* A, const float* V, int32_t k, float* U, void* stream) {
+    if (!csr_f64_ok(A) || !V || !U || k < 1) return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    k_probe_product<<<(A->n + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(A->n, k, A->row_ptr, A->col_idx,
+                                                                  (const double*)A->val, V, U);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int spai_loss_grad(const pbcg_csr* A, const float* feat, const int32_t* rowidx, const double* diag,
+                   const float* params, const float* V, const float* U, int32_t k, float* m_tmp, float* loss,
+                   float* grad, void* ws, size_t ws_bytes, void* stream) {
+    if (!csr_f64_ok(A) || !feat || !rowidx || !diag || !params || !V || !U || k < 1 || !m_tmp || !loss || !grad)
+        return PBCG_ERR_INVALID;
+    if (!ws || ws_bytes < spai_workspace_bytes(A->n, A->nnz, k) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    SpaiWs w = carve(ws, A->n, A->nnz, k);
+    const int n = A->n;
+    const int64_t nnz = A->nnz;
+    const float scale_loss = 1.0f / ((float)k * (float)n);
+    const float scale_grad = 2.0f / ((float)k * (float)n);
+    k_forward<<<grid_for(nnz), BLOCK, 0, s>>>(nnz, feat, params, rowidx, A->col_idx, diag, nullptr, m_tmp);
+    const int nb = (n + BLOCK - 1) / BLOCK;
+    k_residual<<<nb, BLOCK, 0, s>>>(n, k, A->row_ptr, A->col_idx, m_tmp, U, V, w.R, w.part);
+    k_loss<<<1, 64, 0, s>>>(nb, w.part, scale_loss, loss);
+    k_backward<<<grid_for(nnz), BLOCK, 0, s>>>(n, nnz, k, feat, params, rowidx, A->col_idx, diag, w.R, U,
+                                                scale_grad, w.act);
+    k_grad_partial<<<GRAD_BLOCKS, BLOCK, 0, s>>>(nnz, feat, w.act, w.gpart);
+    k_grad_sum<<<(NPARAM + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(GRAD_BLOCKS, w.gpart, grad);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int spai_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr, float b1, float b2,
+              float eps, void* stream) {
+    if (!params || !m || !v || !grad || t < 1) return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    k_adam<<<(NPARAM + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(params, m, v, grad, t, lr, b1, b2, eps);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+}  // extern "C"

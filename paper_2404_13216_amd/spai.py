@@ -1,0 +1,140 @@
+"""Learned sparse approximate inverse: binding of the spai_* C-ABI calls plus the host
+training loop (argument marshalling and loop control only; every arithmetic step runs
+in the HIP kernels of libpbicgstab.so).
+
+m_ij = ([i == j] + f(phi_ij)) / a_ii on A's pattern; f is an MLP 12 -> 64 -> 64 -> 1
+(GELU).  Training minimises ||M A V - V||_F^2 / (k n) over probe blocks V built from
+Rademacher columns and normalised residuals of plain p-BiCGStab runs on the training
+matrix; inference runs in bf16 on the matrix cores and the result is applied as a right
+preconditioner (opts.M) with the unpreconditioned solver as fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import CSR, Solver, _check, _ptr, _stream, _workspace, lib, solve
+
+NPARAM = 5057
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class SpaiMatrix:
+    """A (FP64 CSR on the device) with its features, row indices and diagonal."""
+
+    def __init__(self, A: CSR, k_max: int = 8):
+        torch = _torch()
+        dev = A.val.device
+        self.A = A
+        self.feat = torch.empty(A.nnz * 12, dtype=torch.float32, device=dev)
+        self.rowidx = torch.empty(A.nnz, dtype=torch.int32, device=dev)
+        self.diag = torch.empty(A.n, dtype=torch.float64, device=dev)
+        self.ws = _workspace(lib().spai_workspace_bytes(A.n, A.nnz, k_max), dev)
+        self.k_max = k_max
+        _check(lib().spai_features(A.c, _ptr(self.feat), _ptr(self.rowidx), _ptr(self.diag), _ptr(self.ws),
+                                   self.ws.numel(), _stream()), "spai_features")
+
+    def m_fp32(self, params, f_out=None):
+        torch = _torch()
+        m = torch.empty(self.A.nnz, dtype=torch.float32, device=params.device)
+        _check(lib().spai_forward(self.A.nnz, _ptr(self.feat), _ptr(params), _ptr(self.rowidx), _ptr(self.A.col_idx),
+                                  _ptr(self.diag), _ptr(f_out), _ptr(m), _stream()), "spai_forward")
+        return m
+
+    def m_bf16(self, params):
+        torch = _torch()
+        m = torch.empty(self.A.nnz, dtype=torch.float32, device=params.device)
+        _check(lib().spai_infer_bf16(self.A.nnz, _ptr(self.feat), _ptr(params), _ptr(self.rowidx), _ptr(self.diag),
+                                     _ptr(m), _stream()), "spai_infer_bf16")
+        return m
+
+    def preconditioner(self, params, bf16: bool = True) -> CSR:
+        m = self.m_bf16(params) if bf16 else self.m_fp32(params)
+        return self.A.with_values(m)
+
+    def probe_product(self, V):
+        torch = _torch()
+        k = V.shape[1]
+        Vc = V.t().contiguous()  # column-major n x k
+        U = torch.empty_like(Vc)
+        _check(lib().spai_probe_product(self.A.c, _ptr(Vc), k, _ptr(U), _stream()), "spai_probe_product")
+        return Vc, U
+
+    def loss_grad(self, params, Vc, U, k):
+        torch = _torch()
+        dev = params.device
+        m = torch.empty(self.A.nnz, dtype=torch.float32, device=dev)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        grad = torch.empty(NPARAM, dtype=torch.float32, device=dev)
+        _check(lib().spai_loss_grad(self.A.c, _ptr(self.feat), _ptr(self.rowidx), _ptr(self.diag), _ptr(params),
+                                    _ptr(Vc), _ptr(U), k, _ptr(m), _ptr(loss), _ptr(grad), _ptr(self.ws),
+                                    self.ws.numel(), _stream()), "spai_loss_grad")
+        return loss, grad
+
+
+def adam(params, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    _check(lib().spai_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(t), float(lr), float(b1), float(b2),
+                           float(eps), _stream()), "spai_adam")
+
+
+def init_params(seed: int, device="cuda"):
+    """Xavier-uniform hidden layers, zero last layer: the untrained net is Jacobi.
+    (The seeded draw is input generation; it matches oracle.spai.init_params.)"""
+    torch = _torch()
+    import math
+    rng = np.random.default_rng(seed)
+    th = np.zeros(NPARAM)
+    th[:768] = (rng.uniform(-1, 1, (64, 12)) * math.sqrt(6.0 / 76)).ravel()
+    th[832:832 + 4096] = (rng.uniform(-1, 1, (64, 64)) * math.sqrt(6.0 / 128)).ravel()
+    return torch.from_numpy(th.astype(np.float32)).to(device)
+
+
+def probe_block(A: CSR, b, seed: int, k_rad=4, steps=(1, 4, 16, 64)):
+    """V = [Rademacher columns | r_i / ||r_i|| of plain p-BiCGStab at the given iterations]
+    as an n x k torch tensor (float32).  Residuals come from the GPU solver (r_out)."""
+    torch = _torch()
+    from synthgen import rademacher
+    dev = A.val.device
+    cols = [torch.from_numpy(rademacher(A.n, k_rad, seed)).to(dev)]
+    r = torch.empty(A.n, dtype=torch.float64, device=dev)
+    for s in steps:
+        sv = Solver(A, tol=0.0, max_iter=int(s))
+        sv.solve(b, None, r_out=r)
+        cols.append((r / torch.linalg.vector_norm(r)).unsqueeze(1).clone())
+    return torch.cat(cols, dim=1).to(torch.float32)
+
+
+def train(problems, epochs=30, lr=1e-3, seed=0, device="cuda", log=None):
+    """Adam over the training matrices (one step per matrix per epoch, fixed order).
+
+    `problems`: list of synthgen.Problem.  Returns (params, loss history)."""
+    torch = _torch()
+    params = init_params(seed, device)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    data = []
+    for p in problems:
+        A = CSR.from_host(p.A, device)
+        sm = SpaiMatrix(A)
+        b = torch.from_numpy(p.b).to(device)
+        V = probe_block(A, b, seed=1000 + int(p.meta.get("seed", 0)))
+        Vc, U = sm.probe_product(V)
+        data.append((sm, Vc, U, V.shape[1]))
+    hist = []
+    t = 0
+    for ep in range(epochs):
+        tot = 0.0
+        for sm, Vc, U, k in data:
+            t += 1
+            loss, grad = sm.loss_grad(params, Vc, U, k)
+            adam(params, m, v, grad, t, lr=lr)
+            tot += float(loss.item())
+        hist.append(tot / len(data))
+        if log:
+            log(f"epoch {ep}: mean loss {hist[-1]:.5e}")
+    return params, hist

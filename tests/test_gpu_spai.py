@@ -1,0 +1,117 @@
+"""Learned SPAI kernels vs the float64 oracle (features, FP32 MLP forward, loss and
+gradient, Adam, bf16 MFMA inference) and the gain of the trained preconditioner."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2404_13216_amd as pk
+import synthgen as g
+from oracle import spai as ospai
+from paper_2404_13216_amd import spai
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mat():
+    p = g.problem("spai_eval_128", scale=14)
+    return p
+
+
+def rand_params(seed, scale=0.05):
+    th = ospai.init_params(seed)
+    th[4992:] = np.random.default_rng(seed + 1).standard_normal(65) * scale   # non-zero last layer
+    return th
+
+
+def test_features(mat):
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    got = sm.feat.view(-1, 12).cpu().numpy().astype(np.float64)
+    ref = ospai.features(mat.A)
+    err = np.abs(got - ref)
+    assert np.all(err <= 1e-6 * np.abs(ref) + 1e-7), np.max(err / (np.abs(ref) + 1e-7))
+    assert np.array_equal(sm.rowidx.cpu().numpy(), np.repeat(np.arange(mat.A.n), np.diff(mat.A.row_ptr)))
+    assert np.array_equal(sm.diag.cpu().numpy(), mat.A.diag())
+
+
+def test_untrained_net_is_jacobi(mat):
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    th = torch.from_numpy(ospai.init_params(0).astype(np.float32)).cuda()
+    rows = np.repeat(np.arange(mat.A.n), np.diff(mat.A.row_ptr))
+    jac = np.where(rows == mat.A.col_idx, 1.0 / mat.A.diag()[rows], 0.0)
+    for m in (sm.m_fp32(th), sm.m_bf16(th)):
+        m = m.cpu().numpy().astype(np.float64)
+        assert np.allclose(m, jac, rtol=2e-7, atol=0)
+
+
+def test_forward_fp32(mat):
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    th = rand_params(3)
+    m = sm.m_fp32(torch.from_numpy(th.astype(np.float32)).cuda()).cpu().numpy()
+    ref = ospai.m_values(mat.A, th.astype(np.float32).astype(np.float64))
+    rows = np.repeat(np.arange(mat.A.n), np.diff(mat.A.row_ptr))
+    scale = 1.0 / np.abs(mat.A.diag()[rows])
+    assert np.max(np.abs(m - ref) / scale) <= 1e-5
+
+
+def test_bf16_inference_vs_emulation(mat):
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    th = rand_params(4, scale=0.2).astype(np.float32).astype(np.float64)
+    m = sm.m_bf16(torch.from_numpy(th.astype(np.float32)).cuda()).cpu().numpy()
+    ref = ospai.infer_bf16(mat.A, th)
+    rows = np.repeat(np.arange(mat.A.n), np.diff(mat.A.row_ptr))
+    inv = 1.0 / np.abs(mat.A.diag()[rows])
+    assert np.all(np.abs(m - ref) <= 2.0 ** -7 * (np.abs(ref) + inv)), np.max(np.abs(m - ref) / (np.abs(ref) + inv))
+
+
+def test_loss_grad_and_adam_step(mat):
+    A = mat.A
+    sm = spai.SpaiMatrix(pk.CSR.from_host(A))
+    rng = np.random.default_rng(5)
+    V = np.concatenate([g.rademacher(A.n, 4, 9), rng.standard_normal((A.n, 4))], axis=1).astype(np.float32)
+    th = rand_params(6).astype(np.float32)
+    Vd = torch.from_numpy(V).cuda()
+    Vc, U = sm.probe_product(Vd)
+    p = torch.from_numpy(th).cuda()
+    loss, grad = sm.loss_grad(p, Vc, U, 8)
+    L, gref = ospai.loss_and_grad(A, th.astype(np.float64), V.astype(np.float64))
+    gg = grad.cpu().numpy().astype(np.float64)
+    assert abs(loss.item() - L) <= 1e-4 * L
+    assert np.linalg.norm(gg - gref) <= 1e-4 * np.linalg.norm(gref)
+    # one Adam step
+    mom = torch.zeros_like(p)
+    vel = torch.zeros_like(p)
+    spai.adam(p, mom, vel, grad, 1, lr=1e-3)
+    tref, _, _ = ospai.adam_step(th.astype(np.float64), gg, np.zeros(5057), np.zeros(5057), 1, lr=1e-3)
+    assert np.allclose(p.cpu().numpy(), tref, rtol=1e-6, atol=1e-9)
+
+
+def test_gradient_deterministic(mat):
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    V = torch.from_numpy(g.rademacher(mat.A.n, 8, 1).astype(np.float32)).cuda()
+    Vc, U = sm.probe_product(V)
+    p = torch.from_numpy(rand_params(7).astype(np.float32)).cuda()
+    g1 = sm.loss_grad(p, Vc, U, 8)[1].cpu().numpy()
+    g2 = sm.loss_grad(p, Vc, U, 8)[1].cpu().numpy()
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+
+
+def test_trained_preconditioner_gains(capsys):
+    """Train on small seeded matrices, evaluate on a held-out one: fewer iterations than
+    the unpreconditioned solver (and report Jacobi)."""
+    train = [g.training_problem(s, N=(18 if g.training_params(s)["dim"] == 3 else 64)) for s in range(100, 108)]
+    params, hist = spai.train(train, epochs=25, lr=3e-3, seed=0)
+    ev = g.problem("spai_eval_128", scale=24)
+    A = pk.CSR.from_host(ev.A)
+    b = to_dev(ev.b)
+    sm = spai.SpaiMatrix(A)
+    _, plain = pk.solve(A, b, tol=1e-10)
+    _, jac = pk.solve(A, b, tol=1e-10, M=sm.preconditioner(spai.init_params(0)))
+    _, learned = pk.solve(A, b, tol=1e-10, M=sm.preconditioner(params), fallback=1)
+    with capsys.disabled():
+        print(f"\n  loss {hist[0]:.4e} -> {hist[-1]:.4e}; iterations plain {plain['iterations']} "
+              f"jacobi {jac['iterations']} learned {learned['iterations']} (fell back {learned['fell_back']})")
+    assert hist[-1] < hist[0]
+    assert learned["status"] == pk.OK and learned["true_relres"] <= 1e-10
+    assert learned["iterations"] < plain["iterations"]
