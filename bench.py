@@ -8,12 +8,20 @@ relative residual.  One step = one complete FP64 p-BiCGStab solve with exact dot
 products (initialisation, every iteration's phase A / SpMV / phase B / SpMV with their
 fused exact dots, and the true-residual checks), inputs already resident in HBM.
 
-Also reported (outside the timed steps): the BiCGStab comparator and the FP32-inner /
-FP64-refinement form on the same matrix, per-kernel bandwidth of the SpMV kernels,
-phase A / phase B and the standalone exact dot (HIP events on the launch stream), the
-roofline of the dominant kernel, and the CPU oracle timed on this host.
+Also reported (outside the timed steps):
+  * on the same matrix: the BiCGStab comparator and FP32-inner / FP64-refinement at
+    inner tolerance 1e-3 (the library default) and 1e-5;
+  * the learned preconditioner: training on the seeded matrices 100..299 with the GPU
+    kernels, then the held-out 128^3 Peclet-50 matrix solved plain, with Jacobi and with
+    the learned M (setup time stated separately);
+  * plain FP64 vs FP32-IR on the random unsymmetric n = 10^6 matrix and on the 256^3
+    variable-diffusivity matrix;
+  * per-kernel bandwidth of the SpMV kernels, phase A / phase B and the standalone exact
+    dot (HIP events on the launch stream), the roofline of the dominant kernel, and the
+    CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--solve-only]
+                       [--legs learned,rand_1m,cd3d_256_var] [--epochs 30]
 """
 import argparse
 import hashlib
@@ -57,6 +65,120 @@ def time_launches(fn, reps, torch):
     return s.elapsed_time(e) / 1e3 / reps
 
 
+def timed_solve(pk, torch, A, b, reps=1, **opts):
+    """One untimed solve, then `reps` solves from x0 = 0, each bracketed by device
+    synchronisations; returns (median seconds, info of the last solve, x)."""
+    solver = pk.Solver(A, **opts)
+    x = torch.zeros(A.n, dtype=torch.float64, device=b.device)
+    solver.solve(b, x)
+    secs = []
+    for _ in range(reps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info = solver.solve(b, x)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t)
+    return float(np.median(secs)), info, x
+
+
+def rel(torch, a, b):
+    return (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+
+
+def precision_forms(pk, torch, A, b, xs, x64, t64, info64, reps):
+    """Plain FP64 p-BiCGStab (given) beside FP32-inner / FP64-refinement at the default
+    inner tolerance (1e-3) and at 1e-5, each with its error against the FP64 solution."""
+    forms = {"pbicgstab_fp64": {"seconds": t64, "iterations": info64["iterations"],
+                                "true_relres": info64["true_relres"], "status": info64["status"]}}
+    for key, itol in (("fp32_ir", None), ("fp32_ir_inner_1e-5", 1e-5)):
+        kw = {} if itol is None else {"inner_tol": itol}
+        ti, ii, xi = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, prec=pk.PREC_FP32_IR, **kw)
+        forms[key] = {"seconds": ti, "inner_tol": itol or 1e-3, "inner_iterations": ii["iterations"],
+                      "outer": ii["outer_iterations"], "fell_back_to_fp64": ii["fell_back"],
+                      "true_relres": ii["true_relres"], "status": ii["status"],
+                      "rel_diff_vs_fp64_solve": rel(torch, xi, x64), "rel_err_vs_xstar": rel(torch, xi, xs),
+                      "speedup_vs_fp64": t64 / ti}
+    return forms
+
+
+def config_leg(pk, torch, g, dev, name, reps):
+    """Plain FP64 vs FP32-IR on another workload (time to true relative residual 1e-10)."""
+    t0 = time.time()
+    prob = g.problem(name)
+    A = pk.CSR.from_host(prob.A, dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    xs = torch.from_numpy(prob.xstar).to(dev)
+    gen = time.time() - t0
+    t64, i64, x64 = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000)
+    out = {"n": prob.A.n, "nnz": prob.A.nnz, "host_generation_s": gen,
+           "forms": precision_forms(pk, torch, A, b, xs, x64, t64, i64, reps)}
+    out["forms"]["pbicgstab_fp64"]["rel_err_vs_xstar"] = rel(torch, x64, xs)
+    log(f"{name}:", json.dumps(out))
+    return out
+
+
+def learned_leg(pk, torch, g, dev, reps, epochs):
+    """Learned SPAI: train on the seeded matrices 100..299 (2D/3D convection-diffusion,
+    n 16k-262k, Peclet 1-100, kappa = exp(N(0,1))) with the GPU forward / backward / Adam
+    kernels, then solve the held-out 128^3 Peclet-50 matrix (seed 4) unpreconditioned,
+    with Jacobi, and with the learned M (bf16 inference, FP32 values, fallback on)."""
+    from paper_2404_13216_amd import spai
+    t0 = time.time()
+    train = [g.training_problem(s) for s in range(100, 300)]
+    gen = time.time() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, hist = spai.train(train, epochs=epochs, lr=1e-3, seed=0, device=dev)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    train_rows = sum(p.A.n for p in train)
+    train_nnz = sum(p.A.nnz for p in train)
+    del train
+    torch.cuda.empty_cache()
+    ev = g.problem("spai_eval_128")
+    A = pk.CSR.from_host(ev.A, dev)
+    b = torch.from_numpy(ev.b).to(dev)
+    xs = torch.from_numpy(ev.xstar).to(dev)
+    t_plain, ip, xp = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000)
+    t0 = time.perf_counter()
+    J = pk.jacobi(A, torch.float32)
+    torch.cuda.synchronize()
+    t_jset = time.perf_counter() - t0
+    t_jac, ij, xj = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, M=J, fallback=1)
+    # setup: features (one pass over A) and bf16 inference of the 5,057-parameter MLP per nonzero
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sm = spai.SpaiMatrix(A)
+    M = sm.preconditioner(params)
+    torch.cuda.synchronize()
+    t_set = time.perf_counter() - t0
+    t_inf = time_launches(lambda: sm.m_bf16(params), 10, torch)
+    t_ln, il, xl = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, M=M, fallback=1)
+
+    def row(t, info, x, setup=0.0):
+        return {"seconds": t, "seconds_incl_setup": t + setup, "iterations": info["iterations"],
+                "true_relres": info["true_relres"], "status": info["status"], "fell_back": info["fell_back"],
+                "rel_err_vs_xstar": rel(torch, x, xs), "rel_diff_vs_plain": rel(torch, x, xp)}
+    out = {"workload": "spai_eval_128: 3D convection-diffusion 128^3, Peclet 50 (direction from seed 4), "
+                       "kappa = exp(N(0,1)); n=%d nnz=%d" % (ev.A.n, ev.A.nnz),
+           "training": {"matrices": 200, "seeds": "100-299", "rows": train_rows, "nnz": train_nnz,
+                        "epochs": epochs, "steps": epochs * 200, "optimizer": "Adam lr 1e-3",
+                        "host_generation_s": gen, "gpu_training_s": t_train,
+                        "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]},
+           "plain": row(t_plain, ip, xp),
+           "jacobi": row(t_jac, ij, xj, t_jset),
+           "learned": row(t_ln, il, xl, t_set),
+           "learned_setup_s": t_set,
+           "bf16_inference_us": t_inf * 1e6,
+           "bf16_inference_tflops": ev.A.nnz * 2 * (12 * 64 + 64 * 64 + 64) / t_inf / 1e12}
+    out["learned"]["speedup_vs_plain"] = t_plain / t_ln
+    out["learned"]["speedup_vs_plain_incl_setup"] = t_plain / (t_ln + t_set)
+    out["jacobi"]["speedup_vs_plain"] = t_plain / t_jac
+    log("learned:", json.dumps(out))
+    return out
+
+
 def traffic_run(pk, torch, A, n, nnz, dev):
     """Kernels whose HBM bytes rocprofv3 counters measure: a 256 MiB device copy (the
     calibration: 256 MiB read, 256 MiB written), the SpMV, phase A / phase B and the
@@ -96,6 +218,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-only", action="store_true")
     ap.add_argument("--reps", type=int, default=50)
+    ap.add_argument("--legs", default="learned,rand_1m,cd3d_256_var",
+                    help="comma list of extra legs: learned, rand_1m, cd3d_256_var (empty: none)")
+    ap.add_argument("--epochs", type=int, default=30, help="learned-preconditioner training epochs")
     ap.add_argument("--traffic-run", action="store_true",
                     help="launch each measured kernel 10 times (for rocprofv3 --pmc runs) and exit")
     args = ap.parse_args()
@@ -170,33 +295,10 @@ def main():
     if not args.solve_only:
         forms = {}
         # BiCGStab comparator (Algorithm 1)
-        sb = pk.Solver(A, tol=1e-10, max_iter=10000, alg=pk.ALG_BICGSTAB)
-        xb = torch.zeros(n, dtype=torch.float64, device=dev)
-        sb.solve(b, xb)
-        xb.zero_()
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        _, ib = sb.solve(b, xb)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - tb
+        tb, ib, xb = timed_solve(pk, torch, A, b, 1, tol=1e-10, max_iter=10000, alg=pk.ALG_BICGSTAB)
         forms["bicgstab_fp64"] = {"seconds": tb, "iterations": ib["iterations"], "true_relres": ib["true_relres"],
                                   "status": ib["status"]}
-        # FP32 inner / FP64 refinement
-        si = pk.Solver(A, tol=1e-10, max_iter=5000, prec=pk.PREC_FP32_IR, inner_tol=1e-5)
-        xi = torch.zeros(n, dtype=torch.float64, device=dev)
-        si.solve(b, xi)
-        xi.zero_()
-        torch.cuda.synchronize()
-        ti = time.perf_counter()
-        _, ii = si.solve(b, xi)
-        torch.cuda.synchronize()
-        ti = time.perf_counter() - ti
-        forms["fp32_ir"] = {"seconds": ti, "inner_iterations": ii["iterations"], "outer": ii["outer_iterations"],
-                            "true_relres": ii["true_relres"], "status": ii["status"],
-                            "rel_diff_vs_fp64_solve": (torch.linalg.norm(xi - x) / torch.linalg.norm(x)).item(),
-                            "rel_err_vs_xstar": (torch.linalg.norm(xi - xs) / torch.linalg.norm(xs)).item()}
-        forms["pbicgstab_fp64"] = {"seconds": sec, "iterations": info["iterations"],
-                                   "true_relres": info["true_relres"]}
+        forms.update(precision_forms(pk, torch, A, b, xs, x, sec, info, 1))
         out["forms"] = forms
         log("forms:", json.dumps(forms))
 
@@ -289,6 +391,14 @@ def main():
                            "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                            "algorithmic_bytes_per_launch": kern[dom]["bytes"],
                            "avg_launch_us": kern[dom]["us"]}
+        del V, wsp
+        # further legs run after the kernel table, so that they do not disturb its timings
+        legs = [l for l in args.legs.split(",") if l]
+        if "learned" in legs:
+            out["learned_m"] = learned_leg(pk, torch, g, dev, 1, args.epochs)
+        for name in ("rand_1m", "cd3d_256_var"):
+            if name in legs:
+                out.setdefault("other_workloads", {})[name] = config_leg(pk, torch, g, dev, name, 1)
 
     if not args.no_cpu:
         from oracle import ctier

@@ -121,6 +121,12 @@ int csr_spmv_config(const pbcg_csr* A, const double* x, double* y, int32_t kind,
  * rows summed left to right. */
 int csr_spmv_f32(const pbcg_csr* A32, const float* x, float* y, void* stream);
 
+/* Jacobi preconditioner values (the diagonal right preconditioner M = diag(1/a_ii)
+ * used beside the learned one): m_out[i] = 1/a_ii, the FP64 reciprocal rounded once
+ * to m_type (PBCG_F64 or PBCG_F32).  A must hold FP64 values; a row without a stored
+ * diagonal entry gets 1/0 = +inf.  m_out: n device values of m_type. */
+int csr_jacobi(const pbcg_csr* A, void* m_out, int32_t m_type, void* stream);
+
 /* ---------------------------------------------------------------------------------
  * Exact dot product (paper Section 2, ExBLAS paragraph): *out = RN_even(sum x_i y_i)
  * with the sum formed exactly -- bit-identical for every launch shape.  Exact zero

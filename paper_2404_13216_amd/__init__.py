@@ -59,7 +59,7 @@ class PbcgVectors(ctypes.Structure):
 
 
 EXPORTS = [
-    "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "exdot_workspace_bytes", "exdot", "exdot_config",
+    "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "csr_jacobi", "exdot_workspace_bytes", "exdot", "exdot_config",
     "pbcg_phase_workspace_bytes", "pbcg_phase_a", "pbcg_phase_b", "pbicgstab_workspace_bytes",
     "pbicgstab_solve", "pbcg_default_opts", "pbcg_status_string", "pbcg_abi_version",
     "spai_param_count", "spai_workspace_bytes", "spai_features", "spai_forward", "spai_infer_bf16",
@@ -83,6 +83,7 @@ def lib():
         "csr_spmv": (ctypes.c_int, [CP, _P, _P, _P]),
         "csr_spmv_config": (ctypes.c_int, [CP, _P, _P, i32, _P]),
         "csr_spmv_f32": (ctypes.c_int, [CP, _P, _P, _P]),
+        "csr_jacobi": (ctypes.c_int, [CP, _P, i32, _P]),
         "exdot_workspace_bytes": (sz, [i64]),
         "exdot": (ctypes.c_int, [i64, _P, _P, _P, _P, sz, _P]),
         "exdot_config": (ctypes.c_int, [i64, _P, _P, _P, i32, i32, i32, _P, sz, _P]),
@@ -197,6 +198,18 @@ def csr_spmv_f32(A: CSR, x, y=None):
         y = torch.empty(A.n, dtype=torch.float32, device=x.device)
     _check(lib().csr_spmv_f32(A.c, _ptr(x), _ptr(y), _stream()), "csr_spmv_f32")
     return y
+
+
+def jacobi(A: CSR, dtype=None) -> CSR:
+    """Diagonal right preconditioner M = diag(1/a_ii) as a CSR with one entry per row;
+    the values come from csr_jacobi (FP64 reciprocal rounded once to `dtype`)."""
+    torch = _torch()
+    dtype = torch.float64 if dtype is None else dtype
+    dev = A.val.device
+    m = torch.empty(A.n, dtype=dtype, device=dev)
+    _check(lib().csr_jacobi(A.c, _ptr(m), F64 if dtype == torch.float64 else F32, _stream()), "csr_jacobi")
+    idx = torch.arange(A.n + 1, dtype=torch.int32, device=dev)
+    return CSR(idx, idx[:-1].clone(), m, n=A.n)
 
 
 def exdot(x, y, out=None, ws=None):

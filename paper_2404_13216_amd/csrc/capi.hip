@@ -79,7 +79,7 @@ bool csr_ok(const pbcg_csr* A) {
 }
 
 // ---------------------------------------------------------------- launchers
-constexpr int SEQ_WORKERS = 6 * 256;   // persistent SpMV blocks: 6 resident per CU (24 KB LDS each)
+constexpr int SEQ_WORKERS = 8 * 256;   // persistent SpMV blocks: 8 resident per CU (16 KB LDS each)
 
 // kind: PBCG_SPMV_SEQ (rows summed left to right), PBCG_SPMV_VECTOR (L lanes per row
 // from the mean row length, tree order), PBCG_SPMV_WAVE (one wavefront per row).
@@ -152,10 +152,11 @@ void launch_spmv_dot(const pbcg_csr* A, const double* x, Epi epi, xd::Site site,
 
 // Producer only: returns the finalize role, to be run by fin_kernel or by block 0 of
 // the next SpMV.
-template <int D, class Op>
-XFin<D, Op> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
-                                   int grid = 0, int block = DOT_BLOCK, int K = KEXP, int* seen = nullptr) {
+template <int D, int GM = DOT_GMAX, class Op>
+XFin<D, Op, GM> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
+                                       int grid = 0, int block = DOT_BLOCK, int K = KEXP, int* seen = nullptr) {
     if (grid <= 0) grid = dot_grid(n);
+    grid = std::min(grid, GM);
     if constexpr (D == 1) {  // the standalone dot exposes the expansion length
 #define EW_CASE(KK) \
     case KK: ew_dot_kernel<D, KK, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen); break;
@@ -167,7 +168,7 @@ XFin<D, Op> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const int* h
     } else {
         ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen);
     }
-    return XFin<D, Op>{op, site, grid, halt};
+    return XFin<D, Op, GM>{op, site, grid, halt};
 }
 
 template <int D, class Op>
@@ -317,6 +318,24 @@ int pin_init() {
 }  // namespace
 
 // ============================================================================ C-ABI
+// Jacobi values 1/a_ii (FP64 reciprocal, then rounded once to the output type); the
+// diagonal entry is found by binary search in the row's ascending columns.
+template <class MT>
+__global__ void __launch_bounds__(256) jacobi_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const double* __restrict__ val, MT* __restrict__ m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = rp[i], hi = rp[i + 1] - 1;
+    double d = 0.0;
+    while (lo <= hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        const int c = ci[mid];
+        if (c == i) { d = val[mid]; break; }
+        if (c < i) lo = mid + 1; else hi = mid - 1;
+    }
+    m[i] = (MT)(1.0 / d);
+}
+
 extern "C" {
 
 int pbcg_abi_version(void) { return 2; }
@@ -367,6 +386,19 @@ int csr_spmv_f32(const pbcg_csr* A, const float* x, float* y, void* stream) {
         return PBCG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     launch_spmv_t<float, float, float>(A, x, EpiStore<float>{y}, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int csr_jacobi(const pbcg_csr* A, void* m_out, int32_t m_type, void* stream) {
+    if (!csr_ok(A) || A->val_type != PBCG_F64 || (A->n > 0 && !m_out)) return PBCG_ERR_INVALID;
+    if (m_type != PBCG_F64 && m_type != PBCG_F32) return PBCG_ERR_INVALID;
+    if (A->n == 0) return PBCG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int grid = (A->n + 255) / 256;
+    const double* val = (const double*)A->val;
+    if (m_type == PBCG_F64) jacobi_kernel<double><<<grid, 256, 0, s>>>(A->n, A->row_ptr, A->col_idx, val, (double*)m_out);
+    else jacobi_kernel<float><<<grid, 256, 0, s>>>(A->n, A->row_ptr, A->col_idx, val, (float*)m_out);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
@@ -570,10 +602,10 @@ struct Driver {
         const double* scal = &W.st->alpha;
         PhaseA<FinOmega> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
                             FinOmega{W.st, 1}};
-        auto fa = launch_ew_dot_deferred<4>(pa, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
+        auto fa = launch_ew_dot_deferred<4, DOT_GRID_DEFAULT>(pa, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
         op(W.z, W.v, fa, seen);           // v = A z; omega is finalized by its block 0
         PhaseB<FinPhaseB> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
-        auto fb = launch_ew_dot_deferred<3>(pb, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
+        auto fb = launch_ew_dot_deferred<3, DOT_GRID_DEFAULT>(pb, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
         op(W.w, W.t, fb, seen);           // t = A w; beta, alpha finalized by its block 0
     }
 

@@ -69,16 +69,18 @@ __device__ void fdot_reduce(const FSite& site, int G, float* sh /* D*256 */, flo
 // of the next kernel in the stream when that kernel does not consume the results (the
 // SpMV after each p-BiCGStab phase), which hides its latency behind the SpMV.
 constexpr int DOT_GMAX = 1024;
-constexpr int FIN_SMEM = 32 + 4 * xd::NCH * 8 + 16 + 32 + 2 * DOT_GMAX * 4 * 2;
 
 struct NoFin {
     static constexpr int D = 0;
+    static constexpr int SMEM = 0;
     __device__ void run(unsigned char*) {}
 };
 
-template <int D_, class Op>
+// GM: the largest producer grid the role accepts (sizes its LDS)
+template <int D_, class Op, int GM = DOT_GMAX>
 struct XFin {                       // exact dots
     static constexpr int D = D_;
+    static constexpr int SMEM = 32 + 4 * xd::NCH * 8 + 16 + 32 + 2 * GM * 4 * 2;
     Op op;
     xd::Site site;
     int G;
@@ -89,9 +91,9 @@ struct XFin {                       // exact dots
         long long* fin = (long long*)(smem + 32);                 // D*NCH
         uint32_t* fl = (uint32_t*)(smem + 32 + 4 * xd::NCH * 8);  // 4
         int* rng = (int*)(fl + 4);                                // 8
-        short* hlo = (short*)(rng + 8);                           // DOT_GMAX*4
-        short* hhi = hlo + DOT_GMAX * 4;
-        xd::reduce_records<D, DOT_GMAX>(site, G, fin, hlo, hhi, fl, rng, res);
+        short* hlo = (short*)(rng + 8);                           // GM*4
+        short* hhi = hlo + GM * 4;
+        xd::reduce_records<D, GM>(site, G, fin, hlo, hhi, fl, rng, res);
         if (threadIdx.x == 0) op.finalize(res);
     }
 };
@@ -99,6 +101,7 @@ struct XFin {                       // exact dots
 template <int D_, class Op>
 struct FFin {                       // plain FP32 dots
     static constexpr int D = D_;
+    static constexpr int SMEM = (4 + 4 * 256) * 4;
     Op op;
     FSite site;
     int G;
@@ -114,7 +117,7 @@ struct FFin {                       // plain FP32 dots
 
 template <class Fin>
 __global__ void __launch_bounds__(256) fin_kernel(Fin fin) {
-    __shared__ __align__(16) unsigned char smem[FIN_SMEM];
+    __shared__ __align__(16) unsigned char smem[Fin::SMEM];
     fin.run(smem);
 }
 
@@ -161,23 +164,25 @@ spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ c
     if (lane == 0) epi(row, s);
 }
 
-// Row-sequential SpMV engine (persistent, software-pipelined).
+// Row-sequential SpMV engine (persistent, product-staged).
 //
 // Rows are taken in chunks of R = blockDim.x rows, one row per lane, and every row is
-// summed left to right in storage order.  The chunk's val/col range is loaded with
-// unit-stride (coalesced) reads into registers, parked in LDS, and each lane then walks
-// its row from LDS while gathering x.  The loads of the block's next chunk are issued
-// before the current chunk is summed, so HBM traffic overlaps the gather/sum phase.
+// summed left to right in storage order.  The chunk's nonzeros are swept in windows of
+// CAP entries: all lanes read val/col of the window with unit-stride (coalesced) loads,
+// gather x, and park the rounded products a_k * x_col(k) in LDS; after a barrier each
+// lane adds the products of its own row that fall in the window, carrying its running
+// sum into the next window.  The additions therefore happen in storage order whatever
+// the row lengths (a row longer than CAP simply spans several windows), and the gathers
+// of a whole window are in flight together instead of one per lane and step.
 // Chunks are dealt to the worker blocks of each XCD from a contiguous range of rows
 // (hardware block b runs on XCD b % 8), so the x planes a stencil row touches are
-// shared in that XCD's L2.  A chunk whose nnz exceed the staging capacity falls back
-// to direct reads (same order, same bits).
-template <int PER, class VT, class XT, class AT, class Body>
-__device__ __forceinline__ void seq_pipe(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                         const VT* __restrict__ val, const XT* __restrict__ x,
-                                         int bfirst, int G, VT* sval, int32_t* scol, Body& body) {
-    const int R = blockDim.x;
-    const int CAP = R * PER;
+// shared in that XCD's L2.
+template <int CAP, class VT, class XT, class AT, class Body>
+__device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                          const VT* __restrict__ val, const XT* __restrict__ x,
+                                          int bfirst, int G, AT* sprod, Body& body) {
+    constexpr int R = 256;            // blockDim.x
+    constexpr int PER = CAP / R;
     const int nchunk = (n + R - 1) / R;
     const int hb = blockIdx.x;
     int cbeg, cend, gper, bi;
@@ -195,58 +200,39 @@ __device__ __forceinline__ void seq_pipe(int n, const int32_t* __restrict__ rp, 
         cend = nchunk;
     }
     const int t = threadIdx.x;
-    VT pv[PER];
-    int32_t pc[PER];
-    int a0 = 0, a1 = 0, ra = 0, rb = 0;
-    auto fetch = [&](int cc) {
-        const int r0 = cc * R, r1 = min(r0 + R, n);
-        a0 = rp[r0];
-        a1 = rp[r1];
-        const int row = r0 + t;
-        ra = 0;
-        rb = 0;
-        if (row < r1) { ra = rp[row]; rb = rp[row + 1]; }
-        if (a1 - a0 <= CAP) {
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int k = a0 + t + j * R;
-                if (k < a1) { pv[j] = val[k]; pc[j] = ci[k]; }
-            }
-        }
-    };
-    int c = cbeg + bi;
-    if (c < cend) fetch(c);
-    for (; c < cend; c += gper) {
+    for (int c = cbeg + bi; c < cend; c += gper) {
         const int r0 = c * R, r1 = min(r0 + R, n), row = r0 + t;
-        const int A0 = a0, A1 = a1, RA = ra, RB = rb;
-        const bool staged = A1 - A0 <= CAP;
-        if (staged) {
+        const int A0 = rp[r0], A1 = rp[r1];
+        int RA = 0, RB = 0;
+        if (row < r1) { RA = rp[row]; RB = rp[row + 1]; }
+        AT s = AT(0);
+        for (int w = A0; w < A1; w += CAP) {
+            const int we = min(w + CAP, A1);
+            VT pv[PER];
+            int32_t pc[PER];
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
-                const int k = A0 + t + j * R;
-                if (k < A1) { sval[k - A0] = pv[j]; scol[k - A0] = pc[j]; }
+                const int k = w + t + j * R;
+                if (k < we) { pv[j] = val[k]; pc[j] = ci[k]; }
             }
-        }
-        __syncthreads();
-        if (c + gper < cend) fetch(c + gper);  // next chunk in flight during the sums
-        AT s = AT(0);
-        if (staged) {
-            for (int k = RA; k < RB; ++k) {
-                AT prod = (AT)sval[k - A0] * (AT)x[scol[k - A0]];
-                s = s + prod;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int k = w + t + j * R;
+                if (k < we) {
+                    AT prod = (AT)pv[j] * (AT)x[pc[j]];
+                    sprod[k - w] = prod;
+                }
             }
-        } else {
-            for (int k = RA; k < RB; ++k) {
-                AT prod = (AT)val[k] * (AT)x[ci[k]];
-                s = s + prod;
-            }
+            __syncthreads();
+            const int ka = max(RA, w), kb = min(RB, we);
+            for (int k = ka; k < kb; ++k) s = s + sprod[k - w];
+            __syncthreads();
         }
         if (row < r1) body(row, s);
-        __syncthreads();
     }
 }
 
-constexpr int SEQ_PER = 8;      // staged entries per lane: 8 x 256 = 2048 per chunk
+constexpr int SEQ_CAP = 2048;   // staged products per window (8 per lane)
 
 template <class Epi>
 struct StoreBody {
@@ -261,8 +247,8 @@ __global__ void __launch_bounds__(256)
 spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                 const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt) {
     if (halt && *halt) return;
-    constexpr int STAGE = 256 * SEQ_PER * (int)(sizeof(VT) + sizeof(int32_t));
-    constexpr int SMEM = (Fin::D > 0 && FIN_SMEM > STAGE) ? FIN_SMEM : STAGE;
+    constexpr int STAGE = SEQ_CAP * (int)sizeof(AT);
+    constexpr int SMEM = Fin::SMEM > STAGE ? Fin::SMEM : STAGE;
     __shared__ __align__(16) unsigned char smem[SMEM];
     int bfirst = 0;
     if constexpr (Fin::D > 0) {
@@ -272,10 +258,8 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
         }
         bfirst = 1;
     }
-    VT* sval = (VT*)smem;
-    int32_t* scol = (int32_t*)(smem + 256 * SEQ_PER * sizeof(VT));
     StoreBody<Epi> body{epi};
-    seq_pipe<SEQ_PER, VT, XT, AT>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst, sval, scol, body);
+    seq_stage<SEQ_CAP, VT, XT, AT>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst, (AT*)smem, body);
 }
 
 // ----------------------------------------------------------------------------- dot sites
@@ -399,7 +383,7 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
                     xd::Site site, const int* halt) {
     if (halt && *halt) return;
     XD_SHARED(D)
-    __shared__ __align__(16) unsigned char smem[256 * SEQ_PER * (sizeof(VT) + sizeof(int32_t))];
+    __shared__ double sprod[SEQ_CAP];
     xd::block_init<D>(sh_acc, sh_flags);
     epi.load();
     double e[D][K];
@@ -408,8 +392,7 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 #pragma unroll
         for (int k = 0; k < K; ++k) e[d][k] = 0.0;
     DotBody<D, K, Epi> body{epi, e, sh_acc, sh_flags};
-    seq_pipe<SEQ_PER, VT, double, double>(n, rp, ci, val, x, 0, (int)gridDim.x, (VT*)smem,
-                                          (int32_t*)(smem + 256 * SEQ_PER * sizeof(VT)), body);
+    seq_stage<SEQ_CAP, VT, double, double>(n, rp, ci, val, x, 0, (int)gridDim.x, sprod, body);
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
 }

@@ -27,14 +27,19 @@ def _torch():
 class SpaiMatrix:
     """A (FP64 CSR on the device) with its features, row indices and diagonal."""
 
-    def __init__(self, A: CSR, k_max: int = 8):
+    def __init__(self, A: CSR, k_max: int = 8, ws=None):
+        """`ws`: optional shared device workspace of at least workspace_bytes(A, k_max)
+        bytes (training shares one across its matrices; calls on one stream only)."""
         torch = _torch()
         dev = A.val.device
         self.A = A
         self.feat = torch.empty(A.nnz * 12, dtype=torch.float32, device=dev)
         self.rowidx = torch.empty(A.nnz, dtype=torch.int32, device=dev)
         self.diag = torch.empty(A.n, dtype=torch.float64, device=dev)
-        self.ws = _workspace(lib().spai_workspace_bytes(A.n, A.nnz, k_max), dev)
+        need = workspace_bytes(A, k_max)
+        if ws is not None and ws.numel() < need:
+            raise ValueError(f"shared workspace too small: {ws.numel()} < {need}")
+        self.ws = ws if ws is not None else _workspace(need, dev)
         self.k_max = k_max
         _check(lib().spai_features(A.c, _ptr(self.feat), _ptr(self.rowidx), _ptr(self.diag), _ptr(self.ws),
                                    self.ws.numel(), _stream()), "spai_features")
@@ -75,6 +80,10 @@ class SpaiMatrix:
                                     _ptr(Vc), _ptr(U), k, _ptr(m), _ptr(loss), _ptr(grad), _ptr(self.ws),
                                     self.ws.numel(), _stream()), "spai_loss_grad")
         return loss, grad
+
+
+def workspace_bytes(A, k_max: int = 8) -> int:
+    return int(lib().spai_workspace_bytes(A.n, A.nnz, k_max))
 
 
 def adam(params, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
@@ -118,9 +127,10 @@ def train(problems, epochs=30, lr=1e-3, seed=0, device="cuda", log=None):
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     data = []
+    ws = _workspace(max(workspace_bytes(p.A) for p in problems), device)
     for p in problems:
         A = CSR.from_host(p.A, device)
-        sm = SpaiMatrix(A)
+        sm = SpaiMatrix(A, ws=ws)
         b = torch.from_numpy(p.b).to(device)
         V = probe_block(A, b, seed=1000 + int(p.meta.get("seed", 0)))
         Vc, U = sm.probe_product(V)

@@ -47,6 +47,23 @@ def test_jacobi_bit_identical(m_dtype):
     assert np.array_equal(bits(x), bits(ref.x))
 
 
+def test_csr_jacobi_values():
+    """csr_jacobi: 1/a_ii in FP64 (bitwise), rounded once to FP32, +inf without a diagonal."""
+    p = g.problem("rand_1m", scale=3000)
+    Ad = pk.CSR.from_host(p.A)
+    inv = 1.0 / p.A.diag()
+    J64 = pk.jacobi(Ad)
+    assert np.array_equal(bits(J64.val.cpu().numpy()), bits(inv))
+    assert np.array_equal(J64.row_ptr.cpu().numpy(), np.arange(p.A.n + 1))
+    assert np.array_equal(J64.col_idx.cpu().numpy(), np.arange(p.A.n))
+    J32 = pk.jacobi(Ad, torch.float32)
+    assert np.array_equal(J32.val.cpu().numpy().view(np.uint32), inv.astype(np.float32).view(np.uint32))
+    # a row without a stored diagonal entry
+    B = g.CSR(3, np.array([0, 2, 3, 4], np.int32), np.array([0, 2, 0, 2], np.int32), np.array([2.0, 1.0, 5.0, -4.0]))
+    jb = pk.jacobi(pk.CSR.from_host(B)).val.cpu().numpy()
+    assert jb[0] == 0.5 and jb[1] == np.inf and jb[2] == -0.25
+
+
 def test_fallback_zero_preconditioner():
     p = g.problem("cd3d_256_var", scale=16)
     M = diag_csr(np.zeros(p.A.n))
