@@ -52,11 +52,33 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+_SLEEP_CYCLES_PER_S = None
+
+
+def hold_stream(torch, seconds):
+    """Enqueue a device-side spin of about `seconds` on the current stream, so that the
+    launches the host enqueues behind it start back to back: event timings then measure
+    device time, not the host's launch latency (a ctypes call costs tens of microseconds,
+    longer than some of the kernels it launches)."""
+    global _SLEEP_CYCLES_PER_S
+    if _SLEEP_CYCLES_PER_S is None:
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(1000)
+        s.record()
+        torch.cuda._sleep(1 << 20)
+        e.record()
+        e.synchronize()
+        _SLEEP_CYCLES_PER_S = (1 << 20) / max(s.elapsed_time(e) / 1e3, 1e-6)
+    torch.cuda._sleep(int(seconds * _SLEEP_CYCLES_PER_S))
+
+
 def time_launches(fn, reps, torch):
-    """Average duration of fn() over `reps` launches, HIP events on the current stream."""
+    """Average duration of fn() over `reps` back-to-back launches (HIP events on the
+    current stream, launches queued behind a device-side hold)."""
     fn()
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    hold_stream(torch, 2e-3 + reps * 1e-4)
     s.record()
     for _ in range(reps):
         fn()
@@ -322,6 +344,7 @@ def main():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)]
         acc = {}
         for it in range(reps + 2):
+            hold_stream(torch, 1e-3)
             ev[0].record()
             for k, (name, fn, nb) in enumerate(seq):
                 fn()

@@ -289,6 +289,15 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
 # FP32 inner p-BiCGStab inside FP64 iterative refinement
 # ---------------------------------------------------------------------------
 
+FDOT_BLOCK = 512   # lanes per group of the FP32 dot's reduction tree
+
+
+def fdot_grid(n: int) -> int:
+    """Groups in the FP32 dot's reduction tree: one per 512 x 8 elements, 1 to 256."""
+    g = -(-int(n) // (FDOT_BLOCK * 8))
+    return max(1, min(g, 256))
+
+
 def dot_f32_seq(a: np.ndarray, b: np.ndarray) -> np.float32:
     """Plain float32 dot, sequential left-to-right accumulation (ufunc.accumulate is a
     strictly sequential scan: s_k = s_{k-1} + p_k, each rounded to float32)."""
@@ -298,74 +307,49 @@ def dot_f32_seq(a: np.ndarray, b: np.ndarray) -> np.float32:
     return np.float32(np.add.accumulate(prod, dtype=np.float32)[-1])
 
 
-def pbicgstab_f32(A32, b32, tol=1e-5, max_iter=5000, dot=None, stall=100) -> tuple[np.ndarray, int, float]:
-    """Algorithm 2 entirely in float32 (values, vectors, SpMV, dots, scalars), x0 = 0.
+def dot_f32_tree(a: np.ndarray, b: np.ndarray) -> np.float32:
+    """Plain float32 dot in a fixed reduction tree -- the dot of the FP32 inner solver.
+    Every product and every addition is rounded to float32; the order is fixed by n
+    alone.  With G = fdot_grid(n) groups of 512 lanes (8 waves of 64), S = 512 G:
 
-    Stops on the recursive residual only: sqrt((r, r)) / ||b|| <= tol, or when it has
-    not set a new minimum for ``stall`` iterations, or on breakdown / non-finite
-    scalars, returning the current iterate.  Returns (x, iterations, rec).
+      1. lane g (0 <= g < S) adds, starting from 0, the products a_i b_i for
+         i = g, g + S, g + 2S, ... in that order;
+      2. in every wave of 64 lanes, six butterfly levels u_j <- u_j + u_(j xor o),
+         o = 32, 16, 8, 4, 2, 1; the wave's value is lane 0's;
+      3. a group's 8 wave values are added, starting from 0, in wave order;
+      4. the G group values v_g (zero-padded to 256) become h_j = 0 + v_j and are
+         folded h_j <- h_j + h_(j+w) for w = 128, 64, ..., 1; the dot is h_0.
     """
     f = np.float32
-    dot = dot or dot_f32_seq
-    n = A32.n
-    x = np.zeros(n, dtype=f)
-    nb = f(np.sqrt(f(dot(b32, b32))))
-    if nb == 0:
-        return x, 0, 0.0
-    r = b32.astype(f).copy()
-    rhat = r.copy()
-    w = _spmv_f32(A32, r)
-    t = _spmv_f32(A32, w)
-    rho = f(dot(rhat, r))
-    rw = f(dot(rhat, w))
-    if rw == 0 or not np.isfinite(rw):
-        return x, 0, 1.0
-    alpha = f(rho / rw)
-    beta = omega = f(0)
-    rec = 1.0
-    best, it_best = math.inf, 0
-    for i in range(max_iter):
-        if i == 0:
-            p, s, z = r.copy(), w.copy(), t.copy()
-        else:
-            p = r + beta * (p - omega * s)
-            s = w + beta * (s - omega * z)
-            z = t + beta * (z - omega * v)
-        q = r - alpha * s
-        yv = w - alpha * z
-        qy = f(dot(q, yv))
-        yy = f(dot(yv, yv))
-        rs = f(dot(rhat, s))
-        rz = f(dot(rhat, z))
-        v = _spmv_f32(A32, z)
-        if yy == 0 or not np.isfinite(yy):
-            if yy == 0:
-                x = x + alpha * p
-            return x, i + 1, 0.0
-        omega = f(qy / yy)
-        if omega == 0 or not np.isfinite(omega):
-            return x, i, rec
-        x = (x + alpha * p) + omega * q
-        r = q - omega * yv
-        w = yv - omega * (t - alpha * v)
-        t = _spmv_f32(A32, w)
-        rho_new = f(dot(rhat, r))
-        rw = f(dot(rhat, w))
-        rr = f(dot(r, r))
-        rec = float(f(np.sqrt(rr)) / nb)
-        if rec <= tol:
-            return x, i + 1, rec
-        if rec < best:
-            best, it_best = rec, i + 1
-        elif stall and (i + 1) - it_best >= stall:
-            return x, i + 1, rec
-        beta = f(f(f(alpha / omega) * rho_new) / rho)
-        den = f(f(rw + f(beta * rs)) - f(f(beta * omega) * rz))
-        if rho_new == 0 or den == 0 or not np.isfinite(den):
-            return x, i + 1, rec
-        alpha = f(rho_new / den)
-        rho = rho_new
-    return x, max_iter, rec
+    a = np.asarray(a, dtype=f)
+    b = np.asarray(b, dtype=f)
+    n = a.size
+    G = fdot_grid(n)
+    S = G * FDOT_BLOCK
+    lane = np.zeros(S, dtype=f)
+    for k0 in range(0, n, S):
+        m = min(S, n - k0)
+        lane[:m] = lane[:m] + a[k0:k0 + m] * b[k0:k0 + m]
+    u = lane.reshape(G * 8, 64)
+    j = np.arange(64)
+    for o in (32, 16, 8, 4, 2, 1):
+        u = u + u[:, j ^ o]
+    wv = u[:, 0].reshape(G, 8)
+    gs = np.zeros(G, dtype=f)
+    for w in range(8):
+        gs = gs + wv[:, w]
+    h = np.zeros(256, dtype=f)
+    h[:G] = f(0.0) + gs
+    w = 128
+    while w:
+        h[:w] = h[:w] + h[w:2 * w]
+        w //= 2
+    return f(h[0])
+
+
+# reasons that end a run of FP32 iterations (bit flags)
+_RU_CHECK, _RU_CONVERGED, _RU_BREAKDOWN, _RU_NONFINITE, _RU_STALL, _RU_MAXIT, _RU_YYZERO = 1, 2, 4, 8, 16, 32, 64
+_RU_RESTART = _RU_BREAKDOWN | _RU_NONFINITE | _RU_STALL | _RU_YYZERO
 
 
 def pbicgstab_fallback(A, b, M, tol=1e-10, max_iter=10000, stall_window=200, dot=None, spmv=None) -> Result:
@@ -388,51 +372,173 @@ def pbicgstab_fallback(A, b, M, tol=1e-10, max_iter=10000, stall_window=200, dot
     return r2
 
 
-def ir_solve(A, b, tol=1e-10, inner_tol=1e-3, max_outer=30, max_inner=5000, dot=None,
-             dot32=None, spmv=None, inner_stall=100, max_fp64=10000) -> Result:
-    """FP64 iterative refinement around an FP32 inner p-BiCGStab.
+def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=None, spmv=None,
+             stall=100, max_fp64=10000, x0=None) -> Result:
+    """FP64 iterative refinement around an FP32 p-BiCGStab with reliable updates.
 
-    outer k:  r = b - A x (FP64 SpMV), nu = sqrt(exdot(r, r));
-              stop if nu / ||b|| <= tol;  r32 = fp32(r / nu);
-              (inner tolerance 1e-3: the FP32 pipelined recurrences do not sustain a
-              recursive residual much below 1e-4 on the workloads here -- the gap between
-              recursive and true residual that the paper studies -- and chasing 1e-5
-              ends in inner iteration caps or outer stagnation)
-              d = p-BiCGStab_fp32(fp32(A), r32, x0 = 0, tol = inner_tol);
-              x = x + nu * fp64(d).
-    When nu_{k+1} > 0.9 nu_k (stagnation) or after max_outer steps, the solve finishes
-    with FP64 p-BiCGStab from the iterate with the smallest outer residual
-    (``fell_back`` = 1).  The inner solve also stops when its recursive residual has
-    not set a new minimum for ``inner_stall`` iterations.  x starts at 0.
+    FP32 part: Algorithm 2 with FP32 matrix values, vectors and scalars, the
+    compensated row-sequential FP32 SpMV (``oracle.spmv.spmv_f32``) and the FP32 tree
+    dot (``dot_f32_tree``); it accumulates a correction d (x0 = 0) to the FP64 iterate.
+    FP64 part, a "reliable update" each time the FP32 iterations stop: x = x + nu d,
+    r = b - A x (row-sequential FP64 SpMV), nu' = sqrt(exdot(r, r)); converged when
+    nu' / ||b|| <= tol.  Otherwise the FP32 state is rebuilt from r / nu' and the same
+    Krylov process continues: p is rescaled by fp32(nu / nu'), and w = A r, t = A w,
+    s = A p, z = A s, v = A z are recomputed in FP32 (the replacement of the paper's
+    residual-replacement variant), rho = (r_hat, r) and
+    alpha = rho / ((r_hat, w) + beta (r_hat, s) - (beta omega)(r_hat, z)) follow with the
+    kept beta and omega.  The FP32 iterations stop after an iteration whose recursive
+    residual sqrt((r, r)) (relative to the last update) is <= inner_tol, or
+    <= fp32(tol ||b|| / nu) (the solve looks converged), or on breakdown, a non-finite
+    scalar, (y, y) = 0 (d = d + alpha p first), no new minimum for ``stall``
+    iterations, or when the total reaches max_iter.  After a breakdown, stall or
+    (y, y) = 0 the process restarts instead (r_hat = r, p = r, s = w, z = t).  An update
+    that does not lower nu below the best so far returns x to the best iterate and
+    restarts; three such in a row, ``max_outer`` updates or max_iter iterations end
+    in FP64 p-BiCGStab from the best iterate (``fell_back`` = 1).
+    ``iterations`` counts FP32 iterations (plus the FP64 finish); ``outer_iterations``
+    counts reliable updates.
     """
     from synthgen import CSR
+    f = np.float32
     spmv = spmv or _spmv
+    dot32 = dot_f32_tree
     n = A.n
     dot = dot or default_dot(n)
     b = np.asarray(b, dtype=np.float64)
-    A32 = CSR(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32))
+    A32 = CSR(A.n, A.row_ptr, A.col_idx, A.val.astype(f))
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     normb = math.sqrt(dot(b, b))
-    x = np.zeros(n)
     if normb == 0.0:
-        return Result(x, OK, 0, 0.0, 0.0)
-    total_inner = 0
-    nu_prev = nu_best = math.inf
-    x_best = x
-    for k in range(max_outer + 1):
-        r = b - spmv(A, x)
-        nu = math.sqrt(dot(r, r))
-        rel = nu / normb
-        if rel <= tol:
-            return Result(x, OK, total_inner, rel, rel, outer_iterations=k)
-        if nu < nu_best:
-            nu_best, x_best = nu, x
-        if nu > 0.9 * nu_prev or k == max_outer:
-            # stagnation or budget: finish in FP64 from the best iterate (true residual judges)
-            fin = pbicgstab(A, b, x0=x_best, tol=tol, max_iter=max_fp64, dot=dot, spmv=spmv)
-            return Result(fin.x, fin.status, total_inner + fin.iterations, fin.true_relres, fin.rec_relres,
-                          fin.true_checks, outer_iterations=k, fell_back=1)
-        nu_prev = nu
-        r32 = (r / nu).astype(np.float32)
-        d, its, _ = pbicgstab_f32(A32, r32, inner_tol, max_inner, dot32, inner_stall)
-        total_inner += its
+        return Result(np.zeros(n), OK, 0, 0.0, 0.0)
+    if not math.isfinite(normb):
+        return Result(x, ERR_NONFINITE, 0, math.nan, math.nan)
+    delta = f(inner_tol)
+
+    def residual(xv):
+        r64 = b - spmv(A, xv)
+        return r64, math.sqrt(dot(r64, r64))
+
+    def finish(xs, its, outer):
+        fin = pbicgstab(A, b, x0=xs, tol=tol, max_iter=max_fp64, dot=dot, spmv=spmv)
+        return Result(fin.x, fin.status, its + fin.iterations, fin.true_relres, fin.rec_relres,
+                      fin.true_checks, outer_iterations=outer, fell_back=1)
+
+    r64, nu = residual(x)
+    if not math.isfinite(nu):
+        return Result(x, ERR_NONFINITE, 0, math.nan, math.nan)
+    if nu / normb <= tol:
+        return Result(x, OK, 0, nu / normb, nu / normb)
+    x_best, nu_best, bad, outer, its = x, nu, 0, 0, 0
+    restart = True
+    sigma = f(1.0)
+    p = s = z = v = None
+    alpha = beta = omega = rho = f(0.0)
+    rec = f(1.0)
+    while True:
+        # rebuild the FP32 state from r / nu
+        lim = f(tol * normb / nu)
+        r = (r64 / nu).astype(f)
+        w = _spmv_f32(A32, r)
+        t = _spmv_f32(A32, w)
+        if not restart:
+            p = p * sigma
+            s = _spmv_f32(A32, p)
+            z = _spmv_f32(A32, s)
+            v = _spmv_f32(A32, z)
+            rho = dot32(rhat, r)
+            rw = dot32(rhat, w)
+            rs = dot32(rhat, s)
+            rz = dot32(rhat, z)
+            den = f(f(rw + f(beta * rs)) - f(f(beta * omega) * rz))
+            if rho == 0 or den == 0 or not np.isfinite(den):
+                restart = True
+            else:
+                alpha = f(rho / den)
+        if restart:
+            rhat = r.copy()
+            rho = dot32(rhat, r)
+            rw = dot32(rhat, w)
+            if rw == 0 or not np.isfinite(rw):
+                return finish(x_best, its, outer)
+            alpha = f(rho / rw)
+            beta = omega = f(0.0)
+        first = restart
+        best, it_best = math.inf, its
+        d = np.zeros(n, dtype=f)
+        reason = 0
+        # FP32 iterations until a stop reason
+        while not reason:
+            if first:
+                p, s, z = r.copy(), w.copy(), t.copy()
+                first = False
+            else:
+                p = r + beta * (p - omega * s)
+                s = w + beta * (s - omega * z)
+                z = t + beta * (z - omega * v)
+            q = r - alpha * s
+            yv = w - alpha * z
+            qy = dot32(q, yv)
+            yy = dot32(yv, yv)
+            rs = dot32(rhat, s)
+            rz = dot32(rhat, z)
+            v = _spmv_f32(A32, z)
+            if yy == 0 or not np.isfinite(yy):
+                if yy == 0:
+                    d = d + alpha * p
+                    its += 1
+                    reason = _RU_YYZERO
+                else:
+                    reason = _RU_NONFINITE
+                break
+            om = f(qy / yy)
+            if om == 0 or not np.isfinite(om):
+                reason = _RU_BREAKDOWN
+                break
+            omega = om
+            d = (d + alpha * p) + omega * q
+            r = q - omega * yv
+            w = yv - omega * (t - alpha * v)
+            t = _spmv_f32(A32, w)
+            rho_new = dot32(rhat, r)
+            rw = dot32(rhat, w)
+            rr = dot32(r, r)
+            its += 1
+            rec = f(np.sqrt(rr))
+            bn = f(f(f(alpha / omega) * rho_new) / rho)
+            den = f(f(rw + f(bn * rs)) - f(f(bn * omega) * rz))
+            if rho_new == 0 or den == 0 or not np.isfinite(den):
+                reason |= _RU_BREAKDOWN
+            else:
+                beta, alpha, rho = bn, f(rho_new / den), rho_new
+            if rec <= lim:
+                reason |= _RU_CONVERGED
+            if rec <= delta:
+                reason |= _RU_CHECK
+            if rec < best:
+                best, it_best = rec, its
+            elif stall > 0 and its - it_best >= stall:
+                reason |= _RU_STALL
+            if its >= max_iter:
+                reason |= _RU_MAXIT
+        # reliable update
         x = x + nu * d.astype(np.float64)
+        r64, nu_new = residual(x)
+        outer += 1
+        if not math.isfinite(nu_new):
+            return finish(x_best, its, outer)
+        if nu_new / normb <= tol:
+            return Result(x, OK, its, nu_new / normb, float(rec) * nu / normb, outer_iterations=outer)
+        restart = bool(reason & _RU_RESTART)
+        if nu_new < nu_best:
+            x_best, nu_best, bad = x, nu_new, 0
+        else:
+            bad += 1
+            restart = True
+            x = x_best
+            r64, nu_new = residual(x)
+        if bad >= 3 or outer >= max_outer or (reason & _RU_MAXIT):
+            return finish(x_best, its, outer)
+        sigma = f(nu / nu_new)
+        nu = nu_new
+
+

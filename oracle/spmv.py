@@ -7,8 +7,9 @@ and row i is summed left to right in storage order,
     s = 0;  for k in row i:  s = s + (a_k * x[col_k])
 
 with the multiply and the add rounded separately (no fused multiply-add).
-The GPU sums rows in a different (tree) order, so SpMV results agree only up to
-the classical bound |y - y_exact| <= gamma_len * sum_k |a_k x_col_k|.
+The GPU's row-sequential kernels use the same order and agree bit for bit; its
+vector and wavefront kernels sum rows as trees, which agree up to the classical bound
+|y - y_exact| <= gamma_len * sum_k |a_k x_col_k|.
 """
 from __future__ import annotations
 
@@ -48,13 +49,62 @@ def spmv_abs(A, x: np.ndarray) -> np.ndarray:
 
 
 def spmv_f32(A32, x32: np.ndarray) -> np.ndarray:
-    """Row-sequential SpMV in float32 arithmetic (values, vector and accumulator)."""
+    """Row-sequential SpMV in float32 with compensated accumulation: algorithm Dot2 of
+    Ogita, Rump and Oishi ("Accurate sum and dot product", SIAM J. Sci. Comput. 2005)
+    applied to every row in storage order.  Starting from s = c = 0, for each entry
+
+        p = fl(a x),  e = a x - p                      (TwoProduct: e is exact)
+        s' = fl(s + p),  b = fl(s' - s),
+        err = fl(fl(s - fl(s' - b)) + fl(p - b))       (TwoSum, Knuth: s + p = s' + err)
+        c = fl(c + fl(err + e)),  s = s'
+
+    and the row's result is fl(s + c).  Every operation is float32; the product error
+    e is taken from the exact float64 product a x (a 48-bit significand) minus p, which
+    is the same value a fused multiply-add fma(a, x, -p) returns.  The result is as
+    accurate as a sum in twice the working precision, rounded once.
+    """
+    f = np.float32
     rp = A32.row_ptr.astype(np.int64)
     lens = np.diff(rp)
-    y = np.zeros(A32.n, dtype=np.float32)
+    s = np.zeros(A32.n, dtype=f)
+    c = np.zeros(A32.n, dtype=f)
     kmax = int(lens.max()) if lens.size else 0
+    x32 = np.asarray(x32, dtype=f)
     for k in range(kmax):
         rows = np.nonzero(lens > k)[0]
         idx = rp[rows] + k
-        y[rows] = y[rows] + A32.val[idx] * x32[A32.col_idx[idx]]
-    return y
+        a = A32.val[idx].astype(f)
+        xv = x32[A32.col_idx[idx]]
+        ax = a.astype(np.float64) * xv.astype(np.float64)
+        pr = ax.astype(f)
+        e = (ax - pr.astype(np.float64)).astype(f)
+        so = s[rows]
+        sn = so + pr
+        bb = sn - so
+        err = (so - (sn - bb)) + (pr - bb)
+        s[rows] = sn
+        c[rows] = c[rows] + (err + e)
+    return s + c
+
+
+def spmv_f32_loops(A32, x32) -> list:
+    """The same Dot2 row sums written as plain loops over numpy float32 scalars, with
+    the product error from Python's exact rational arithmetic (tiny inputs only)."""
+    from fractions import Fraction
+    f = np.float32
+    out = []
+    for i in range(A32.n):
+        s = f(0.0)
+        c = f(0.0)
+        for k in range(int(A32.row_ptr[i]), int(A32.row_ptr[i + 1])):
+            a = f(A32.val[k])
+            xv = f(x32[int(A32.col_idx[k])])
+            p = a * xv
+            e = f(float(Fraction(float(a)) * Fraction(float(xv)) - Fraction(float(p))))
+            sn = s + p
+            bb = sn - s
+            err = (s - (sn - bb)) + (p - bb)
+            s = sn
+            c = c + (err + e)
+        out.append(s + c)
+    return out

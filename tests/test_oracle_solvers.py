@@ -183,14 +183,6 @@ def test_cd2d_64_reaches_true_residual():
     assert np.linalg.norm(r["x"] - p.xstar) <= 1e-7 * np.linalg.norm(p.xstar)
 
 
-def test_ir_oracle_small():
-    p = g.problem("cd2d_64", scale=20)
-    r = solvers.ir_solve(p.A, p.b, tol=1e-10)
-    assert r.status == solvers.OK and r.true_relres <= 1e-10 and r.outer_iterations >= 2
-    ref = solvers.pbicgstab(p.A, p.b, tol=1e-12)
-    assert np.linalg.norm(r.x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
-
-
 def test_right_preconditioned_jacobi_invariance():
     """With a constant diagonal d, Jacobi M = I/d only rescales the Krylov iterates."""
     p = g.problem("cd2d_64", scale=16)
