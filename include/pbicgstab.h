@@ -69,11 +69,12 @@ typedef struct {
 /* Solver options (host struct). */
 typedef struct {
     double tol;                /* stop when the TRUE relative residual ||b-Ax||/||b|| <= tol */
-    int32_t max_iter;          /* iterations (FP64 solve) / inner iterations per outer step  */
+    int32_t max_iter;          /* iterations (FP64 solve) / FP32 iterations in total (IR)    */
     int32_t alg;               /* pbcg_alg                                                    */
     int32_t prec;              /* pbcg_prec                                                   */
-    int32_t max_outer;         /* FP32-IR: outer refinement steps (default 30 if 0)           */
-    double inner_tol;          /* FP32-IR: inner recursive tolerance (default 1e-3 if 0)      */
+    int32_t max_outer;         /* FP32-IR: reliable updates before the FP64 finish (60 if 0)  */
+    double inner_tol;          /* FP32-IR: update threshold -- the FP32 iterations stop when
+                                  their residual dropped by this factor (default 0.1 if 0)   */
     const pbcg_csr* M;         /* right preconditioner on the same n (NULL = none): the
                                   solver runs on A.M and returns x = M y                      */
     int32_t fallback;          /* with M: on breakdown / non-finite / stall restart the
@@ -85,7 +86,7 @@ typedef struct {
     int32_t stall_window;      /* with M + fallback: iterations without halving the recursive
                                   residual that count as a stall (default 200)               */
     int32_t spmv_kind;         /* pbcg_spmv_kind used for every A.v of the solve (default SEQ) */
-    int32_t pad;
+    int32_t trace;             /* nonzero: one line per FP32-IR reliable update on stderr     */
 } pbcg_opts;
 
 /* Result summary (host struct). */
@@ -117,8 +118,11 @@ int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream);
 /* Same with an explicit kernel shape (pbcg_spmv_kind). */
 int csr_spmv_config(const pbcg_csr* A, const double* x, double* y, int32_t kind, void* stream);
 
-/* FP32 y = A x with FP32 values, vectors and accumulation (the inner solver's SpMV),
- * rows summed left to right. */
+/* FP32 y = A x with FP32 values and vectors (the refinement's FP32 operator).  Every
+ * row is accumulated in FP32 in storage order with the compensated algorithm Dot2 of
+ * Ogita, Rump and Oishi (2005): TwoProduct by fused multiply-add, TwoSum (Knuth), the
+ * errors summed into a compensation term; y_i = fl(s + c) is as accurate as a sum in
+ * twice the working precision, rounded once.  y must not alias x. */
 int csr_spmv_f32(const pbcg_csr* A32, const float* x, float* y, void* stream);
 
 /* Jacobi preconditioner values (the diagonal right preconditioner M = diag(1/a_ii)
@@ -168,9 +172,17 @@ int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal,
  * Algorithm 1).  x holds x0 on entry and the returned iterate on exit.  Stopping: the
  * recursive residual sqrt((r,r))/||b|| is checked every iteration; when it is <= tol
  * the true residual ||b - A x||/||b|| is evaluated and the solve stops if it is <= tol.
- * prec = PBCG_PREC_FP32_IR runs an FP32 inner p-BiCGStab (FP32 values, vectors, SpMV
- * and plain FP32 dot products, recursive tolerance inner_tol) inside FP64 iterative
- * refinement whose residual, exact dots and solution update are FP64.
+ * prec = PBCG_PREC_FP32_IR: FP64 iterative refinement around an FP32 p-BiCGStab (FP32
+ * values, vectors and scalars, the compensated FP32 SpMV of csr_spmv_f32, plain FP32
+ * dot products in a fixed reduction tree) with reliable updates.  The FP32 process
+ * accumulates a correction d; when its residual has dropped by inner_tol (or it looks
+ * converged, breaks down or stalls) x = x + nu d, the true residual b - A x and its
+ * exact norm nu are formed in FP64, and the FP32 process continues from r / nu with its
+ * search direction kept (the paper's residual replacement: w, t, s, z, v recomputed)
+ * or, after a breakdown or stall, restarts.  An update that does not lower the true
+ * residual below the best so far (FP32 has reached its accuracy floor, about
+ * u32 cond(A)), max_outer updates or max_iter FP32 iterations end in FP64 p-BiCGStab
+ * from the best iterate (info->fell_back = 1).
  * `info` (host) may be NULL.  Workspace: pbicgstab_workspace_bytes(n, nnz, opts).
  */
 size_t pbicgstab_workspace_bytes(int32_t n, int64_t nnz, const pbcg_opts* opts);

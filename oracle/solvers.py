@@ -373,7 +373,7 @@ def pbicgstab_fallback(A, b, M, tol=1e-10, max_iter=10000, stall_window=200, dot
 
 
 def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=None, spmv=None,
-             stall=100, max_fp64=10000, x0=None) -> Result:
+             stall=100, max_fp64=10000, x0=None, max_bad=1) -> Result:
     """FP64 iterative refinement around an FP32 p-BiCGStab with reliable updates.
 
     FP32 part: Algorithm 2 with FP32 matrix values, vectors and scalars, the
@@ -392,9 +392,11 @@ def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=N
     scalar, (y, y) = 0 (d = d + alpha p first), no new minimum for ``stall``
     iterations, or when the total reaches max_iter.  After a breakdown, stall or
     (y, y) = 0 the process restarts instead (r_hat = r, p = r, s = w, z = t).  An update
-    that does not lower nu below the best so far returns x to the best iterate and
-    restarts; three such in a row, ``max_outer`` updates or max_iter iterations end
-    in FP64 p-BiCGStab from the best iterate (``fell_back`` = 1).
+    that does not lower nu below the best so far means the FP32 process has reached
+    the accuracy its operator allows (about u32 cond(A) relative): after ``max_bad``
+    such updates (default 1) -- or ``max_outer`` updates, or max_iter FP32 iterations
+    -- the solve finishes in FP64 p-BiCGStab from the best iterate (``fell_back`` = 1).
+    (With max_bad > 1, x returns to the best iterate and the FP32 process restarts.)
     ``iterations`` counts FP32 iterations (plus the FP64 finish); ``outer_iterations``
     counts reliable updates.
     """
@@ -536,7 +538,7 @@ def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=N
             restart = True
             x = x_best
             r64, nu_new = residual(x)
-        if bad >= 3 or outer >= max_outer or (reason & _RU_MAXIT):
+        if bad >= max_bad or outer >= max_outer or (reason & _RU_MAXIT):
             return finish(x_best, its, outer)
         sigma = f(nu / nu_new)
         nu = nu_new

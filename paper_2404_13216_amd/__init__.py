@@ -40,7 +40,7 @@ class PbcgOpts(ctypes.Structure):
                 ("M", ctypes.POINTER(PbcgCsr)), ("fallback", ctypes.c_int32),
                 ("history_len", ctypes.c_int32), ("history", _P), ("r_out", _P),
                 ("batch", ctypes.c_int32), ("stall_window", ctypes.c_int32),
-                ("spmv_kind", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("spmv_kind", ctypes.c_int32), ("trace", ctypes.c_int32)]
 
 
 class PbcgInfo(ctypes.Structure):

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 
 #include "../../include/pbicgstab.h"
@@ -19,6 +20,11 @@ constexpr int BLOCK = 256;
 constexpr int DOT_BLOCK = 512;       // fused element-wise kernels with exact dots
 constexpr int DOT_GRID_MAX = 1024;   // records available in a dot site
 constexpr int DOT_GRID_DEFAULT = 256;
+constexpr int IR_INNER_STALL = 100;   // FP32 iterations without a new minimum
+constexpr int IR_MAX_UPDATES = 60;    // reliable updates before the FP64 finish
+constexpr int IR_MAX_BAD = 1;         // updates that did not improve on the best before it
+constexpr double IR_DELTA = 0.1;      // default update threshold (inner_tol)
+constexpr int IR_FP64_FINISH = 10000; // iteration limit of the FP64 finish after stagnation
 constexpr int KEXP = 3;              // expansion terms per lane in the solver kernels
 
 #define HIPCHK(expr)                              \
@@ -116,6 +122,18 @@ void launch_spmv64(const pbcg_csr* A, const double* x, Epi epi, const int* halt,
                    int kind = PBCG_SPMV_SEQ, Fin fin = Fin{}) {
     if (A->val_type == PBCG_F64) launch_spmv_t<double, double, double>(A, x, epi, halt, s, kind, fin);
     else launch_spmv_t<float, double, double>(A, x, epi, halt, s, kind, fin);
+}
+
+// FP32 row-sequential SpMV with Dot2-compensated accumulation (the refinement's FP32
+// operator; `fin` rides on block 0 as in launch_spmv_t)
+template <class Epi, class Fin = NoFin>
+void launch_spmv32c(const pbcg_csr* A, const float* x, Epi epi, const int* halt, hipStream_t s, Fin fin = Fin{}) {
+    const int n = A->n;
+    const int workers = std::min((n + BLOCK - 1) / BLOCK, SEQ_WORKERS);
+    const int grid = workers + (Fin::D > 0 ? 1 : 0);
+    if (grid > 0)
+        spmv_seq_kernel<float, float, float, Epi, Fin, true><<<grid, BLOCK, 0, s>>>(
+            n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt);
 }
 
 template <int D, class VT, class Epi>
@@ -276,6 +294,23 @@ struct FnInitFState {
         *st = z;
     }
 };
+struct FnSetFState {       // a reliable update: new convergence limit, stall window restarts
+    FState* st; float lim;
+    __device__ void operator()() const {
+        st->lim = lim;
+        st->best = __int_as_float(0x7f800000);   // +inf
+        st->it_best = st->iter;
+        st->halt = 0; st->reason = 0; st->halt_seen = 0;
+    }
+};
+struct FnFIterPlus {       // (y, y) = 0: d = d + alpha p completed one more FP32 iteration
+    FState* st;
+    __device__ void operator()() const { st->iter += 1; }
+};
+struct FnScaleF {          // p = p * sigma (FP32)
+    float* p; float sigma;
+    __device__ void operator()(int64_t i) const { p[i] = p[i] * sigma; }
+};
 struct FnResume {          // clear halt flags (host decided to continue)
     State* st;
     __device__ void operator()() const { st->halt = 0; st->reason = 0; st->halt_seen = 0; }
@@ -361,8 +396,8 @@ void pbcg_default_opts(pbcg_opts* o) {
     o->max_iter = 10000;
     o->alg = PBCG_ALG_PBICGSTAB;
     o->prec = PBCG_PREC_FP64;
-    o->max_outer = 30;
-    o->inner_tol = 1e-3;
+    o->max_outer = IR_MAX_UPDATES;
+    o->inner_tol = IR_DELTA;
     o->batch = 16;
     o->stall_window = 200;
 }
@@ -385,7 +420,7 @@ int csr_spmv_f32(const pbcg_csr* A, const float* x, float* y, void* stream) {
     if (!csr_ok(A) || A->val_type != PBCG_F32 || (A->n > 0 && (!x || !y)) || (x == y && A->n > 0))
         return PBCG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    launch_spmv_t<float, float, float>(A, x, EpiStore<float>{y}, nullptr, s);
+    launch_spmv32c(A, x, EpiStore<float>{y}, nullptr, s);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
@@ -516,8 +551,6 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
 
 constexpr int CONTINUE = -100;
 constexpr int STALLED = 4;   // internal status of a stalled preconditioned solve
-constexpr int IR_INNER_STALL = 100;   // inner FP32 solve: iterations without a new best residual
-constexpr int IR_FP64_FINISH = 10000; // iteration limit of the FP64 finish after stagnation
 
 struct Driver {
     const pbcg_csr* A;
@@ -704,47 +737,29 @@ struct Driver {
     }
 
     // FP32 p-BiCGStab (Algorithm 2) on A32 with right-hand side W.r32, x0 = 0 -> W.d32.
-    int run_fp32_inner(int& iters) {
+    // FP32 iterations (phase A, v = A z, phase B, t = A w) until a finalizer sets a stop
+    // reason; returns the final FState in hf.
+    int run_fp32(FState& hf, bool first) {
         const int n = A->n;
         FState* fs = W.fst;
         int* fh = &fs->halt;
         int* fseen = &fs->halt_seen;
         const float* scal = &fs->alpha;
-        const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-3;
-        launch_single(FnInitFState{fs, (float)itol, std::max(o->max_iter, 1), IR_INNER_STALL}, s);
-        launch_ew(FnZeroF{W.d32}, n, nullptr, s);
-        launch_ew(FnCopyF{W.rh32, W.r32}, n, nullptr, s);
-        launch_spmv_t<float, float, float>(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s, kind);
-        launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, nullptr, s, kind);
-        {
-            FDotsOp<3, FFinInit> d{};
-            d.a[0] = W.r32;  d.b[0] = W.r32;
-            d.a[1] = W.rh32; d.b[1] = W.r32;
-            d.a[2] = W.rh32; d.b[2] = W.w32;
-            d.fin = FFinInit{fs};
-            launch_ew_fdot<3>(d, n, W.fsite, nullptr, s);
-        }
-        FState hf{};
-        HIPCHK(hipMemcpyAsync(&hf, fs, sizeof(FState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        iters = 0;
-        if (hf.halt) return 0;
-        bool first = true;
         int polled = 0, batches = 0;
         const long long limit = (long long)std::max(o->max_iter, 1) + 4LL * batch + 64;
         long long enqueued = 0;
         while (true) {
-            if (enqueued > limit) return PBCG_ERR_HIP;
+            if (enqueued > limit) return PBCG_ERR_HIP;   // a stop reason must have come (MAXIT)
             enqueued += batch;
             for (int k = 0; k < batch; ++k) {
                 FPhaseA<FFinOmega> pa{W.r32, W.w32, W.t32, W.v32, W.rh32, W.p32, W.s32, W.z32, W.q32, W.y32,
                                       scal, first ? 1 : 0, FFinOmega{fs}};
                 auto fa = launch_ew_fdot_deferred<4>(pa, n, W.fsite, fh, s, fseen);
-                launch_spmv_t<float, float, float>(&A32, W.z32, EpiStore<float>{W.v32}, fseen, s, kind, fa);
-                FPhaseB<FFinPhaseB> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
-                                       FFinPhaseB{fs}};
+                launch_spmv32c(&A32, W.z32, EpiStore<float>{W.v32}, fseen, s, fa);
+                FPhaseB<FFinRU> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
+                                   FFinRU{fs}};
                 auto fb = launch_ew_fdot_deferred<3>(pb, n, W.fsite, fh, s, fseen);
-                launch_spmv_t<float, float, float>(&A32, W.w32, EpiStore<float>{W.t32}, fseen, s, kind, fb);
+                launch_spmv32c(&A32, W.w32, EpiStore<float>{W.t32}, fseen, s, fb);
                 first = false;
             }
             HIPCHK(hipGetLastError());
@@ -759,20 +774,30 @@ struct Driver {
                 if (g_pin.f[ps].halt) {
                     HIPCHK(hipMemcpyAsync(&hf, fs, sizeof(FState), hipMemcpyDeviceToHost, s));
                     HIPCHK(hipStreamSynchronize(s));
-                    iters = hf.iter;
-                    if (hf.reason & R_YYZERO) {  // (y,y) = 0: x = x + alpha p completes the iteration
-                        launch_ew(FnFAxpyState{W.d32, W.p32, fs}, n, nullptr, s);
-                        iters += 1;
-                    }
                     return 0;
                 }
             }
         }
     }
 
-    // FP64 iterative refinement around the FP32 inner solver.
+    // r = b - A x (row-sequential FP64 SpMV) and nu = sqrt(exdot(r, r)) -> st, h
+    int true_residual_ir(State& h) {
+        EpiResidDot<FinIR> epi{b, W.r, FinIR{W.st}};
+        launch_spmv_dot<1>(A, x, epi, W.site, nullptr, s, kind);
+        return sync_state(&h);
+    }
+
+    // FP64 iterative refinement around FP32 p-BiCGStab with reliable updates: the FP32
+    // Krylov process runs on r / nu and accumulates a correction d; each time it stops
+    // (its residual dropped by inner_tol, it looks converged, a breakdown or a stall),
+    // x = x + nu d, the true residual is formed in FP64 with an exact norm, and the FP32
+    // state is rebuilt from it -- continued (p rescaled; w, t, s, z, v recomputed) or,
+    // after a breakdown or stall, restarted.  An update that does not improve on the
+    // best iterate means FP32 has reached its accuracy floor (about u32 cond(A)): the
+    // solve then finishes in FP64 p-BiCGStab from the best iterate.
     int run_ir(State& h, int& outer, int& inner_total) {
         const int n = A->n;
+        FState* fs = W.fst;
         launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0, 0, nullptr}, s);
         launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
         A32 = *A;
@@ -792,38 +817,101 @@ struct Driver {
             return PBCG_OK;
         }
         if (h.reason & R_NONFINITE) return PBCG_ERR_NONFINITE;
-        const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
-        double nu_prev = INFINITY, nu_best = INFINITY;
-        double* x_best = W.p;   // free during the outer loop
-        for (int k = 0; k <= max_outer; ++k) {
-            EpiResidDot<FinIR> epi{b, W.r, FinIR{W.st}};
-            launch_spmv_dot<1>(A, x, epi, W.site, nullptr, s, kind);
-            if (sync_state(&h)) return PBCG_ERR_HIP;
-            outer = k;
-            const double nu = h.last_dot;
-            if (h.true_rel <= o->tol) return PBCG_OK;
-            if (!std::isfinite(nu)) return PBCG_ERR_NONFINITE;
-            if (nu < nu_best) {
-                nu_best = nu;
-                launch_ew(FnCopy{x_best, x}, n, nullptr, s);
-            }
-            if (nu > 0.9 * nu_prev || k == max_outer) {
-                // stagnation or budget: finish in FP64 from the best iterate
-                launch_ew(FnCopy{x, x_best}, n, nullptr, s);
-                fell_back = 1;
-                max_iter = IR_FP64_FINISH;
-                int st = run_fp64(h);
-                inner_total += h.iter;
-                return st;
-            }
-            nu_prev = nu;
+        const double normb = h.normb;
+        const int max_outer = o->max_outer > 0 ? o->max_outer : IR_MAX_UPDATES;
+        const float delta = (float)(o->inner_tol > 0.0 ? o->inner_tol : IR_DELTA);
+        double* x_best = W.p;   // the FP64 p vector is free during the refinement
+        if (true_residual_ir(h)) return PBCG_ERR_HIP;
+        double nu = h.last_dot;
+        if (!std::isfinite(nu)) return PBCG_ERR_NONFINITE;
+        if (h.true_rel <= o->tol) return PBCG_OK;
+        launch_ew(FnCopy{x_best, x}, n, nullptr, s);
+        double nu_best = nu;
+        int bad = 0;
+        bool restart = true;
+        float sigma = 1.0f;
+        launch_single(FnInitFState{fs, delta, std::max(o->max_iter, 1), IR_INNER_STALL}, s);
+        auto finish = [&]() -> int {   // FP64 p-BiCGStab from the best iterate
+            launch_ew(FnCopy{x, x_best}, n, nullptr, s);
+            fell_back = 1;
+            max_iter = IR_FP64_FINISH;
+            const int st = run_fp64(h);
+            inner_total += h.iter;
+            return st;
+        };
+        while (true) {
+            // rebuild the FP32 state from r / nu
+            const float lim = (float)(o->tol * normb / nu);
             launch_ew(FnCastScaled{W.r32, W.r, W.st}, n, nullptr, s);
-            int its = 0;
-            if (run_fp32_inner(its)) return PBCG_ERR_HIP;
-            inner_total += its;
+            launch_spmv32c(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s);
+            launch_spmv32c(&A32, W.w32, EpiStore<float>{W.t32}, nullptr, s);
+            launch_single(FnSetFState{fs, lim}, s);
+            FState hf{};
+            if (!restart) {
+                launch_ew(FnScaleF{W.p32, sigma}, n, nullptr, s);
+                launch_spmv32c(&A32, W.p32, EpiStore<float>{W.s32}, nullptr, s);
+                launch_spmv32c(&A32, W.s32, EpiStore<float>{W.z32}, nullptr, s);
+                launch_spmv32c(&A32, W.z32, EpiStore<float>{W.v32}, nullptr, s);
+                FDotsOp<4, FFinReplace> d{};
+                d.a[0] = W.rh32; d.b[0] = W.r32;
+                d.a[1] = W.rh32; d.b[1] = W.w32;
+                d.a[2] = W.rh32; d.b[2] = W.s32;
+                d.a[3] = W.rh32; d.b[3] = W.z32;
+                d.fin = FFinReplace{fs};
+                launch_ew_fdot<4>(d, n, W.fsite, nullptr, s);
+                HIPCHK(hipMemcpyAsync(&hf, fs, sizeof(FState), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                if (hf.halt) {              // no usable alpha: restart from the same residual
+                    restart = true;
+                    launch_single(FnSetFState{fs, lim}, s);
+                }
+            }
+            if (restart) {
+                launch_ew(FnCopyF{W.rh32, W.r32}, n, nullptr, s);
+                FDotsOp<2, FFinRestart> d{};
+                d.a[0] = W.rh32; d.b[0] = W.r32;
+                d.a[1] = W.rh32; d.b[1] = W.w32;
+                d.fin = FFinRestart{fs};
+                launch_ew_fdot<2>(d, n, W.fsite, nullptr, s);
+                HIPCHK(hipMemcpyAsync(&hf, fs, sizeof(FState), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                if (hf.halt) return finish();
+            }
+            launch_ew(FnZeroF{W.d32}, n, nullptr, s);
+            if (run_fp32(hf, restart)) return PBCG_ERR_HIP;
+            const int reason = hf.reason;
+            if (reason & R_YYZERO) {        // (y, y) = 0: d = d + alpha p completes the iteration
+                launch_ew(FnFAxpyState{W.d32, W.p32, fs}, n, nullptr, s);
+                launch_single(FnFIterPlus{fs}, s);
+            }
+            inner_total = hf.iter + ((reason & R_YYZERO) ? 1 : 0);
+            // reliable update
             launch_ew(FnIRUpdate{x, W.d32, W.st}, n, nullptr, s);
+            if (true_residual_ir(h)) return PBCG_ERR_HIP;
+            ++outer;
+            double nu_new = h.last_dot;
+            if (o->trace)
+                std::fprintf(stderr, "pbicgstab ir: update %d after %d FP32 iterations: reason 0x%x rec %.3e "
+                             "true/previous %.3e true/||b|| %.3e%s\n", outer, inner_total, reason, (double)hf.rec,
+                             nu_new / nu, h.true_rel, restart ? " (restarted)" : "");
+            if (!std::isfinite(nu_new)) return finish();
+            if (h.true_rel <= o->tol) return PBCG_OK;
+            restart = (reason & (R_BREAKDOWN | R_NONFINITE | R_STALL | R_YYZERO)) != 0;
+            if (nu_new < nu_best) {
+                nu_best = nu_new;
+                bad = 0;
+                launch_ew(FnCopy{x_best, x}, n, nullptr, s);
+            } else {
+                ++bad;
+                restart = true;
+                launch_ew(FnCopy{x, x_best}, n, nullptr, s);
+                if (true_residual_ir(h)) return PBCG_ERR_HIP;
+                nu_new = h.last_dot;
+            }
+            if (bad >= IR_MAX_BAD || outer >= max_outer || (reason & R_MAXIT)) return finish();
+            sigma = (float)(nu / nu_new);
+            nu = nu_new;
         }
-        return PBCG_NOT_CONVERGED;
     }
 };
 

@@ -177,10 +177,16 @@ spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ c
 // Chunks are dealt to the worker blocks of each XCD from a contiguous range of rows
 // (hardware block b runs on XCD b % 8), so the x planes a stencil row touches are
 // shared in that XCD's L2.
-template <int CAP, class VT, class XT, class AT, class Body>
+//
+// COMP (float only): compensated accumulation, algorithm Dot2 of Ogita, Rump and Oishi
+// (2005) in storage order -- the window holds (p, e) with p = fl(a x) and the exact
+// product error e = fma(a, x, -p); each lane runs TwoSum(s, p) and adds err + e into a
+// compensation c; the row's value is fl(s + c).  All arithmetic is float32.
+template <int CAP, class VT, class XT, class AT, class Body, bool COMP = false>
 __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const XT* __restrict__ x,
                                           int bfirst, int G, AT* sprod, Body& body) {
+    static_assert(!COMP || (sizeof(AT) == 4 && sizeof(VT) == 4 && sizeof(XT) == 4), "Dot2 path is float32");
     constexpr int R = 256;            // blockDim.x
     constexpr int PER = CAP / R;
     const int nchunk = (n + R - 1) / R;
@@ -205,7 +211,7 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
         const int A0 = rp[r0], A1 = rp[r1];
         int RA = 0, RB = 0;
         if (row < r1) { RA = rp[row]; RB = rp[row + 1]; }
-        AT s = AT(0);
+        AT s = AT(0), cmp = AT(0);
         for (int w = A0; w < A1; w += CAP) {
             const int we = min(w + CAP, A1);
             VT pv[PER];
@@ -219,15 +225,34 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
             for (int j = 0; j < PER; ++j) {
                 const int k = w + t + j * R;
                 if (k < we) {
-                    AT prod = (AT)pv[j] * (AT)x[pc[j]];
-                    sprod[k - w] = prod;
+                    const AT a = (AT)pv[j], xv = (AT)x[pc[j]];
+                    AT prod = a * xv;
+                    if constexpr (COMP) {
+                        float2* sp2 = (float2*)sprod;
+                        sp2[k - w] = make_float2(prod, fmaf(a, xv, -prod));
+                    } else {
+                        sprod[k - w] = prod;
+                    }
                 }
             }
             __syncthreads();
             const int ka = max(RA, w), kb = min(RB, we);
-            for (int k = ka; k < kb; ++k) s = s + sprod[k - w];
+            if constexpr (COMP) {
+                const float2* sp2 = (const float2*)sprod;
+                for (int k = ka; k < kb; ++k) {
+                    const float2 pe = sp2[k - w];
+                    const float sn = s + pe.x;
+                    const float bb = sn - s;
+                    const float err = (s - (sn - bb)) + (pe.x - bb);
+                    s = sn;
+                    cmp = cmp + (err + pe.y);
+                }
+            } else {
+                for (int k = ka; k < kb; ++k) s = s + sprod[k - w];
+            }
             __syncthreads();
         }
+        if constexpr (COMP) s = s + cmp;
         if (row < r1) body(row, s);
     }
 }
@@ -242,12 +267,12 @@ struct StoreBody {
 };
 
 // grid = worker blocks (+1 when block 0 carries a finalize role)
-template <class VT, class XT, class AT, class Epi, class Fin>
+template <class VT, class XT, class AT, class Epi, class Fin, bool COMP = false>
 __global__ void __launch_bounds__(256)
 spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                 const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt) {
     if (halt && *halt) return;
-    constexpr int STAGE = SEQ_CAP * (int)sizeof(AT);
+    constexpr int STAGE = SEQ_CAP * (int)sizeof(AT) * (COMP ? 2 : 1);
     constexpr int SMEM = Fin::SMEM > STAGE ? Fin::SMEM : STAGE;
     __shared__ __align__(16) unsigned char smem[SMEM];
     int bfirst = 0;
@@ -259,7 +284,8 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
         bfirst = 1;
     }
     StoreBody<Epi> body{epi};
-    seq_stage<SEQ_CAP, VT, XT, AT>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst, (AT*)smem, body);
+    seq_stage<SEQ_CAP, VT, XT, AT, StoreBody<Epi>, COMP>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst,
+                                                          (AT*)smem, body);
 }
 
 // ----------------------------------------------------------------------------- dot sites
@@ -821,16 +847,31 @@ struct FDotsOp {
 };
 
 // (b,b), (r_hat,r), (r_hat,w) of the inner solve (r = r_hat = b at x0 = 0)
-struct FFinInit {
+// Restart of the FP32 process (r_hat = r, p = r, s = w, z = t follow in phase A):
+// d = (r_hat, r), (r_hat, w) -> rho, alpha = rho / (r_hat, w); beta = omega = 0.
+struct FFinRestart {
     FState* st;
     __device__ void operator()(const float* d) const {
-        float nb = sqrtf(d[0]);
-        st->normb = nb; st->rho = d[1];
-        st->beta = 0.0f; st->omega = 0.0f; st->rec = 1.0f;
-        if (nb == 0.0f) { st->halt = 1; st->reason |= R_ZERO_RHS; return; }
-        float rw = d[2];
+        const float rho = d[0], rw = d[1];
+        st->beta = 0.0f; st->omega = 0.0f;
         if (rw == 0.0f || !isfinite(rw)) { st->halt = 1; st->reason |= R_BREAKDOWN; return; }
-        st->alpha = d[1] / rw;
+        st->rho = rho;
+        st->alpha = rho / rw;
+    }
+};
+
+// Continuation after a reliable update (r, w, t, s, z, v rebuilt; beta, omega kept):
+// d = (r_hat, r), (r_hat, w), (r_hat, s), (r_hat, z);
+// alpha = rho / (((r_hat, w) + beta (r_hat, s)) - (beta omega)(r_hat, z)).
+struct FFinReplace {
+    FState* st;
+    __device__ void operator()(const float* d) const {
+        const float rho = d[0];
+        const float beta = st->beta, omega = st->omega;
+        const float den = (d[1] + beta * d[2]) - (beta * omega) * d[3];
+        if (rho == 0.0f || den == 0.0f || !isfinite(den)) { st->halt = 1; st->reason |= R_BREAKDOWN; return; }
+        st->rho = rho;
+        st->alpha = rho / den;
     }
 };
 
@@ -841,30 +882,32 @@ struct FFinOmega {
         st->rs = d[2]; st->rz = d[3];
         if (yy == 0.0f || !isfinite(yy)) { st->halt = 1; st->reason |= (yy == 0.0f ? R_YYZERO : R_NONFINITE); return; }
         float om = qy / yy;
+        if (om == 0.0f || !isfinite(om)) { st->halt = 1; st->reason |= R_BREAKDOWN; return; }
         st->omega = om;
-        if (om == 0.0f || !isfinite(om)) { st->halt = 1; st->reason |= R_BREAKDOWN; }
     }
 };
 
-struct FFinPhaseB {
+// End of an FP32 iteration: beta, alpha for the next one, then the stop reasons of the
+// refinement (R_CONVERGED: rec <= lim; R_CHECK: rec <= tol, a reliable update is due;
+// R_BREAKDOWN; R_STALL: no new minimum of rec for `stall` iterations; R_MAXIT).
+struct FFinRU {
     FState* st;
     __device__ void operator()(const float* d) const {
         const float rho_new = d[0], rw = d[1], rr = d[2];
-        const float alpha = st->alpha, omega = st->omega, rho = st->rho;
         const int it = st->iter + 1;
         st->iter = it;
-        const float rec = sqrtf(rr) / st->normb;
+        const float rec = sqrtf(rr);
         st->rec = rec;
         int reason = 0;
-        if (rec <= st->tol) reason |= R_CONVERGED;
-        else {
-            if (rec < st->best) { st->best = rec; st->it_best = it; }
-            else if (st->stall > 0 && it - st->it_best >= st->stall) reason |= R_STALL;
-            const float beta = ((alpha / omega) * rho_new) / rho;
-            const float den = (rw + beta * st->rs) - (beta * omega) * st->rz;
-            if (rho_new == 0.0f || den == 0.0f || !isfinite(den)) reason |= R_BREAKDOWN;
-            else { st->beta = beta; st->alpha = rho_new / den; st->rho = rho_new; }
-        }
+        const float alpha = st->alpha, omega = st->omega, rho = st->rho;
+        const float bn = ((alpha / omega) * rho_new) / rho;
+        const float den = (rw + bn * st->rs) - (bn * omega) * st->rz;
+        if (rho_new == 0.0f || den == 0.0f || !isfinite(den)) reason |= R_BREAKDOWN;
+        else { st->beta = bn; st->alpha = rho_new / den; st->rho = rho_new; }
+        if (rec <= st->lim) reason |= R_CONVERGED;
+        if (rec <= st->tol) reason |= R_CHECK;
+        if (rec < st->best) { st->best = rec; st->it_best = it; }
+        else if (st->stall > 0 && it - st->it_best >= st->stall) reason |= R_STALL;
         if (it >= st->max_iter) reason |= R_MAXIT;
         if (reason) { st->halt = 1; st->reason |= reason; }
     }

@@ -35,11 +35,13 @@ struct State {
     double* stall_hist;     // full per-iteration history for stall detection (or null)
 };
 
-// FP32 inner-solver scalars.
+// State of the FP32 iterations of the refinement solver.  rec = sqrt((r, r)) in units
+// of the last reliable update's residual norm; tol: the update threshold on rec; lim:
+// the rec below which the solve looks converged (tol ||b|| / nu).
 struct FState {
     float alpha, beta, omega, rho;
-    float rs, rz, normb, rec;
-    float tol, best, pad1, pad2;     // best: smallest recursive residual so far
+    float rs, rz, pad0, rec;
+    float tol, best, lim, pad2;      // best: smallest rec since the last update
     int32_t iter, max_iter, halt, reason;
     int32_t halt_seen, it_best, stall, fpad2;   // stall: iterations without a new best that stop
 };

@@ -89,7 +89,7 @@ def test_spmv_fp32_values_and_f32_path():
     A32h = g.CSR(p.A.n, p.A.row_ptr, p.A.col_idx, p.A.val.astype(np.float32).astype(np.float64))
     check_bound(A32h, x, y)
     assert np.array_equal(y, spmv(A32h, x))  # FP32 values are exact in FP64
-    # pure FP32 path: row-sequential in float32, bit-identical to the oracle's float32 loop
+    # pure FP32 path: row-sequential Dot2-compensated float32, bit-identical to the oracle
     from oracle.spmv import spmv_f32
     x32 = x.astype(np.float32)
     y32 = pk.csr_spmv_f32(A32, to_dev(x32)).cpu().numpy()

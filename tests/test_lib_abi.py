@@ -63,7 +63,7 @@ def test_status_strings_and_defaults():
     assert pk.status_string(0) == "ok"
     assert pk.status_string(-4) == "workspace too small"
     o = pk.default_opts()
-    assert o.tol == 1e-10 and o.max_iter == 10000 and o.batch == 16 and o.inner_tol == 1e-3
+    assert o.tol == 1e-10 and o.max_iter == 10000 and o.batch == 16 and o.inner_tol == 0.1 and o.max_outer == 60
 
 
 def test_host_argument_checks_without_gpu():
