@@ -151,27 +151,51 @@ __device__ __forceinline__ void accumulate(double (&e)[K], double x, double y,
     }
 }
 
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+// Cross-lane moves within a row of 16 lanes (DPP, register to register): quad_perm
+// [1,0,3,2] and [2,3,0,1] exchange with lane^1 and lane^2, row_ror:4 and row_ror:8
+// rotate the row.  Applied in that order, a + move(a) leaves every lane of the row
+// holding the row's total.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = dpp_move<CTRL>(__double2loint(v));
+    const int hi = dpp_move<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_ROR4 = 0x124, DPP_ROR8 = 0x128;
+
+__device__ __forceinline__ int row_min_i(int v) {
+    v = min(v, dpp_move<DPP_XOR1>(v));
+    v = min(v, dpp_move<DPP_XOR2>(v));
+    v = min(v, dpp_move<DPP_ROR4>(v));
+    v = min(v, dpp_move<DPP_ROR8>(v));
     return v;
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o);
+__device__ __forceinline__ double row_sum_d(double v) {
+    v = v + dpp_move<DPP_XOR1>(v);
+    v = v + dpp_move<DPP_XOR2>(v);
+    v = v + dpp_move<DPP_ROR4>(v);
+    v = v + dpp_move<DPP_ROR8>(v);
     return v;
 }
 
-// Exact wave-wide deposit of one double per lane (zeros ignored).  All 64 lanes of
-// the wave must call it together.
+// Exact deposit of one double per lane (zeros ignored), reduced per row of 16 lanes.
+// All 64 lanes of the wave must call it together.  A row's values whose 32-bit chunk
+// index is within one of the row's smallest are cut at that chunk into four signed
+// 32-bit pieces; the pieces are summed across the row in FP64 (at most 16 integers
+// below 2^32: exact) and the row's leader adds the four sums into the accumulator.
+// Other values go through deposit_double.
 __device__ __forceinline__ void wave_deposit(unsigned long long* acc, double v) {
     bool nz = v != 0.0;
     if (__ballot(nz) == 0) return;
     uint64_t m = 0; int P = 0; bool neg = false;
     if (nz) decompose(v, m, P, neg);
     int c = nz ? (P >> 5) : 0x7fffffff;
-    int cmin = wave_min_i(c);
+    const int cmin = row_min_i(c);
     bool inwin = nz && (c - cmin) <= 1;
     double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
     if (inwin) {
@@ -184,12 +208,11 @@ __device__ __forceinline__ void wave_deposit(unsigned long long* acc, double v) 
         q2 = sg * (double)(w1 & 0xffffffffull);
         q3 = sg * (double)(w1 >> 32);
     }
-    // sums of <= 64 integers of magnitude < 2^32: exact in FP64
-    q0 = wave_sum_d(q0);
-    q1 = wave_sum_d(q1);
-    q2 = wave_sum_d(q2);
-    q3 = wave_sum_d(q3);
-    if ((threadIdx.x & (WAVE - 1)) == 0) {
+    q0 = row_sum_d(q0);
+    q1 = row_sum_d(q1);
+    q2 = row_sum_d(q2);
+    q3 = row_sum_d(q3);
+    if ((threadIdx.x & 15) == 0 && cmin != 0x7fffffff) {
         if (q0 != 0.0) atomicAdd(acc + cmin, (unsigned long long)(long long)q0);
         if (q1 != 0.0) atomicAdd(acc + cmin + 1, (unsigned long long)(long long)q1);
         if (q2 != 0.0) atomicAdd(acc + cmin + 2, (unsigned long long)(long long)q2);
