@@ -45,8 +45,10 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the sources of the solver kernels whose HBM traffic the counter profile
+    records (the learned-preconditioner kernels live in spai.hip and are not profiled)."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in ("capi.hip", "kernels.hpp", "state.hpp", "xdot.hpp"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -73,18 +75,39 @@ def hold_stream(torch, seconds):
 
 
 def time_launches(fn, reps, torch):
-    """Average duration of fn() over `reps` back-to-back launches (HIP events on the
-    current stream, launches queued behind a device-side hold)."""
+    """Median duration of fn() over `reps` back-to-back launches, each bracketed by HIP
+    events on the current stream, all queued behind a device-side hold."""
     fn()
     torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     hold_stream(torch, 2e-3 + reps * 1e-4)
-    s.record()
-    for _ in range(reps):
+    ev[0].record()
+    for k in range(reps):
         fn()
-    e.record()
-    e.synchronize()
-    return s.elapsed_time(e) / 1e3 / reps
+        ev[k + 1].record()
+    ev[-1].synchronize()
+    return float(np.median([ev[k].elapsed_time(ev[k + 1]) / 1e3 for k in range(reps)]))
+
+
+def spmv_cold(pk, torch, A, reps, kind=None):
+    """Median duration of one SpMV launch with a 512 MB write before each (no launch is
+    served from the Infinity Cache); returns (seconds, GB/s of 12 B/nnz + 20 B/row)."""
+    flush = torch.empty(64 << 20, dtype=torch.float64, device=A.val.device)
+    vin = torch.ones(A.n, dtype=torch.float64, device=A.val.device)
+    vout = torch.empty_like(vin)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for it in range(reps + 1):
+        flush.zero_()
+        e0.record()
+        pk.csr_spmv(A, vin, vout, kind=kind)
+        e1.record()
+        e1.synchronize()
+        if it:
+            ts.append(e0.elapsed_time(e1) / 1e3)
+    dt = float(np.median(ts))
+    vb = 12 if A.val.dtype == torch.float64 else 8
+    return dt, ((vb * A.nnz + 20 * A.n) / dt / 1e9)
 
 
 def timed_solve(pk, torch, A, b, reps=1, **opts):
@@ -136,6 +159,11 @@ def config_leg(pk, torch, g, dev, name, reps):
     t64, i64, x64 = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000)
     out = {"n": prob.A.n, "nnz": prob.A.nnz, "host_generation_s": gen,
            "forms": precision_forms(pk, torch, A, b, xs, x64, t64, i64, reps)}
+    kern = {}
+    for kname, kind in (("spmv_seq_cold", pk.SPMV_SEQ), ("spmv_vector_cold", pk.SPMV_VECTOR)):
+        dt, gbs = spmv_cold(pk, torch, A, 20, kind)
+        kern[kname] = {"us": dt * 1e6, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    out["kernels"] = kern
     out["forms"]["pbicgstab_fp64"]["rel_err_vs_xstar"] = rel(torch, x64, xs)
     log(f"{name}:", json.dumps(out))
     return out
@@ -361,29 +389,26 @@ def main():
             dt = tsum / cnt
             kern[name] = {"us": dt * 1e6, "bytes": nb, "GBs": nb / dt / 1e9, "launches": cnt}
         # SpMV kernel shapes, each launch preceded by a 512 MB write that evicts the cache
-        flush = torch.empty(64 << 20, dtype=torch.float64, device=dev)
-        vin, vout = V["z"], V["v"]
         for name, kind in (("spmv_seq_cold", pk.SPMV_SEQ), ("spmv_vector_cold", pk.SPMV_VECTOR),
                            ("spmv_wave_cold", pk.SPMV_WAVE)):
-            tsum = 0.0
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            for it in range(min(reps, 20) + 1):
-                flush.zero_()
-                e0.record()
-                pk.csr_spmv(A, vin, vout, kind=kind)
-                e1.record()
-                e1.synchronize()
-                if it:
-                    tsum += e0.elapsed_time(e1) / 1e3
-            dt = tsum / min(reps, 20)
-            kern[name] = {"us": dt * 1e6, "bytes": spmv_bytes, "GBs": spmv_bytes / dt / 1e9}
-        del flush
-        # standalone exact dot, rotating over buffers larger than the cache
-        for ne in (1 << 21, 1 << 24, 1 << 26):
+            dt, gbs = spmv_cold(pk, torch, A, min(reps, 20), kind)
+            kern[name] = {"us": dt * 1e6, "bytes": spmv_bytes, "GBs": gbs}
+        # standalone exact dot, rotating over buffers larger than the cache: uniform
+        # U[-1, 1] at 2^20, 2^24, 2^26; wide exponents (+-1000) and exactly cancelling
+        # (ill-conditioned) inputs at 2^24
+        cases = [("uniform", 1 << 20), ("uniform", 1 << 24), ("uniform", 1 << 26),
+                 ("wide_exponent", 1 << 24), ("ill_conditioned", 1 << 24)]
+        for fam, ne in cases:
             nbuf = max(2, int((768 << 20) // (16 * ne)))
-            bufs = [(torch.from_numpy(np.random.default_rng(10 + i).uniform(-1, 1, ne)).to(dev),
-                     torch.from_numpy(np.random.default_rng(20 + i).uniform(-1, 1, ne)).to(dev))
-                    for i in range(nbuf)]
+
+            def vecs(i):
+                if fam == "uniform":
+                    return (np.random.default_rng(10 + i).uniform(-1, 1, ne),
+                            np.random.default_rng(20 + i).uniform(-1, 1, ne))
+                if fam == "wide_exponent":
+                    return g.wide_exponent_vec(ne, 10 + i), g.wide_exponent_vec(ne, 20 + i, -20, 20)
+                return g.cancelling_vec(ne, 10 + i), np.ones(ne)
+            bufs = [tuple(torch.from_numpy(v).to(dev) for v in vecs(i)) for i in range(nbuf)]
             o1 = torch.empty(1, dtype=torch.float64, device=dev)
             wse = torch.empty(pk.lib().exdot_workspace_bytes(ne), dtype=torch.uint8, device=dev)
             cnt = [0]
@@ -393,7 +418,8 @@ def main():
                 cnt[0] += 1
                 pk.exdot(xa, ya, o1, wse)
             dt = time_launches(f, reps, torch)
-            kern[f"exdot_2^{ne.bit_length() - 1}"] = {"us": dt * 1e6, "bytes": 16 * ne, "GBs": 16 * ne / dt / 1e9}
+            key = f"exdot_2^{ne.bit_length() - 1}" + ("" if fam == "uniform" else f"_{fam}")
+            kern[key] = {"us": dt * 1e6, "bytes": 16 * ne, "GBs": 16 * ne / dt / 1e9}
             del bufs
         for k, v in kern.items():
             v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS

@@ -228,6 +228,16 @@ int spai_loss_grad(const pbcg_csr* A, const float* feat, const int32_t* rowidx, 
 int spai_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr,
               float b1, float b2, float eps, void* stream);
 
+/* One training step on one matrix: spai_loss_grad then spai_adam, with the step's M
+ * values and gradient kept in the workspace (spai_workspace_bytes(n, nnz, k)).
+ * feat / rowidx / diag from spai_features; V, U = A V (spai_probe_product) n x k
+ * column-major; adam_m, adam_v: 5057 device floats each (zero before step t = 1);
+ * hyper (host): {lr, beta1, beta2, eps}; loss: one device float (this step's loss,
+ * before the update). */
+int spai_train_step(const pbcg_csr* A, const float* feat, const int32_t* rowidx, const double* diag,
+                    const float* V, const float* U, int32_t k, float* params, float* adam_m, float* adam_v,
+                    int32_t t, const float* hyper, float* loss, void* ws, size_t ws_bytes, void* stream);
+
 /* Fill `opts` (host) with defaults: tol 1e-10, max_iter 10000, p-BiCGStab, FP64. */
 void pbcg_default_opts(pbcg_opts* opts);
 

@@ -63,7 +63,7 @@ EXPORTS = [
     "pbcg_phase_workspace_bytes", "pbcg_phase_a", "pbcg_phase_b", "pbicgstab_workspace_bytes",
     "pbicgstab_solve", "pbcg_default_opts", "pbcg_status_string", "pbcg_abi_version",
     "spai_param_count", "spai_workspace_bytes", "spai_features", "spai_forward", "spai_infer_bf16",
-    "spai_probe_product", "spai_loss_grad", "spai_adam",
+    "spai_probe_product", "spai_loss_grad", "spai_adam", "spai_train_step",
 ]
 
 _lib = None
@@ -105,6 +105,8 @@ def lib():
         "spai_loss_grad": (ctypes.c_int, [CP, _P, _P, _P, _P, _P, _P, i32, _P, _P, _P, _P, sz, _P]),
         "spai_adam": (ctypes.c_int, [_P, _P, _P, _P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, _P]),
+        "spai_train_step": (ctypes.c_int, [CP, _P, _P, _P, _P, _P, i32, _P, _P, _P, i32,
+                                           ctypes.POINTER(ctypes.c_float), _P, _P, sz, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -474,6 +474,8 @@ struct SpaiWs {
     float* gpart;     // gradient partials [GRAD_BLOCKS][NPARAM]
     float* R;         // n x k
     float* act;       // nnz x ACT
+    float* mstep;     // nnz: M values of a training step
+    float* gstep;     // NPARAM: gradient of a training step
     size_t need;
 };
 
@@ -494,6 +496,8 @@ SpaiWs carve(void* ws, int32_t n, int64_t nnz, int32_t k) {
     w.gpart = (float*)take(4 * (size_t)GRAD_BLOCKS * NPARAM);
     w.R = (float*)take(4 * (size_t)std::max(n, 1) * std::max(k, 1));
     w.act = (float*)take(4 * (size_t)std::max<int64_t>(nnz, 1) * ACT);
+    w.mstep = (float*)take(4 * (size_t)std::max<int64_t>(nnz, 1));
+    w.gstep = (float*)take(4 * (size_t)NPARAM);
     w.need = o;
     return w;
 }
@@ -591,6 +595,17 @@ int spai_adam(float* params, float* m, float* v, const float* grad, int32_t t, f
     k_adam<<<(NPARAM + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(params, m, v, grad, t, lr, b1, b2, eps);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
+}
+
+int spai_train_step(const pbcg_csr* A, const float* feat, const int32_t* rowidx, const double* diag,
+                    const float* V, const float* U, int32_t k, float* params, float* adam_m, float* adam_v,
+                    int32_t t, const float* hyper, float* loss, void* ws, size_t ws_bytes, void* stream) {
+    if (!csr_f64_ok(A) || !adam_m || !adam_v || !hyper || t < 1) return PBCG_ERR_INVALID;
+    if (!ws || ws_bytes < spai_workspace_bytes(A->n, A->nnz, k) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
+    SpaiWs w = carve(ws, A->n, A->nnz, k);
+    int rc = spai_loss_grad(A, feat, rowidx, diag, params, V, U, k, w.mstep, loss, w.gstep, ws, ws_bytes, stream);
+    if (rc != PBCG_OK) return rc;
+    return spai_adam(params, adam_m, adam_v, w.gstep, t, hyper[0], hyper[1], hyper[2], hyper[3], stream);
 }
 
 }  // extern "C"

@@ -70,6 +70,18 @@ class SpaiMatrix:
         _check(lib().spai_probe_product(self.A.c, _ptr(Vc), k, _ptr(U), _stream()), "spai_probe_product")
         return Vc, U
 
+    def train_step(self, params, m, v, Vc, U, k, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, loss=None):
+        """One fused training step (loss/gradient then Adam) via spai_train_step;
+        returns the device loss (before the update)."""
+        torch = _torch()
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=params.device)
+        hyper = (ctypes.c_float * 4)(lr, b1, b2, eps)
+        _check(lib().spai_train_step(self.A.c, _ptr(self.feat), _ptr(self.rowidx), _ptr(self.diag), _ptr(Vc),
+                                     _ptr(U), k, _ptr(params), _ptr(m), _ptr(v), int(t), hyper, _ptr(loss),
+                                     _ptr(self.ws), self.ws.numel(), _stream()), "spai_train_step")
+        return loss
+
     def loss_grad(self, params, Vc, U, k):
         torch = _torch()
         dev = params.device
@@ -139,11 +151,11 @@ def train(problems, epochs=30, lr=1e-3, seed=0, device="cuda", log=None):
     t = 0
     for ep in range(epochs):
         tot = 0.0
-        for sm, Vc, U, k in data:
+        losses = torch.empty(len(data), dtype=torch.float32, device=device)
+        for j, (sm, Vc, U, k) in enumerate(data):
             t += 1
-            loss, grad = sm.loss_grad(params, Vc, U, k)
-            adam(params, m, v, grad, t, lr=lr)
-            tot += float(loss.item())
+            sm.train_step(params, m, v, Vc, U, k, t, lr=lr, loss=losses[j:j + 1])
+        tot = float(losses.sum().item())
         hist.append(tot / len(data))
         if log:
             log(f"epoch {ep}: mean loss {hist[-1]:.5e}")

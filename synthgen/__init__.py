@@ -297,6 +297,17 @@ def uniform_vec(n: int, seed: int, lo=-1.0, hi=1.0) -> np.ndarray:
     return np.random.default_rng(seed).uniform(lo, hi, n)
 
 
+def cancelling_vec(n: int, seed: int, big_exp=300, n_small=16) -> np.ndarray:
+    """Ill-conditioned dot input against y = 1: pairs (u, -u) with exponents up to
+    big_exp cancel exactly, so the exact sum is that of n_small values in [-1, 1];
+    condition number sum|x| / |sum x| is astronomically large.  Seeded shuffle."""
+    rng = np.random.default_rng(seed)
+    h = (n - n_small) // 2
+    u = np.ldexp(rng.uniform(1.0, 2.0, h), rng.integers(-big_exp, big_exp, size=h, endpoint=True))
+    small = rng.uniform(-1.0, 1.0, n - 2 * h)
+    return rng.permutation(np.concatenate([u, -u, small]))
+
+
 def wide_exponent_vec(n: int, seed: int, emin=-1000, emax=1000) -> np.ndarray:
     """Signed doubles with uniformly random exponents in [emin, emax]."""
     rng = np.random.default_rng(seed)

@@ -115,3 +115,21 @@ def test_trained_preconditioner_gains(capsys):
     assert hist[-1] < hist[0]
     assert learned["status"] == pk.OK and learned["true_relres"] <= 1e-10
     assert learned["iterations"] < plain["iterations"]
+
+
+def test_train_step_equals_loss_grad_then_adam(mat):
+    """spai_train_step = spai_loss_grad followed by spai_adam, bit for bit."""
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    V = torch.from_numpy(g.rademacher(mat.A.n, 8, 2).astype(np.float32)).cuda()
+    Vc, U = sm.probe_product(V)
+    p0 = torch.from_numpy(rand_params(9).astype(np.float32)).cuda()
+    pa, pb = p0.clone(), p0.clone()
+    ma, va = torch.zeros_like(p0), torch.zeros_like(p0)
+    mb, vb = torch.zeros_like(p0), torch.zeros_like(p0)
+    for t in (1, 2):
+        loss_a, grad = sm.loss_grad(pa, Vc, U, 8)
+        spai.adam(pa, ma, va, grad, t, lr=1e-3)
+        loss_b = sm.train_step(pb, mb, vb, Vc, U, 8, t, lr=1e-3)
+        assert loss_a.item() == loss_b.item()
+    assert torch.equal(pa.view(torch.int32), pb.view(torch.int32))
+    assert torch.equal(ma.view(torch.int32), mb.view(torch.int32))

@@ -68,3 +68,39 @@ def test_mutated_product_scale_is_caught():
     good = exact.scaled_product(3.0, 5.0)
     assert exact.round_scaled(bad(3.0, 5.0)) != exact.round_scaled(good)
     assert math.isclose(exact.round_scaled(good), 15.0)
+
+
+# --- FP32 pieces of the refinement -------------------------------------------------
+def test_mutated_dot2_spmv_is_caught():
+    """Dropping the product error e from the compensation loses the 2^-24 that the
+    cancellation pin demands."""
+    from oracle import spmv as ospmv
+    from tests.test_oracle_ir import csr_rows
+    A = csr_rows([[(0, 1.0 + 2.0 ** -12), (1, 1.0)]])
+    x = np.array([1.0 + 2.0 ** -12, -(1.0 + 2.0 ** -11)], dtype=np.float32)
+    assert ospmv.spmv_f32(A, x)[0] == np.float32(2.0 ** -24)
+    bad = _mutant(ospmv.spmv_f32, "c[rows] = c[rows] + (err + e)", "c[rows] = c[rows] + err")
+    assert bad(A, x)[0] != np.float32(2.0 ** -24)
+
+
+def test_mutated_tree_dot_order_is_caught():
+    big = float(2 ** 24)
+    a = np.zeros(4096, dtype=np.float32)
+    a[0], a[1], a[32] = big, 1.0, -big
+    b = np.ones(4096, dtype=np.float32)
+    assert solvers.dot_f32_tree(a, b) == 1.0
+    bad = _mutant(solvers.dot_f32_tree, "for o in (32, 16, 8, 4, 2, 1):", "for o in (1, 2, 4, 8, 16, 32):")
+    assert bad(a, b) != 1.0
+
+
+@pytest.mark.parametrize("old,new", [
+    ("        r = (r64 / nu).astype(f)\n", "        r = r if p is not None else (r64 / nu).astype(f)\n"),  # no replacement
+    ("x = x + nu * d.astype(np.float64)", "x = x - nu * d.astype(np.float64)"),                          # wrong sign
+])
+def test_mutated_refinement_is_caught(old, new):
+    import synthgen as g
+    p = g.problem("cd3d_128", scale=16)
+    ok = solvers.ir_solve(p.A, p.b, tol=1e-10)
+    assert ok.status == solvers.OK and ok.fell_back == 0
+    bad = _mutant(solvers.ir_solve, old, new)(p.A, p.b, tol=1e-10)
+    assert bad.fell_back == 1 or bad.status != solvers.OK
