@@ -11,6 +11,8 @@ fused exact dots, and the true-residual checks), inputs already resident in HBM.
 Also reported (outside the timed steps):
   * on the same matrix: the BiCGStab comparator and FP32 / FP64 refinement with
     reliable updates at update threshold 0.1 (the library default) and 1e-5;
+  * the paper's central comparison: exact vs ordinary FP64 dots, with and without
+    residual replacement, at tolerances 1e-10 and 1e-13;
   * the learned preconditioner: training on the seeded matrices 100..299 with the GPU
     kernels, then the held-out 128^3 Peclet-50 matrix solved plain, with Jacobi and with
     the learned M (setup time stated separately);
@@ -21,7 +23,7 @@ Also reported (outside the timed steps):
     CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--solve-only]
-                       [--legs learned,rand_1m,cd3d_256_var] [--epochs 30]
+                       [--legs claim,learned,rand_1m,cd3d_256_var] [--epochs 30]
 """
 import argparse
 import hashlib
@@ -169,6 +171,22 @@ def config_leg(pk, torch, g, dev, name, reps):
     return out
 
 
+def claim_leg(pk, torch, A, b, n):
+    """The paper's central comparison on the benchmark matrix: exact vs ordinary FP64
+    dots, without and with residual replacement (period 50), at the benchmark tolerance
+    1e-10 and at 1e-13 (below what the recurrences sustain); iteration cap 1500."""
+    out = {}
+    for tol in (1e-10, 1e-13):
+        for label, dots, rr in (("exact", pk.DOTS_EXACT, 0), ("plain", pk.DOTS_PLAIN, 0),
+                                ("exact_rr50", pk.DOTS_EXACT, 50), ("plain_rr50", pk.DOTS_PLAIN, 50)):
+            t, info, _ = timed_solve(pk, torch, A, b, 1, tol=tol, max_iter=1500, dots=dots, rr_period=rr)
+            out[f"{label}_tol{tol:g}"] = {"seconds": t, "status": info["status"], "iterations": info["iterations"],
+                                         "true_checks": info["true_checks"], "true_relres": info["true_relres"],
+                                         "rec_relres": info["rec_relres"]}
+    log("claim:", json.dumps(out))
+    return out
+
+
 def learned_leg(pk, torch, g, dev, reps, epochs):
     """Learned SPAI: train on the seeded matrices 100..299 (2D/3D convection-diffusion,
     n 16k-262k, Peclet 1-100, kappa = exp(N(0,1))) with the GPU forward / backward / Adam
@@ -269,8 +287,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-only", action="store_true")
     ap.add_argument("--reps", type=int, default=50)
-    ap.add_argument("--legs", default="learned,rand_1m,cd3d_256_var",
-                    help="comma list of extra legs: learned, rand_1m, cd3d_256_var (empty: none)")
+    ap.add_argument("--legs", default="claim,learned,rand_1m,cd3d_256_var",
+                    help="comma list of extra legs: claim, learned, rand_1m, cd3d_256_var (empty: none)")
     ap.add_argument("--epochs", type=int, default=30, help="learned-preconditioner training epochs")
     ap.add_argument("--traffic-run", action="store_true",
                     help="launch each measured kernel 10 times (for rocprofv3 --pmc runs) and exit")
@@ -444,6 +462,8 @@ def main():
         del V, wsp
         # further legs run after the kernel table, so that they do not disturb its timings
         legs = [l for l in args.legs.split(",") if l]
+        if "claim" in legs:
+            out["exact_vs_plain_dots"] = claim_leg(pk, torch, A, b, n)
         if "learned" in legs:
             out["learned_m"] = learned_leg(pk, torch, g, dev, 1, args.epochs)
         for name in ("rand_1m", "cd3d_256_var"):

@@ -56,6 +56,13 @@ typedef enum { PBCG_PREC_FP64 = 0, PBCG_PREC_FP32_IR = 1 } pbcg_prec;
  * WAVE one 64-lane wavefront per row, both with a fixed tree order per matrix. */
 typedef enum { PBCG_SPMV_SEQ = 0, PBCG_SPMV_VECTOR = 1, PBCG_SPMV_WAVE = 2 } pbcg_spmv_kind;
 
+/* Inner products of the p-BiCGStab recurrences.  EXACT: accumulated exactly and rounded
+ * once (paper, Section 2, the ExBLAS paragraph).  PLAIN: ordinary FP64 products and sums
+ * in a fixed reduction tree -- the comparator for the paper's claim that exact dots keep
+ * the recursive residual with the true one.  ||b||, the true residual and the (q, q)
+ * test of a lucky breakdown stay exact in both. */
+typedef enum { PBCG_DOTS_EXACT = 0, PBCG_DOTS_PLAIN = 1 } pbcg_dots;
+
 /* Square CSR matrix.  `val` points to nnz values of type `val_type`. */
 typedef struct {
     int32_t n;
@@ -87,6 +94,11 @@ typedef struct {
                                   residual that count as a stall (default 200)               */
     int32_t spmv_kind;         /* pbcg_spmv_kind used for every A.v of the solve (default SEQ) */
     int32_t trace;             /* nonzero: one line per FP32-IR reliable update on stderr     */
+    int32_t dots;              /* pbcg_dots (FP64 p-BiCGStab without M; default EXACT)         */
+    int32_t rr_period;         /* > 0: residual replacement every rr_period iterations (paper,
+                                  the p-BiCGStabRR variant): r = b - A x, w = A r, t = A w,
+                                  s = A p, z = A s, v = A z; scalars kept.  FP64 p-BiCGStab
+                                  without M only.  0: none                                    */
 } pbcg_opts;
 
 /* Result summary (host struct). */

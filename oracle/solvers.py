@@ -96,16 +96,25 @@ def _true_relres(A, b, x, normb, dot, spmv):
 
 
 def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=None,
-              record=0, stall_window=0) -> Result:
+              record=0, stall_window=0, exact_dot=None, rr_period=0) -> Result:
     """p-BiCGStab, Algorithm 2, with the readings in the module docstring.
 
     With ``M`` (a CSR right preconditioner) the recurrences run on A.M and y,
     starting from y_0 = 0, and x = M y; ``x0`` must then be None.
     ``record`` keeps (x_i, r_i, alpha, omega) for the first ``record`` iterations.
+    ``dot`` forms the inner products of the recurrences; ``exact_dot`` (default: the
+    same) forms ||b||, the true residual and the (q, q) test -- with dot = dot_f64_tree
+    and the exact dot there, this is the ordinary-dot comparator.
+    ``rr_period`` > 0: residual replacement (the p-BiCGStabRR variant the paper refers
+    to) after every rr_period-th completed iteration: r = b - A x, w = A r, t = A w,
+    s = A p, z = A s, v = A z, with the scalars kept (unpreconditioned only).
     """
     spmv = spmv or _spmv
     n = A.n
     dot = dot or default_dot(n)
+    xdot = exact_dot or dot
+    if rr_period and M is not None:
+        raise ValueError("residual replacement is defined for the unpreconditioned solve")
     op = _Operator(A, M, spmv)
     b = np.asarray(b, dtype=np.float64)
     if M is not None and x0 is not None:
@@ -115,10 +124,10 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     def finish(status, iters, rec, hist, its, checks, true=None):
         x = op.to_x(y)
         if true is None:
-            true = _true_relres(A, b, x, normb, dot, spmv) if normb > 0 else 0.0
+            true = _true_relres(A, b, x, normb, xdot, spmv) if normb > 0 else 0.0
         return Result(x, status, iters, true, rec, checks, hist, its)
 
-    nb2 = dot(b, b)
+    nb2 = xdot(b, b)
     if not math.isfinite(nb2):
         return Result(op.to_x(y), ERR_NONFINITE, 0, math.nan, math.nan)
     normb = math.sqrt(nb2)
@@ -135,7 +144,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     hist, its, checks = [], [], 0
     if rec <= tol:
         checks += 1
-        tr = _true_relres(A, b, op.to_x(y), normb, dot, spmv)
+        tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
         if tr <= tol:
             return finish(OK, 0, rec, hist, its, checks, tr)
     if not _finite(rho, rw):
@@ -162,10 +171,10 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         if not _finite(qy, yy, rs, rz):
             return finish(ERR_NONFINITE, i, rec, hist, its, checks)
         if yy == 0.0:
-            if dot(q, q) == 0.0:  # lucky breakdown: r_{i+1} = q_i = 0
+            if xdot(q, q) == 0.0:  # lucky breakdown: r_{i+1} = q_i = 0
                 y = y + alpha * p
                 checks += 1
-                tr = _true_relres(A, b, op.to_x(y), normb, dot, spmv)
+                tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
                 return finish(OK if tr <= tol else BREAKDOWN, i + 1, 0.0, hist, its, checks, tr)
             return finish(BREAKDOWN, i, rec, hist, its, checks)
         omega = qy / yy
@@ -187,7 +196,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         alpha_new = rho_new / den if den != 0.0 else math.nan
         if rec <= tol:
             checks += 1
-            tr = _true_relres(A, b, op.to_x(y), normb, dot, spmv)
+            tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
             if tr <= tol:
                 return finish(OK, i + 1, rec, hist, its, checks, tr)
         if not _finite(rho_new, rw, rr, beta) or (den != 0.0 and not math.isfinite(alpha_new)):
@@ -198,6 +207,13 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         if stall_window and len(hist) > stall_window and rec > 0.5 * hist[-1 - stall_window]:
             return finish(STALLED, i + 1, rec, hist, its, checks)
         alpha, rho = alpha_new, rho_new
+        if rr_period and (i + 1) % rr_period == 0:
+            r = b - spmv(A, y)
+            w = op.apply(r)
+            t = op.apply(w)
+            s = op.apply(p)
+            z = op.apply(s)
+            v = op.apply(z)
     return finish(NOT_CONVERGED, max_iter, rec, hist, its, checks)
 
 
@@ -307,6 +323,13 @@ def dot_f32_seq(a: np.ndarray, b: np.ndarray) -> np.float32:
     return np.float32(np.add.accumulate(prod, dtype=np.float32)[-1])
 
 
+def dot_f64_tree(a: np.ndarray, b: np.ndarray) -> float:
+    """Ordinary FP64 dot (products and sums rounded to double) in the same fixed
+    reduction tree as ``dot_f32_tree`` -- the non-exact comparator of the paper's
+    claim about exact inner products."""
+    return float(_tree_dot(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64), np.float64))
+
+
 def dot_f32_tree(a: np.ndarray, b: np.ndarray) -> np.float32:
     """Plain float32 dot in a fixed reduction tree -- the dot of the FP32 inner solver.
     Every product and every addition is rounded to float32; the order is fixed by n
@@ -320,9 +343,11 @@ def dot_f32_tree(a: np.ndarray, b: np.ndarray) -> np.float32:
       4. the G group values v_g (zero-padded to 256) become h_j = 0 + v_j and are
          folded h_j <- h_j + h_(j+w) for w = 128, 64, ..., 1; the dot is h_0.
     """
-    f = np.float32
-    a = np.asarray(a, dtype=f)
-    b = np.asarray(b, dtype=f)
+    return _tree_dot(np.asarray(a, dtype=np.float32), np.asarray(b, dtype=np.float32), np.float32)
+
+
+def _tree_dot(a, b, f):
+    """The fixed tree of ``dot_f32_tree`` in the arithmetic of type f."""
     n = a.size
     G = fdot_grid(n)
     S = G * FDOT_BLOCK

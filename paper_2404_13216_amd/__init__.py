@@ -25,6 +25,7 @@ F64, F32 = 0, 1
 ALG_PBICGSTAB, ALG_BICGSTAB = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 SPMV_SEQ, SPMV_VECTOR, SPMV_WAVE = 0, 1, 2
+DOTS_EXACT, DOTS_PLAIN = 0, 1
 
 _P = ctypes.c_void_p
 
@@ -40,7 +41,8 @@ class PbcgOpts(ctypes.Structure):
                 ("M", ctypes.POINTER(PbcgCsr)), ("fallback", ctypes.c_int32),
                 ("history_len", ctypes.c_int32), ("history", _P), ("r_out", _P),
                 ("batch", ctypes.c_int32), ("stall_window", ctypes.c_int32),
-                ("spmv_kind", ctypes.c_int32), ("trace", ctypes.c_int32)]
+                ("spmv_kind", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("dots", ctypes.c_int32), ("rr_period", ctypes.c_int32)]
 
 
 class PbcgInfo(ctypes.Structure):

@@ -196,18 +196,19 @@ void launch_ew_dot(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t
     fin_kernel<XFin<D, Op>><<<1, BLOCK, 0, s>>>(f);
 }
 
-template <int D, class Op>
-FFin<D, Op> launch_ew_fdot_deferred(Op op, int64_t n, FSite site, const int* halt, hipStream_t s,
-                                    int* seen = nullptr) {
+// plain dots in the fixed tree (T = float: the FP32 solver; double: ordinary FP64 dots)
+template <int D, class T, class Op>
+TFin<T, D, Op> launch_ew_fdot_deferred(Op op, int64_t n, TSite<T> site, const int* halt, hipStream_t s,
+                                       int* seen = nullptr) {
     int grid = dot_grid(n);
-    ew_fdot_kernel<D, Op><<<grid, DOT_BLOCK, 0, s>>>(op, n, site, halt, seen);
-    return FFin<D, Op>{op, site, grid, halt};
+    ew_fdot_kernel<T, D, Op><<<grid, DOT_BLOCK, 0, s>>>(op, n, site, halt, seen);
+    return TFin<T, D, Op>{op, site, grid, halt};
 }
 
-template <int D, class Op>
-void launch_ew_fdot(Op op, int64_t n, FSite site, const int* halt, hipStream_t s) {
-    FFin<D, Op> f = launch_ew_fdot_deferred<D>(op, n, site, halt, s);
-    fin_kernel<FFin<D, Op>><<<1, BLOCK, 0, s>>>(f);
+template <int D, class T, class Op>
+void launch_ew_fdot(Op op, int64_t n, TSite<T> site, const int* halt, hipStream_t s) {
+    TFin<T, D, Op> f = launch_ew_fdot_deferred<D>(op, n, site, halt, s);
+    fin_kernel<TFin<T, D, Op>><<<1, BLOCK, 0, s>>>(f);
 }
 
 template <class F>
@@ -373,7 +374,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int n, const int* __restric
 
 extern "C" {
 
-int pbcg_abi_version(void) { return 2; }
+int pbcg_abi_version(void) { return 3; }
 
 const char* pbcg_status_string(int status) {
     switch (status) {
@@ -520,6 +521,7 @@ struct Work {
     FState* fst;
     xd::Site site;
     FSite fsite;
+    TSite<double> dsite;   // partials of the ordinary (plain) FP64 dots
     double *rhat, *r, *w, *t, *p, *s, *z, *q, *y, *v, *tmp, *tmp2, *hist;
     float *r32, *rh32, *w32, *t32, *p32, *s32, *z32, *q32, *y32, *v32, *d32, *val32;
     size_t need;
@@ -533,6 +535,7 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
     W.fst = c.take<FState>(1);
     W.site = carve_site(c, DOT_GRID_MAX);
     W.fsite.part = c.take<float>((size_t)DOT_GRID_MAX * 4);
+    W.dsite.part = c.take<double>((size_t)DOT_GRID_MAX * 4);
     const size_t N = (size_t)std::max(n, 1);
     double** v64[] = {&W.rhat, &W.r, &W.w, &W.t, &W.p, &W.s, &W.z, &W.q, &W.y, &W.v, &W.tmp, &W.tmp2};
     for (double** pp : v64) *pp = c.take<double>(N);
@@ -635,11 +638,29 @@ struct Driver {
         const double* scal = &W.st->alpha;
         PhaseA<FinOmega> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
                             FinOmega{W.st, 1}};
+        PhaseB<FinPhaseB> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
+        if (o->dots == PBCG_DOTS_PLAIN) {
+            auto fa = launch_ew_fdot_deferred<4>(ElemOf<PhaseA<FinOmega>>{pa}, n, W.dsite, halt, s, seen);
+            op(W.z, W.v, fa, seen);
+            auto fb = launch_ew_fdot_deferred<3>(ElemOf<PhaseB<FinPhaseB>>{pb}, n, W.dsite, halt, s, seen);
+            op(W.w, W.t, fb, seen);
+            return;
+        }
         auto fa = launch_ew_dot_deferred<4, DOT_GRID_DEFAULT>(pa, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
         op(W.z, W.v, fa, seen);           // v = A z; omega is finalized by its block 0
-        PhaseB<FinPhaseB> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
         auto fb = launch_ew_dot_deferred<3, DOT_GRID_DEFAULT>(pb, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
         op(W.w, W.t, fb, seen);           // t = A w; beta, alpha finalized by its block 0
+    }
+
+    // Residual replacement after a completed iteration (skipped if the iteration halted):
+    // r = b - A x, w = A r, t = A w, s = A p, z = A s, v = A z; scalars unchanged.
+    void enqueue_replacement() {
+        launch_spmv64(A, x, EpiResid<double>{b, W.r, nullptr, nullptr}, halt, s, kind);
+        launch_spmv64(A, W.r, EpiStore<double>{W.w}, halt, s, kind);
+        launch_spmv64(A, W.w, EpiStore<double>{W.t}, halt, s, kind);
+        launch_spmv64(A, W.p, EpiStore<double>{W.s}, halt, s, kind);
+        launch_spmv64(A, W.s, EpiStore<double>{W.z}, halt, s, kind);
+        launch_spmv64(A, W.z, EpiStore<double>{W.v}, halt, s, kind);
     }
 
     void enqueue_iteration_b() {
@@ -682,7 +703,8 @@ struct Driver {
             d3.a[1] = W.rhat; d3.b[1] = W.w;
             d3.a[2] = W.r;    d3.b[2] = W.r;
             d3.fin = FinInitP{W.st};
-            launch_ew_dot<3>(d3, n, W.site, halt, s);
+            if (o->dots == PBCG_DOTS_PLAIN) launch_ew_fdot<3>(ElemOf<DotsOp<3, FinInitP>>{d3}, n, W.dsite, halt, s);
+            else launch_ew_dot<3>(d3, n, W.site, halt, s);
         } else {
             DotsOp<2, FinInitB> d2{};
             d2.a[0] = W.rhat; d2.b[0] = W.r;
@@ -703,6 +725,7 @@ struct Driver {
         }
         if (max_iter == 0) return PBCG_NOT_CONVERGED;
         bool first = true;
+        long long it_enq = 0;   // iterations enqueued since the start (replacement schedule)
         int polled = 0, batches = 0;
         // device-side halts end the loop; this bound only guards against a broken state
         const long long limit = (long long)max_iter + 4LL * batch + 64;
@@ -714,6 +737,8 @@ struct Driver {
                 if (bicg) enqueue_iteration_b();
                 else enqueue_iteration_p(first);
                 first = false;
+                ++it_enq;
+                if (o->rr_period > 0 && it_enq % o->rr_period == 0) enqueue_replacement();
             }
             HIPCHK(hipGetLastError());
             const int slot = batches & 1;
@@ -731,6 +756,9 @@ struct Driver {
                     launch_single(FnResume{W.st}, s);
                     polled = batches;
                     enqueued = h.iter;  // batches queued behind the halt were no-ops
+                    it_enq = h.iter;
+                    // the replacement after the halted iteration was skipped with it
+                    if (o->rr_period > 0 && h.iter > 0 && h.iter % o->rr_period == 0) enqueue_replacement();
                 }
             }
         }
@@ -941,6 +969,11 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         return PBCG_ERR_INVALID;
     if (opts->history && opts->history_len < 0) return PBCG_ERR_INVALID;
     if (opts->spmv_kind < PBCG_SPMV_SEQ || opts->spmv_kind > PBCG_SPMV_WAVE) return PBCG_ERR_INVALID;
+    if (opts->dots != PBCG_DOTS_EXACT && opts->dots != PBCG_DOTS_PLAIN) return PBCG_ERR_INVALID;
+    if (opts->rr_period < 0) return PBCG_ERR_INVALID;
+    if ((opts->dots == PBCG_DOTS_PLAIN || opts->rr_period > 0) &&
+        (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || opts->prec != PBCG_PREC_FP64))
+        return PBCG_ERR_INVALID;
     if (!ws || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
     Work W = carve_work(ws, ws_bytes, A->n, A->nnz, opts);
     if (!W.ok) return PBCG_ERR_WORKSPACE;

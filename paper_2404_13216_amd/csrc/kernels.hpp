@@ -37,18 +37,21 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return xcd * base + min(xcd, rem) + idx;
 }
 
-// per-block FP32 partials of a plain-dot site
-struct FSite {
-    float* part;            // [grid][D]
+// per-block partials of a plain-dot site (T = float for the FP32 solver, double for
+// the ordinary-dot FP64 comparator)
+template <class T>
+struct TSite {
+    T* part;                // [grid][D]
 };
+using FSite = TSite<float>;
 
 // Fixed-order tree over the G per-block partials (blockDim.x == 256).
-template <int D>
-__device__ void fdot_reduce(const FSite& site, int G, float* sh /* D*256 */, float* res /* D */) {
+template <int D, class T>
+__device__ void fdot_reduce(const TSite<T>& site, int G, T* sh /* D*256 */, T* res /* D */) {
     const int t = threadIdx.x;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        float s = 0.0f;
+        T s = T(0);
         for (int g = t; g < G; g += 256) s = s + site.part[(size_t)g * D + d];
         sh[d * 256 + t] = s;
     }
@@ -98,22 +101,24 @@ struct XFin {                       // exact dots
     }
 };
 
-template <int D_, class Op>
-struct FFin {                       // plain FP32 dots
+template <class T, int D_, class Op>
+struct TFin {                       // plain dots in a fixed tree
     static constexpr int D = D_;
-    static constexpr int SMEM = (4 + 4 * 256) * 4;
+    static constexpr int SMEM = (4 + 4 * 256) * (int)sizeof(T);
     Op op;
-    FSite site;
+    TSite<T> site;
     int G;
     const int* halt;
     __device__ void run(unsigned char* smem) {
         if (halt && *halt) return;
-        float* res = (float*)smem;
-        float* sh = res + 4;
+        T* res = (T*)smem;
+        T* sh = res + 4;
         fdot_reduce<D>(site, G, sh, res);
         if (threadIdx.x == 0) op.finalize(res);
     }
 };
+template <int D, class Op>
+using FFin = TFin<float, D, Op>;
 
 template <class Fin>
 __global__ void __launch_bounds__(256) fin_kernel(Fin fin) {
@@ -428,43 +433,57 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 // Plain FP32 dots: per-thread sequential sums in grid-stride order, xor-butterfly
 // within the wave, waves in index order; the per-block partials are summed in a fixed
 // tree by a finalize role (FFin; deterministic for a given launch shape).
-template <int D, class Op>
+template <class T, int D, class Op>
 __global__ void __launch_bounds__(1024)
-ew_fdot_kernel(Op op, int64_t n, FSite site, const int* halt, int* seen) {
+ew_fdot_kernel(Op op, int64_t n, TSite<T> site, const int* halt, int* seen) {
     if (halt && *halt) {
         if (seen && blockIdx.x == 0 && threadIdx.x == 0) *seen = 1;
         return;
     }
-    __shared__ float sh_w[D][16];
+    __shared__ T sh_w[D][16];
     op.load();
-    float a[D];
+    T a[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) a[d] = 0.0f;
+    for (int d = 0; d < D; ++d) a[d] = T(0);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        float xa[D], ya[D];
+        T xa[D], ya[D];
         op.elem(i, xa, ya);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            float p = xa[d] * ya[d];
+            T p = xa[d] * ya[d];
             a[d] = a[d] + p;
         }
     }
     const int wid = threadIdx.x / xd::WAVE, nw = blockDim.x / xd::WAVE;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        float v = a[d];
+        T v = a[d];
 #pragma unroll
         for (int o = xd::WAVE / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o);
         if ((threadIdx.x & (xd::WAVE - 1)) == 0) sh_w[d][wid] = v;
     }
     __syncthreads();
     if (threadIdx.x < D) {
-        float s = 0.0f;
+        T s = T(0);
         for (int w = 0; w < nw; ++w) s = s + sh_w[threadIdx.x][w];
         site.part[(size_t)blockIdx.x * D + threadIdx.x] = s;
     }
 }
+
+// Element interface (elem(i, xa, ya)) over an exact-dot op (ld / st), so that an FP64
+// phase can run with plain tree dots.
+template <class Op>
+struct ElemOf {
+    Op op;
+    __device__ __forceinline__ void load() { op.load(); }
+    __device__ __forceinline__ void elem(int64_t i, double (&xa)[Op::ND], double (&ya)[Op::ND]) {
+        double in[Op::NIN];
+        op.ld(i, in);
+        op.st(i, in, xa, ya);
+    }
+    __device__ __forceinline__ void finalize(const double* d) { op.finalize(d); }
+};
 
 // ----------------------------------------------------------------------------- small kernels
 template <class F>
@@ -489,6 +508,7 @@ struct PhaseA {
     int first;
     Fin fin;
     double alpha, beta, omega;
+    static constexpr int ND = 4;
     static constexpr int NIN = 8;
     __device__ __forceinline__ void load() { alpha = scal[0]; beta = scal[1]; omega = scal[2]; }
     __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
@@ -525,6 +545,7 @@ struct PhaseB {
     const double* scal;
     Fin fin;
     double alpha, omega;
+    static constexpr int ND = 3;
     static constexpr int NIN = 7;
     __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
     __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
@@ -550,6 +571,7 @@ struct DotsOp {
     const double* a[4];
     const double* b[4];
     Fin fin;
+    static constexpr int ND = D;
     static constexpr int NIN = 2 * D;
     __device__ __forceinline__ void load() {}
     __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {

@@ -1,0 +1,94 @@
+"""Pins of the comparators for the paper's central claim: p-BiCGStab with ordinary
+FP64 dots (a fixed reduction tree) and p-BiCGStab with residual replacement.
+
+* The FP64 tree dot is exact on small integers, obeys the gamma_n bound, and its
+  association order is pinned by hand-worked inputs (2^53 + 1 rounds to 2^53).
+* Residual replacement does not change the iterates in exact arithmetic, so the FP64
+  run with replacement must still track the rational Algorithm 2 (as the plain run
+  does); a planted mistake in the replacement is caught by the same check.
+* The ordinary-dot run tracks the rational iterates too (its dots differ from exact by
+  a few ulps), and passing the exact dot in its place reproduces the exact run bit for
+  bit (the plumbing of recurrence dots vs. the exact ||b|| / true residual).
+"""
+import numpy as np
+import pytest
+
+import synthgen as g
+from oracle import ctier, rational, solvers
+from tests.test_oracle_mutations import _mutant
+from tests.test_oracle_solvers import small_unsym
+
+U64 = 2.0 ** -53
+
+
+@pytest.mark.parametrize("n", [0, 1, 64, 4097, 70000, 1_500_000])
+def test_f64_tree_dot_exact_on_integers(n):
+    rng = np.random.default_rng(n + 7)
+    a = rng.integers(-1000, 1001, n).astype(np.float64)
+    b = rng.integers(-1000, 1001, n).astype(np.float64)
+    assert solvers.dot_f64_tree(a, b) == float(np.dot(a.astype(np.int64), b.astype(np.int64)))
+
+
+def test_f64_tree_dot_bound_and_order():
+    rng = np.random.default_rng(3)
+    n = 200000
+    a, b = rng.standard_normal(n), rng.standard_normal(n)
+    exact = ctier.exact_dot(a, b)
+    gam = n * U64 / (1 - n * U64)
+    assert abs(solvers.dot_f64_tree(a, b) - exact) <= gam * float(np.dot(np.abs(a), np.abs(b)))
+    big = 2.0 ** 53
+    x = np.zeros(4096)
+    x[0], x[1], x[32] = big, 1.0, -big       # lanes 0 and 32 meet first in the butterfly
+    assert solvers.dot_f64_tree(x, np.ones(4096)) == 1.0
+    x = np.zeros(4096)
+    x[0], x[512], x[1024] = big, 1.0, -big   # one lane's own elements, in index order
+    assert solvers.dot_f64_tree(x, np.ones(4096)) == 0.0
+
+
+def _tracks(kw, tol=1e-12, dot=None):
+    for seed in range(4):
+        A, D, b = small_unsym(seed, n=8, diag=12.0)
+        xs = rational.pbicgstab_q(A, b, 6)
+        res = solvers.pbicgstab(A, b, tol=0.0, max_iter=len(xs), record=len(xs), dot=dot, **kw)
+        if len(res.iterates) != len(xs):
+            return False
+        for (xf, _, _, _), xq in zip(res.iterates, xs):
+            xq = np.array([float(v) for v in xq])
+            if not np.linalg.norm(xf - xq) <= tol * np.linalg.norm(xq):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("period", [1, 2, 3])
+def test_replacement_tracks_rational(period):
+    assert _tracks({"rr_period": period})
+
+
+def test_replacement_mutation_caught():
+    bad = _mutant(solvers.pbicgstab, "            z = op.apply(s)\n            v = op.apply(z)\n",
+                  "            z = op.apply(p)\n            v = op.apply(z)\n")
+    ok = True
+    for seed in range(4):
+        A, D, b = small_unsym(seed, n=8, diag=12.0)
+        xs = rational.pbicgstab_q(A, b, 6)
+        res = bad(A, b, tol=0.0, max_iter=len(xs), record=len(xs), rr_period=2)
+        for (xf, _, _, _), xq in zip(res.iterates, xs):
+            xq = np.array([float(v) for v in xq])
+            ok = ok and np.linalg.norm(xf - xq) <= 1e-12 * np.linalg.norm(xq)
+    assert not ok
+
+
+def test_plain_dots_track_rational():
+    assert _tracks({"exact_dot": None}, tol=1e-11, dot=solvers.dot_f64_tree)
+
+
+def test_plain_dot_plumbing():
+    """dot = exact dot in the plain slot reproduces the exact run bit for bit."""
+    p = g.problem("cd2d_64", scale=24)
+    ex = solvers.pbicgstab(p.A, p.b, tol=1e-10)
+    same = solvers.pbicgstab(p.A, p.b, tol=1e-10, dot=solvers.default_dot(p.A.n),
+                             exact_dot=solvers.default_dot(p.A.n))
+    assert ex.iterations == same.iterations and np.array_equal(ex.x, same.x)
+    pl = solvers.pbicgstab(p.A, p.b, tol=1e-10, dot=solvers.dot_f64_tree, exact_dot=solvers.default_dot(p.A.n))
+    assert pl.status == solvers.OK and pl.true_relres <= 1e-10
+    assert np.linalg.norm(pl.x - ex.x) <= 1e-8 * np.linalg.norm(ex.x)

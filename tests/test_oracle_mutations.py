@@ -89,8 +89,8 @@ def test_mutated_tree_dot_order_is_caught():
     a[0], a[1], a[32] = big, 1.0, -big
     b = np.ones(4096, dtype=np.float32)
     assert solvers.dot_f32_tree(a, b) == 1.0
-    bad = _mutant(solvers.dot_f32_tree, "for o in (32, 16, 8, 4, 2, 1):", "for o in (1, 2, 4, 8, 16, 32):")
-    assert bad(a, b) != 1.0
+    bad = _mutant(solvers._tree_dot, "for o in (32, 16, 8, 4, 2, 1):", "for o in (1, 2, 4, 8, 16, 32):")
+    assert bad(a, b, np.float32) != 1.0
 
 
 @pytest.mark.parametrize("old,new", [
