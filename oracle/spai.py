@@ -195,6 +195,13 @@ def infer_bf16(A, theta, phi=None):
     """Weights and layer inputs rounded to bf16, products accumulated in float64 here
     (the GPU accumulates in float32 in its own order), GELU on the accumulated values."""
     phi = features(A) if phi is None else phi
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr.astype(np.int64)))
+    return infer_bf16_values(theta, phi, A.diag()[rows])
+
+
+def infer_bf16_values(theta, phi, a_ii):
+    """The bf16 inference of ``infer_bf16`` for given feature rows phi (k x 12) and the
+    diagonal entry a_ii of each one's row (any subset of the nonzeros)."""
     W1, b1, W2, b2, w3, b3 = [np.asarray(t, dtype=np.float32) for t in unpack(theta)]
     x0 = to_bf16(phi.astype(np.float32)).astype(np.float64)
     z1 = x0 @ to_bf16(W1).astype(np.float64).T + b1
@@ -202,8 +209,7 @@ def infer_bf16(A, theta, phi=None):
     z2 = h1 @ to_bf16(W2).astype(np.float64).T + b2
     h2 = to_bf16(gelu(z2).astype(np.float32)).astype(np.float64)
     f = h2 @ to_bf16(w3).astype(np.float64) + float(b3)
-    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr.astype(np.int64)))
-    return (phi[:, 10] + f) / A.diag()[rows]
+    return (phi[:, 10] + f) / a_ii
 
 
 # ------------------------------------------------------------------ probe blocks
