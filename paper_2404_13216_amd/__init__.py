@@ -204,6 +204,31 @@ def csr_spmv_f32(A: CSR, x, y=None):
     return y
 
 
+def csr_validate(A) -> None:
+    """Host-side structural check of a CSR (a synthgen.CSR or a device CSR, copied to the
+    host): row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz < 2^31; columns in [0, n)
+    and strictly ascending within every row.  Raises ValueError.  The kernels take the
+    column ranges on trust; this is the check to run on untrusted input."""
+    rp = A.row_ptr.cpu().numpy() if hasattr(A.row_ptr, "cpu") else np.asarray(A.row_ptr)
+    ci = A.col_idx.cpu().numpy() if hasattr(A.col_idx, "cpu") else np.asarray(A.col_idx)
+    n = int(A.n)
+    rp = rp.astype(np.int64)
+    ci = ci.astype(np.int64)
+    if rp.shape != (n + 1,) or rp[0] != 0:
+        raise ValueError("row_ptr must have n + 1 entries starting at 0")
+    if np.any(np.diff(rp) < 0):
+        raise ValueError("row_ptr must be non-decreasing")
+    if rp[-1] != ci.size or ci.size >= 2 ** 31:
+        raise ValueError("row_ptr[n] must equal nnz (< 2^31)")
+    if ci.size and (ci.min() < 0 or ci.max() >= n):
+        raise ValueError("column index out of range")
+    if ci.size > 1:
+        same_row = np.repeat(np.arange(n), np.diff(rp))
+        d = np.diff(ci)
+        if np.any((d <= 0) & (same_row[1:] == same_row[:-1])):
+            raise ValueError("columns must be strictly ascending within a row")
+
+
 def jacobi(A: CSR, dtype=None) -> CSR:
     """Diagonal right preconditioner M = diag(1/a_ii) as a CSR with one entry per row;
     the values come from csr_jacobi (FP64 reciprocal rounded once to `dtype`)."""

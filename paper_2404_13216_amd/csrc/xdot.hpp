@@ -184,41 +184,44 @@ __device__ __forceinline__ double row_sum_d(double v) {
 }
 
 // Exact deposit of one double per lane (zeros ignored), reduced per row of 16 lanes.
-// All 64 lanes of the wave must call it together.  A row's values whose 32-bit chunk
-// index is within one of the row's smallest are cut at that chunk into four signed
-// 32-bit pieces; the pieces are summed across the row in FP64 (at most 16 integers
-// below 2^32: exact) and the row's leader adds the four sums into the accumulator.
-// Other values go through deposit_double.
+// All 64 lanes of the wave must call it together.  In each round, the row's pending
+// values whose 32-bit chunk index is within one of the smallest pending index are cut
+// at that chunk into four signed 32-bit pieces; the pieces are summed across the row
+// in FP64 (at most 16 integers below 2^32: exact) and the row's leader adds the four
+// sums into the accumulator.  The lane holding the smallest index always joins, so a
+// row needs at most 16 rounds; typically one or two.
 __device__ __forceinline__ void wave_deposit(unsigned long long* acc, double v) {
-    bool nz = v != 0.0;
-    if (__ballot(nz) == 0) return;
+    bool pending = v != 0.0;
+    if (__ballot(pending) == 0) return;
     uint64_t m = 0; int P = 0; bool neg = false;
-    if (nz) decompose(v, m, P, neg);
-    int c = nz ? (P >> 5) : 0x7fffffff;
-    const int cmin = row_min_i(c);
-    bool inwin = nz && (c - cmin) <= 1;
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-    if (inwin) {
-        int sh = P - 32 * cmin;                 // 0..63
-        uint64_t w0 = m << sh;
-        uint64_t w1 = sh ? (m >> (64 - sh)) : 0;
-        double sg = neg ? -1.0 : 1.0;
-        q0 = sg * (double)(w0 & 0xffffffffull);
-        q1 = sg * (double)(w0 >> 32);
-        q2 = sg * (double)(w1 & 0xffffffffull);
-        q3 = sg * (double)(w1 >> 32);
+    if (pending) decompose(v, m, P, neg);
+    const int c = pending ? (P >> 5) : 0x7fffffff;
+    while (__ballot(pending) != 0) {
+        const int cmin = row_min_i(pending ? c : 0x7fffffff);
+        const bool inwin = pending && (c - cmin) <= 1;
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+        if (inwin) {
+            int sh = P - 32 * cmin;                 // 0..63
+            uint64_t w0 = m << sh;
+            uint64_t w1 = sh ? (m >> (64 - sh)) : 0;
+            double sg = neg ? -1.0 : 1.0;
+            q0 = sg * (double)(w0 & 0xffffffffull);
+            q1 = sg * (double)(w0 >> 32);
+            q2 = sg * (double)(w1 & 0xffffffffull);
+            q3 = sg * (double)(w1 >> 32);
+        }
+        q0 = row_sum_d(q0);
+        q1 = row_sum_d(q1);
+        q2 = row_sum_d(q2);
+        q3 = row_sum_d(q3);
+        if ((threadIdx.x & 15) == 0 && cmin != 0x7fffffff) {
+            if (q0 != 0.0) atomicAdd(acc + cmin, (unsigned long long)(long long)q0);
+            if (q1 != 0.0) atomicAdd(acc + cmin + 1, (unsigned long long)(long long)q1);
+            if (q2 != 0.0) atomicAdd(acc + cmin + 2, (unsigned long long)(long long)q2);
+            if (q3 != 0.0 && cmin + 3 < NCH) atomicAdd(acc + cmin + 3, (unsigned long long)(long long)q3);
+        }
+        pending = pending && !inwin;
     }
-    q0 = row_sum_d(q0);
-    q1 = row_sum_d(q1);
-    q2 = row_sum_d(q2);
-    q3 = row_sum_d(q3);
-    if ((threadIdx.x & 15) == 0 && cmin != 0x7fffffff) {
-        if (q0 != 0.0) atomicAdd(acc + cmin, (unsigned long long)(long long)q0);
-        if (q1 != 0.0) atomicAdd(acc + cmin + 1, (unsigned long long)(long long)q1);
-        if (q2 != 0.0) atomicAdd(acc + cmin + 2, (unsigned long long)(long long)q2);
-        if (q3 != 0.0 && cmin + 3 < NCH) atomicAdd(acc + cmin + 3, (unsigned long long)(long long)q3);
-    }
-    if (nz && !inwin) deposit_double(acc, v);
 }
 
 // ------------------------------------------------------------------------------

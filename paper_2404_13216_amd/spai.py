@@ -115,6 +115,35 @@ def init_params(seed: int, device="cuda"):
     return torch.from_numpy(th.astype(np.float32)).to(device)
 
 
+LAYOUT = "W1[64x12] row-major, b1[64], W2[64x64] row-major, b2[64], w3[64], b3 (float32)"
+
+
+def save_params(path: str, params) -> str:
+    """Write trained parameters to an .npz with their layout and the SHA-256 of the
+    float32 bytes; returns the digest."""
+    import hashlib
+    th = np.ascontiguousarray(params.detach().cpu().numpy() if hasattr(params, "detach") else params,
+                              dtype=np.float32)
+    if th.shape != (NPARAM,):
+        raise ValueError(f"expected {NPARAM} parameters")
+    digest = hashlib.sha256(th.tobytes()).hexdigest()
+    np.savez(path, params=th, layout=np.array(LAYOUT), sha256=np.array(digest))
+    return digest
+
+
+def load_params(path: str, device="cuda"):
+    """Read parameters written by save_params; the digest and layout must match."""
+    import hashlib
+    with np.load(path, allow_pickle=False) as z:
+        th = np.ascontiguousarray(z["params"], dtype=np.float32)
+        digest, layout = str(z["sha256"]), str(z["layout"])
+    if layout != LAYOUT or th.shape != (NPARAM,):
+        raise ValueError("parameter file has a different layout")
+    if hashlib.sha256(th.tobytes()).hexdigest() != digest:
+        raise ValueError("parameter file checksum mismatch")
+    return _torch().from_numpy(th).to(device)
+
+
 def probe_block(A: CSR, b, seed: int, k_rad=4, steps=(1, 4, 16, 64)):
     """V = [Rademacher columns | r_i / ||r_i|| of plain p-BiCGStab at the given iterations]
     as an n x k torch tensor (float32).  Residuals come from the GPU solver (r_out)."""

@@ -286,6 +286,37 @@ def training_problem(seed: int, N: int | None = None) -> Problem:
     return Problem(f"train_{seed}", A, xstar, _rhs(A, xstar), p)
 
 
+def save_problem(path: str, prob: Problem) -> str:
+    """Cache a generated problem as .npz with the SHA-256 of its arrays; returns it."""
+    import hashlib
+    import json
+    arrays = {"row_ptr": prob.A.row_ptr, "col_idx": prob.A.col_idx, "val": prob.A.val,
+              "xstar": prob.xstar, "b": prob.b}
+    h = hashlib.sha256()
+    for k in sorted(arrays):
+        h.update(np.ascontiguousarray(arrays[k]).tobytes())
+    digest = h.hexdigest()
+    meta = json.dumps({"name": prob.name, "n": prob.A.n, "meta": prob.meta}, default=float)
+    np.savez(path, **arrays, meta=np.array(meta), sha256=np.array(digest))
+    return digest
+
+
+def load_problem(path: str) -> Problem:
+    """Load a problem written by save_problem, verifying its checksum."""
+    import hashlib
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        arrays = {k: z[k] for k in ("row_ptr", "col_idx", "val", "xstar", "b")}
+        digest, meta = str(z["sha256"]), json.loads(str(z["meta"]))
+    h = hashlib.sha256()
+    for k in sorted(arrays):
+        h.update(np.ascontiguousarray(arrays[k]).tobytes())
+    if h.hexdigest() != digest:
+        raise ValueError(f"{path}: checksum mismatch")
+    A = CSR(int(meta["n"]), arrays["row_ptr"], arrays["col_idx"], arrays["val"])
+    return Problem(meta["name"], A, arrays["xstar"], arrays["b"], meta["meta"])
+
+
 def rademacher(n: int, k: int, seed: int) -> np.ndarray:
     """n x k column-major (Fortran order) block of +-1 probes."""
     rng = np.random.default_rng(seed)
