@@ -99,6 +99,14 @@ typedef struct {
                                   the p-BiCGStabRR variant): r = b - A x, w = A r, t = A w,
                                   s = A p, z = A s, v = A z; scalars kept.  FP64 p-BiCGStab
                                   without M only.  0: none                                    */
+    int32_t true_every;        /* > 0 with true_history: after every true_every-th completed
+                                  iteration i that the solve continues from, the true relative
+                                  residual ||b - A x_i||/||b|| (exact dot) is written to
+                                  true_history[i / true_every - 1] (FP64 p-BiCGStab without
+                                  M; the iterates are not affected) -- the recursive / true
+                                  residual gap                                                */
+    int32_t true_history_len;  /* entries available in true_history                        */
+    double* true_history;      /* optional device buffer                                     */
 } pbcg_opts;
 
 /* Result summary (host struct). */

@@ -61,6 +61,7 @@ class Result:
     iterates: list = dataclasses.field(default_factory=list)  # (x, r, alpha, omega) per iteration
     outer_iterations: int = 0
     fell_back: int = 0
+    true_history: list = dataclasses.field(default_factory=list)
 
 
 def default_dot(n: int):
@@ -96,7 +97,7 @@ def _true_relres(A, b, x, normb, dot, spmv):
 
 
 def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=None,
-              record=0, stall_window=0, exact_dot=None, rr_period=0) -> Result:
+              record=0, stall_window=0, exact_dot=None, rr_period=0, true_every=0) -> Result:
     """p-BiCGStab, Algorithm 2, with the readings in the module docstring.
 
     With ``M`` (a CSR right preconditioner) the recurrences run on A.M and y,
@@ -108,6 +109,8 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     ``rr_period`` > 0: residual replacement (the p-BiCGStabRR variant the paper refers
     to) after every rr_period-th completed iteration: r = b - A x, w = A r, t = A w,
     s = A p, z = A s, v = A z, with the scalars kept (unpreconditioned only).
+    ``true_every`` > 0: after every true_every-th completed iteration the solve
+    continues from, the true relative residual is appended to ``true_history``.
     """
     spmv = spmv or _spmv
     n = A.n
@@ -121,11 +124,13 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         raise ValueError("right-preconditioned solve starts from y0 = 0")
     y = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
 
+    true_hist = []
+
     def finish(status, iters, rec, hist, its, checks, true=None):
         x = op.to_x(y)
         if true is None:
             true = _true_relres(A, b, x, normb, xdot, spmv) if normb > 0 else 0.0
-        return Result(x, status, iters, true, rec, checks, hist, its)
+        return Result(x, status, iters, true, rec, checks, hist, its, true_history=true_hist)
 
     nb2 = xdot(b, b)
     if not math.isfinite(nb2):
@@ -207,6 +212,10 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         if stall_window and len(hist) > stall_window and rec > 0.5 * hist[-1 - stall_window]:
             return finish(STALLED, i + 1, rec, hist, its, checks)
         alpha, rho = alpha_new, rho_new
+        if i + 1 == max_iter:          # the solve does not continue from the last iteration
+            break
+        if true_every and (i + 1) % true_every == 0:
+            true_hist.append(_true_relres(A, b, op.to_x(y), normb, xdot, spmv))
         if rr_period and (i + 1) % rr_period == 0:
             r = b - spmv(A, y)
             w = op.apply(r)

@@ -42,7 +42,9 @@ class PbcgOpts(ctypes.Structure):
                 ("history_len", ctypes.c_int32), ("history", _P), ("r_out", _P),
                 ("batch", ctypes.c_int32), ("stall_window", ctypes.c_int32),
                 ("spmv_kind", ctypes.c_int32), ("trace", ctypes.c_int32),
-                ("dots", ctypes.c_int32), ("rr_period", ctypes.c_int32)]
+                ("dots", ctypes.c_int32), ("rr_period", ctypes.c_int32),
+                ("true_every", ctypes.c_int32), ("true_history_len", ctypes.c_int32),
+                ("true_history", ctypes.c_void_p)]
 
 
 class PbcgInfo(ctypes.Structure):
@@ -320,6 +322,12 @@ class Solver:
             self.history = torch.full((history,), float("nan"), dtype=torch.float64, device=A.val.device)
             self.opts.history = self.history.data_ptr()
             self.opts.history_len = history
+        self.true_history = None
+        if self.opts.true_every > 0:
+            cap = max(self.opts.max_iter // self.opts.true_every, 1)
+            self.true_history = torch.full((cap,), float("nan"), dtype=torch.float64, device=A.val.device)
+            self.opts.true_history = self.true_history.data_ptr()
+            self.opts.true_history_len = cap
         nb = lib().pbicgstab_workspace_bytes(A.n, A.nnz, ctypes.byref(self.opts))
         self.ws = _workspace(nb, A.val.device)
 
@@ -343,4 +351,7 @@ def solve(A: CSR, b, x0=None, M: CSR | None = None, history: int = 0, **opts):
     x, info = s.solve(b, x)
     if history:
         info["history"] = s.history[: info["iterations"]].cpu().numpy()
+    if s.true_history is not None:
+        th = s.true_history.cpu().numpy()
+        info["true_history"] = th[~np.isnan(th)]
     return x, info

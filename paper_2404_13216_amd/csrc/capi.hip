@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int n, const int* __restric
 
 extern "C" {
 
-int pbcg_abi_version(void) { return 3; }
+int pbcg_abi_version(void) { return 4; }
 
 const char* pbcg_status_string(int status) {
     switch (status) {
@@ -589,13 +589,13 @@ struct Driver {
     }
 
     // true residual of the current iterate (x = M y with a preconditioner) -> st->true_rel
-    void true_residual_enqueue() {
+    void true_residual_enqueue(int count = 1) {
         const double* xt = x;
         if (M) {
             launch_spmv64(M, x, EpiStore<double>{W.tmp2}, nullptr, s, kind);
             xt = W.tmp2;
         }
-        EpiResidDot<FinTrue> epi{b, W.tmp, FinTrue{W.st}};
+        EpiResidDot<FinTrue> epi{b, W.tmp, FinTrue{W.st, count}};
         launch_spmv_dot<1>(A, xt, epi, W.site, nullptr, s, kind);
     }
 
@@ -650,6 +650,19 @@ struct Driver {
         op(W.z, W.v, fa, seen);           // v = A z; omega is finalized by its block 0
         auto fb = launch_ew_dot_deferred<3, DOT_GRID_DEFAULT>(pb, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
         op(W.w, W.t, fb, seen);           // t = A w; beta, alpha finalized by its block 0
+    }
+
+    // After completed iteration `it` (skipped if it halted): the periodic true residual
+    // for the history, then the residual replacement.
+    void enqueue_after_iteration(long long it) {
+        if (o->true_every > 0 && o->true_history && it % o->true_every == 0) {
+            const long long k = it / o->true_every - 1;
+            if (k < o->true_history_len) {
+                EpiResidDot<FinTrueHist> epi{b, W.tmp, FinTrueHist{W.st, o->true_history + k}};
+                launch_spmv_dot<1>(A, x, epi, W.site, halt, s, kind);
+            }
+        }
+        if (o->rr_period > 0 && it % o->rr_period == 0) enqueue_replacement();
     }
 
     // Residual replacement after a completed iteration (skipped if the iteration halted):
@@ -738,7 +751,7 @@ struct Driver {
                 else enqueue_iteration_p(first);
                 first = false;
                 ++it_enq;
-                if (o->rr_period > 0 && it_enq % o->rr_period == 0) enqueue_replacement();
+                if (!bicg) enqueue_after_iteration(it_enq);
             }
             HIPCHK(hipGetLastError());
             const int slot = batches & 1;
@@ -757,8 +770,8 @@ struct Driver {
                     polled = batches;
                     enqueued = h.iter;  // batches queued behind the halt were no-ops
                     it_enq = h.iter;
-                    // the replacement after the halted iteration was skipped with it
-                    if (o->rr_period > 0 && h.iter > 0 && h.iter % o->rr_period == 0) enqueue_replacement();
+                    // the work after the halted iteration was skipped with it
+                    if (!bicg && h.iter > 0) enqueue_after_iteration(h.iter);
                 }
             }
         }
@@ -971,6 +984,10 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     if (opts->spmv_kind < PBCG_SPMV_SEQ || opts->spmv_kind > PBCG_SPMV_WAVE) return PBCG_ERR_INVALID;
     if (opts->dots != PBCG_DOTS_EXACT && opts->dots != PBCG_DOTS_PLAIN) return PBCG_ERR_INVALID;
     if (opts->rr_period < 0) return PBCG_ERR_INVALID;
+    if (opts->true_every < 0 || (opts->true_history && opts->true_history_len < 0)) return PBCG_ERR_INVALID;
+    if (opts->true_every > 0 && opts->true_history &&
+        (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || opts->prec != PBCG_PREC_FP64))
+        return PBCG_ERR_INVALID;
     if ((opts->dots == PBCG_DOTS_PLAIN || opts->rr_period > 0) &&
         (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || opts->prec != PBCG_PREC_FP64))
         return PBCG_ERR_INVALID;
@@ -1017,7 +1034,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         const bool have_true = (opts->prec == PBCG_PREC_FP32_IR && !fell_back) ||
                                (status == PBCG_OK && (h.reason & (R_CHECK | R_YYZERO)));
         if (!have_true && !(h.reason & R_ZERO_RHS)) {
-            D.true_residual_enqueue();
+            D.true_residual_enqueue(0);   // the reported value, not a stopping test
         }
         if (D.M) {  // x = M y
             launch_spmv64(D.M, x, EpiStore<double>{W.tmp2}, nullptr, D.s, D.kind);

@@ -709,10 +709,18 @@ struct FinIR {
 // true residual: (res,res) -> true_rel
 struct FinTrue {
     State* st;
+    int count;   // 1: a stopping test (counted in true_checks); 0: the final report
     __device__ void operator()(const double* d) const {
         st->true_rel = sqrt(d[0]) / st->normb;
-        st->true_checks += 1;
+        st->true_checks += count;
     }
+};
+
+// true residual for the history: out = sqrt((res,res)) / ||b||, the state untouched
+struct FinTrueHist {
+    const State* st;
+    double* out;
+    __device__ void operator()(const double* d) const { *out = sqrt(d[0]) / st->normb; }
 };
 
 // epilogue for res = b - A x with the dot (res,res)

@@ -51,3 +51,20 @@ def test_comparator_invalid_combinations():
                {"dots": 7}, {"rr_period": -1}):
         with pytest.raises(pk.LibError):
             pk.solve(A, b, **kw)
+
+
+@pytest.mark.parametrize("name,scale", [("cd2d_64", None), ("cd3d_128", 24)])
+@pytest.mark.parametrize("dots", [pk.DOTS_EXACT, pk.DOTS_PLAIN])
+def test_true_history_bitwise(name, scale, dots):
+    """The recursive / true residual gap past the attainable accuracy (tol 1e-13): the
+    true residual every 10 iterations, bit for bit with the oracle."""
+    p = g.problem(name, scale=scale)
+    ex = solvers.default_dot(p.A.n)
+    dot = solvers.dot_f64_tree if dots == pk.DOTS_PLAIN else ex
+    ref = solvers.pbicgstab(p.A, p.b, tol=1e-13, max_iter=300, dot=dot, exact_dot=ex, true_every=10)
+    x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), tol=1e-13, max_iter=300, dots=dots, true_every=10,
+                       history=300)
+    assert info["iterations"] == ref.iterations and info["true_checks"] == ref.true_checks
+    assert len(info["true_history"]) == len(ref.true_history) > 0
+    assert np.array_equal(bits(info["true_history"]), bits(ref.true_history))
+    assert np.array_equal(bits(info["history"]), bits(ref.history))
