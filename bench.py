@@ -174,15 +174,32 @@ def config_leg(pk, torch, g, dev, name, reps):
 def claim_leg(pk, torch, A, b, n):
     """The paper's central comparison on the benchmark matrix: exact vs ordinary FP64
     dots, without and with residual replacement (period 50), at the benchmark tolerance
-    1e-10 and at 1e-13 (below what the recurrences sustain); iteration cap 1500."""
+    1e-10 and at 1e-13 (below what the recurrences sustain); iteration cap 1500.  For
+    the 1e-13 runs the true residual is recorded every 10 iterations (bit-identical to
+    the oracle's) and its minimum is reported: the attainable accuracy."""
     out = {}
     for tol in (1e-10, 1e-13):
         for label, dots, rr in (("exact", pk.DOTS_EXACT, 0), ("plain", pk.DOTS_PLAIN, 0),
                                 ("exact_rr50", pk.DOTS_EXACT, 50), ("plain_rr50", pk.DOTS_PLAIN, 50)):
-            t, info, _ = timed_solve(pk, torch, A, b, 1, tol=tol, max_iter=1500, dots=dots, rr_period=rr)
-            out[f"{label}_tol{tol:g}"] = {"seconds": t, "status": info["status"], "iterations": info["iterations"],
-                                         "true_checks": info["true_checks"], "true_relres": info["true_relres"],
-                                         "rec_relres": info["rec_relres"]}
+            every = 10 if tol < 1e-12 else 0
+            solver = pk.Solver(A, tol=tol, max_iter=1500, dots=dots, rr_period=rr, true_every=every)
+            x = torch.zeros(n, dtype=torch.float64, device=b.device)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = solver.solve(b, x)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+            row = {"seconds": t, "status": info["status"], "iterations": info["iterations"],
+                   "true_checks": info["true_checks"], "true_relres": info["true_relres"],
+                   "rec_relres": info["rec_relres"]}
+            if every:
+                th = solver.true_history.cpu().numpy()
+                th = th[~np.isnan(th)]
+                if th.size:
+                    k = int(np.argmin(th))
+                    row["min_true_relres"] = float(th[k])
+                    row["min_true_at_iteration"] = (k + 1) * every
+            out[f"{label}_tol{tol:g}"] = row
     log("claim:", json.dumps(out))
     return out
 

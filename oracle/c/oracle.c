@@ -208,7 +208,27 @@ void ora_spmv(int32_t n, const int32_t* rp, const int32_t* ci, const double* val
     }
 }
 
-enum { S_OK = 0, S_NOT_CONVERGED = 1, S_BREAKDOWN = 2, S_ERR_NONFINITE = -3 };
+enum { S_OK = 0, S_NOT_CONVERGED = 1, S_BREAKDOWN = 2, S_STAGNATED = 3, S_ERR_NONFINITE = -3 };
+
+/* The stopping test: the true residual is tested when rec <= tol and rec has at least
+ * halved since the last failed test, or (once a test has failed) 50 iterations after
+ * the last failed one; a failed
+ * test below 0.9 x the best failed one becomes the best (its iterate is kept in xb);
+ * three failed tests in a row without that mean stagnation. */
+typedef struct { double lim, best; int stag, it_fail; double* xb; } true_test;
+static int tt_due(const true_test* t, double rec, double tol, int it) {
+    return (rec <= tol && rec <= t->lim) || (t->it_fail >= 0 && it - t->it_fail >= 50);
+}
+static int tt_failed(true_test* t, double rec, double tr, int it, const double* x, int32_t n) {
+    t->lim = 0.5 * rec;
+    t->it_fail = it;
+    if (tr < 0.9 * t->best) {
+        t->best = tr; t->stag = 0;
+        memcpy(t->xb, x, sizeof(double) * (size_t)n);
+        return 0;
+    }
+    return ++t->stag >= 3;
+}
 
 typedef struct {
     int32_t status, iterations, true_checks, pad;
@@ -231,7 +251,7 @@ int ora_pbicgstab(int32_t n, const int32_t* rp, const int32_t* ci, const double*
                   const double* b, double* x, double tol, int32_t max_iter,
                   ora_info* info, double* hist) {
     ALLOCV(r); ALLOCV(rh); ALLOCV(w); ALLOCV(t); ALLOCV(p); ALLOCV(s); ALLOCV(z);
-    ALLOCV(q); ALLOCV(y); ALLOCV(v); ALLOCV(tmp);
+    ALLOCV(q); ALLOCV(y); ALLOCV(v); ALLOCV(tmp); ALLOCV(xbest);
     int status = S_NOT_CONVERGED, iters = 0, checks = 0;
     double rec = NAN, tr = NAN;
     double nb2 = ora_exact_dot(b, b, n);
@@ -249,10 +269,15 @@ int ora_pbicgstab(int32_t n, const int32_t* rp, const int32_t* ci, const double*
     double rho = ora_exact_dot(rh, r, n);
     double rw = ora_exact_dot(rh, w, n);
     rec = sqrt(ora_exact_dot(r, r, n)) / normb;
-    if (rec <= tol) {
+    true_test tt = {INFINITY, INFINITY, 0, -1, xbest};
+    if (tt_due(&tt, rec, tol, 0)) {
         checks++;
         tr = true_relres(n, rp, ci, val, b, x, normb, tmp);
         if (tr <= tol) { status = S_OK; goto done_tr; }
+        if (tt_failed(&tt, rec, tr, 0, x, n)) {
+            memcpy(x, xbest, sizeof(double) * (size_t)n);
+            tr = tt.best; status = S_STAGNATED; goto done_tr;
+        }
     }
     if (!isfinite(rho) || !isfinite(rw)) { status = S_ERR_NONFINITE; goto done; }
     if (rw == 0.0) { status = S_BREAKDOWN; goto done; }
@@ -306,10 +331,14 @@ int ora_pbicgstab(int32_t n, const int32_t* rp, const int32_t* ci, const double*
         beta = ((alpha / omega) * rho_new) / rho;
         double den = (rw + beta * rs) - (beta * omega) * rz;
         double alpha_new = den != 0.0 ? rho_new / den : NAN;
-        if (rec <= tol) {
+        if (tt_due(&tt, rec, tol, it + 1)) {
             checks++;
             tr = true_relres(n, rp, ci, val, b, x, normb, tmp);
             if (tr <= tol) { status = S_OK; goto done_tr; }
+            if (tt_failed(&tt, rec, tr, it + 1, x, n)) {
+                memcpy(x, xbest, sizeof(double) * (size_t)n);
+                tr = tt.best; status = S_STAGNATED; goto done_tr;
+            }
         }
         if (!isfinite(rho_new) || !isfinite(rw) || !isfinite(rr) || !isfinite(beta) ||
             (den != 0.0 && !isfinite(alpha_new))) { status = S_ERR_NONFINITE; goto done; }
@@ -325,7 +354,7 @@ done_tr:
         info->status = status; info->iterations = iters; info->true_checks = checks;
         info->true_relres = tr; info->rec_relres = rec;
     }
-    free(r); free(rh); free(w); free(t); free(p); free(s); free(z); free(q); free(y); free(v); free(tmp);
+    free(r); free(rh); free(w); free(t); free(p); free(s); free(z); free(q); free(y); free(v); free(tmp); free(xbest);
     return status;
 }
 
@@ -333,7 +362,7 @@ done_tr:
 int ora_bicgstab(int32_t n, const int32_t* rp, const int32_t* ci, const double* val,
                  const double* b, double* x, double tol, int32_t max_iter,
                  ora_info* info, double* hist) {
-    ALLOCV(r); ALLOCV(rh); ALLOCV(p); ALLOCV(s); ALLOCV(q); ALLOCV(y); ALLOCV(tmp);
+    ALLOCV(r); ALLOCV(rh); ALLOCV(p); ALLOCV(s); ALLOCV(q); ALLOCV(y); ALLOCV(tmp); ALLOCV(xbest);
     int status = S_NOT_CONVERGED, iters = 0, checks = 0;
     double rec = NAN, tr = NAN;
     double nb2 = ora_exact_dot(b, b, n);
@@ -348,10 +377,15 @@ int ora_bicgstab(int32_t n, const int32_t* rp, const int32_t* ci, const double* 
     for (int32_t i = 0; i < n; ++i) { r[i] = b[i] - tmp[i]; rh[i] = r[i]; p[i] = r[i]; }
     double rho = ora_exact_dot(rh, r, n);
     rec = sqrt(ora_exact_dot(r, r, n)) / normb;
-    if (rec <= tol) {
+    true_test tt = {INFINITY, INFINITY, 0, -1, xbest};
+    if (tt_due(&tt, rec, tol, 0)) {
         checks++;
         tr = true_relres(n, rp, ci, val, b, x, normb, tmp);
         if (tr <= tol) { status = S_OK; goto done_tr; }
+        if (tt_failed(&tt, rec, tr, 0, x, n)) {
+            memcpy(x, xbest, sizeof(double) * (size_t)n);
+            tr = tt.best; status = S_STAGNATED; goto done_tr;
+        }
     }
     if (!isfinite(rho)) { status = S_ERR_NONFINITE; goto done; }
     for (int32_t it = 0; it < max_iter; ++it) {
@@ -389,10 +423,14 @@ int ora_bicgstab(int32_t n, const int32_t* rp, const int32_t* ci, const double* 
         if (hist) hist[it] = rec;
         iters = it + 1;
         double beta = ((alpha / omega) * rho_new) / rho;
-        if (rec <= tol) {
+        if (tt_due(&tt, rec, tol, it + 1)) {
             checks++;
             tr = true_relres(n, rp, ci, val, b, x, normb, tmp);
             if (tr <= tol) { status = S_OK; goto done_tr; }
+            if (tt_failed(&tt, rec, tr, it + 1, x, n)) {
+                memcpy(x, xbest, sizeof(double) * (size_t)n);
+                tr = tt.best; status = S_STAGNATED; goto done_tr;
+            }
         }
         if (!isfinite(rho_new) || !isfinite(rr) || !isfinite(beta)) { status = S_ERR_NONFINITE; goto done; }
         if (rho_new == 0.0) { status = S_BREAKDOWN; goto done; }
@@ -409,7 +447,7 @@ done_tr:
         info->status = status; info->iterations = iters; info->true_checks = checks;
         info->true_relres = tr; info->rec_relres = rec;
     }
-    free(r); free(rh); free(p); free(s); free(q); free(y); free(tmp);
+    free(r); free(rh); free(p); free(s); free(q); free(y); free(tmp); free(xbest);
     return status;
 }
 

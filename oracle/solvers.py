@@ -26,7 +26,11 @@ Readings of Algorithm 2 (p-BiCGStab) where the printed text is garbled or silent
 Stopping (the paper states tolerances but not the norm): after each iteration
 rec = sqrt((r, r)) / ||b||; when rec <= tol the true relative residual
 sqrt((b - A x, b - A x)) / ||b|| is computed and the solve stops if it is <= tol,
-otherwise it continues.  ``iterations`` counts completed loop bodies.
+otherwise it continues.  After a failed test the next one comes when rec has halved
+since it (and is <= tol) or 50 iterations have passed; three failed tests in a row that do not bring
+the true residual below 0.9 times the best failed one end the solve with STAGNATED
+(the recursive residual has left the true one behind), returning the iterate of the
+best failed test.  ``iterations`` counts completed loop bodies.
 
 Breakdowns (the paper is silent): ||b|| = 0 -> x = 0, OK; (r_hat, w_0) = 0 or an
 alpha denominator = 0 or rho = 0 or omega = 0 -> BREAKDOWN; (y, y) = 0 and
@@ -91,6 +95,34 @@ class _Operator:
         return y if self.M is None else self.spmv(self.M, y)
 
 
+class _TrueTest:
+    """When the true residual is tested, and when failed tests mean stagnation.
+
+    A test is due when rec <= tol and rec has halved since the last failed test, or
+    (once a test has failed) when 50 iterations have passed since the last failed one.  A failed test whose true residual is below
+    0.9 times the best failed one so far becomes the best (its iterate is kept);
+    three failed tests in a row without that mean stagnation, and the solve returns
+    the kept iterate."""
+
+    EVERY = 50
+
+    def __init__(self, tol):
+        self.tol, self.lim, self.best, self.stag, self.it_fail = tol, math.inf, math.inf, 0, -1
+        self.x_best = None
+
+    def due(self, rec, it):
+        return (rec <= self.tol and rec <= self.lim) or (self.it_fail >= 0 and it - self.it_fail >= self.EVERY)
+
+    def failed(self, rec, tr, it, x):
+        """Record a failed test at iteration it with iterate x; True on stagnation."""
+        self.lim, self.it_fail = 0.5 * rec, it
+        if tr < 0.9 * self.best:
+            self.best, self.stag, self.x_best = tr, 0, x.copy()
+            return False
+        self.stag += 1
+        return self.stag >= 3
+
+
 def _true_relres(A, b, x, normb, dot, spmv):
     res = b - spmv(A, x)
     return math.sqrt(dot(res, res)) / normb
@@ -147,11 +179,15 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     rw = dot(rhat, w)
     rec = math.sqrt(dot(r, r)) / normb
     hist, its, checks = [], [], 0
-    if rec <= tol:
+    test = _TrueTest(tol)
+    if test.due(rec, 0):
         checks += 1
         tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
         if tr <= tol:
             return finish(OK, 0, rec, hist, its, checks, tr)
+        if test.failed(rec, tr, 0, y):
+            y = test.x_best
+            return finish(STAGNATED, 0, rec, hist, its, checks, test.best)
     if not _finite(rho, rw):
         return finish(ERR_NONFINITE, 0, rec, hist, its, checks)
     if rw == 0.0:
@@ -199,11 +235,14 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         beta = ((alpha / omega) * rho_new) / rho
         den = (rw + beta * rs) - (beta * omega) * rz
         alpha_new = rho_new / den if den != 0.0 else math.nan
-        if rec <= tol:
+        if test.due(rec, i + 1):
             checks += 1
             tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
             if tr <= tol:
                 return finish(OK, i + 1, rec, hist, its, checks, tr)
+            if test.failed(rec, tr, i + 1, y):
+                y = test.x_best
+                return finish(STAGNATED, i + 1, rec, hist, its, checks, test.best)
         if not _finite(rho_new, rw, rr, beta) or (den != 0.0 and not math.isfinite(alpha_new)):
             return finish(ERR_NONFINITE, i + 1, rec, hist, its, checks)
         if rho_new == 0.0 or den == 0.0:
@@ -256,11 +295,15 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
     rho = dot(rhat, r)
     rec = math.sqrt(dot(r, r)) / normb
     hist, its, checks = [], [], 0
-    if rec <= tol:
+    test = _TrueTest(tol)
+    if test.due(rec, 0):
         checks += 1
         tr = _true_relres(A, b, x, normb, dot, spmv)
         if tr <= tol:
             return finish(OK, 0, rec, tr)
+        if test.failed(rec, tr, 0, x):
+            x = test.x_best
+            return finish(STAGNATED, 0, rec, test.best)
     if not math.isfinite(rho):
         return finish(ERR_NONFINITE, 0, rec)
     for i in range(max_iter):
@@ -296,11 +339,14 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
         if len(its) < record:
             its.append((x.copy(), r.copy(), alpha, omega))
         beta = ((alpha / omega) * rho_new) / rho
-        if rec <= tol:
+        if test.due(rec, i + 1):
             checks += 1
             tr = _true_relres(A, b, x, normb, dot, spmv)
             if tr <= tol:
                 return finish(OK, i + 1, rec, tr)
+            if test.failed(rec, tr, i + 1, x):
+                x = test.x_best
+                return finish(STAGNATED, i + 1, rec, test.best)
         if not _finite(rho_new, rr, beta):
             return finish(ERR_NONFINITE, i + 1, rec)
         if rho_new == 0.0:

@@ -282,6 +282,8 @@ struct FnInitState {
         memset(&z, 0, sizeof(z));
         z.tol = tol; z.max_iter = max_iter; z.hist = hist; z.hist_len = hist_len;
         z.stall_window = stall_window; z.stall_hist = stall_hist;
+        z.check_lim = __longlong_as_double(0x7ff0000000000000ll);   // +inf
+        z.check_it = -1;
         *st = z;
     }
 };
@@ -311,6 +313,10 @@ struct FnFIterPlus {       // (y, y) = 0: d = d + alpha p completed one more FP3
 struct FnScaleF {          // p = p * sigma (FP32)
     float* p; float sigma;
     __device__ void operator()(int64_t i) const { p[i] = p[i] * sigma; }
+};
+struct FnSetCheckLim {     // after a failed true-residual test
+    State* st; double lim; int it;
+    __device__ void operator()() const { st->check_lim = lim; st->check_it = it; }
 };
 struct FnResume {          // clear halt flags (host decided to continue)
     State* st;
@@ -522,7 +528,7 @@ struct Work {
     xd::Site site;
     FSite fsite;
     TSite<double> dsite;   // partials of the ordinary (plain) FP64 dots
-    double *rhat, *r, *w, *t, *p, *s, *z, *q, *y, *v, *tmp, *tmp2, *hist;
+    double *rhat, *r, *w, *t, *p, *s, *z, *q, *y, *v, *tmp, *tmp2, *xbest, *hist;   // xbest: best tested iterate
     float *r32, *rh32, *w32, *t32, *p32, *s32, *z32, *q32, *y32, *v32, *d32, *val32;
     size_t need;
     bool ok;
@@ -537,7 +543,7 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
     W.fsite.part = c.take<float>((size_t)DOT_GRID_MAX * 4);
     W.dsite.part = c.take<double>((size_t)DOT_GRID_MAX * 4);
     const size_t N = (size_t)std::max(n, 1);
-    double** v64[] = {&W.rhat, &W.r, &W.w, &W.t, &W.p, &W.s, &W.z, &W.q, &W.y, &W.v, &W.tmp, &W.tmp2};
+    double** v64[] = {&W.rhat, &W.r, &W.w, &W.t, &W.p, &W.s, &W.z, &W.q, &W.y, &W.v, &W.tmp, &W.tmp2, &W.xbest};
     for (double** pp : v64) *pp = c.take<double>(N);
     const bool need_hist = o && o->M && o->fallback;
     W.hist = need_hist ? c.take<double>((size_t)std::max(o->max_iter, 1)) : nullptr;
@@ -570,6 +576,8 @@ struct Driver {
     int fell_back = 0;     // a fallback (preconditioned) or an FP64 finish (refinement) ran
     int kind;              // SpMV kernel shape
     pbcg_csr A32;          // FP32 copy of A (refinement)
+    double fail_best = INFINITY;   // best true residual of a failed stopping test
+    int fail_stag = 0;             // failed tests in a row without improving on it
 
     // out = A in, or A (M in); `fin` (a pending dot-site finalize) rides on the first SpMV
     template <class Fin = NoFin>
@@ -613,6 +621,18 @@ struct Driver {
             true_residual_enqueue();
             if (sync_state(&h)) return PBCG_ERR_HIP;
             if (h.true_rel <= h.tol) return PBCG_OK;
+            // failed test: the next one when rec has halved, or 50 iterations on; a test
+            // below 0.9 x the best failed one keeps its iterate; three failed tests in a
+            // row without that: stagnation, and the kept iterate is returned
+            launch_single(FnSetCheckLim{W.st, 0.5 * h.rec, h.iter}, s);
+            if (h.true_rel < 0.9 * fail_best) {
+                fail_best = h.true_rel;
+                fail_stag = 0;
+                launch_ew(FnCopy{W.xbest, x}, n, nullptr, s);
+            } else if (++fail_stag >= 3) {
+                launch_ew(FnCopy{x, W.xbest}, n, nullptr, s);
+                return PBCG_STAGNATED;
+            }
         }
         if (reason & R_NONFINITE) return PBCG_ERR_NONFINITE;
         if (reason & R_YYZERO) {
@@ -690,6 +710,8 @@ struct Driver {
     // FP64 p-BiCGStab / BiCGStab on A (or A.M).  x: x0 in, iterate out (y with M).
     int run_fp64(State& h) {
         const int n = A->n;
+        fail_best = INFINITY;
+        fail_stag = 0;
         const bool bicg = o->alg == PBCG_ALG_BICGSTAB;
         double* hist = o->history;
         const int hist_len = hist ? o->history_len : 0;

@@ -611,6 +611,12 @@ struct FinNormB {
     }
 };
 
+// The stopping test is due when rec <= tol and rec has halved since the last failed
+// test, or (once a test has failed) 50 iterations after the last failed one.
+__device__ __forceinline__ bool true_test_due(const State* st, double rec, int it) {
+    return (rec <= st->tol && rec <= st->check_lim) || (st->check_it >= 0 && it - st->check_it >= 50);
+}
+
 // initial (r_hat, r0), (r_hat, w0), (r0, r0) -> rho, alpha0, rec
 struct FinInitP {
     State* st;
@@ -619,7 +625,7 @@ struct FinInitP {
         double rec = sqrt(rr) / st->normb;
         st->rec = rec; st->rho = rho; st->rw = rw;
         int reason = 0;
-        if (rec <= st->tol) reason |= R_CHECK;
+        if (true_test_due(st, rec, 0)) reason |= R_CHECK;
         if (!isfinite(rho) || !isfinite(rw)) reason |= R_NONFINITE;
         else if (rw == 0.0) reason |= R_BREAKDOWN;
         else st->alpha = rho / rw;
@@ -669,7 +675,7 @@ struct FinPhaseB {
         const double den = (rw + beta * st->rs) - (beta * omega) * st->rz;
         const double alpha_new = den != 0.0 ? rho_new / den : __longlong_as_double(0x7ff8000000000000ll);
         int reason = 0;
-        if (rec <= st->tol) reason |= R_CHECK;
+        if (true_test_due(st, rec, it)) reason |= R_CHECK;
         bool nonfin = !(isfinite(rho_new) && isfinite(rw) && isfinite(rr) && isfinite(beta)) ||
                       (den != 0.0 && !isfinite(alpha_new));
         if (nonfin) reason |= R_NONFINITE;
@@ -690,7 +696,7 @@ struct FinInitB {
         st->rec = rec; st->rho = rho;
         st->alpha = 0.0; st->beta = 0.0; st->omega = 0.0;
         int reason = 0;
-        if (rec <= st->tol) reason |= R_CHECK;
+        if (true_test_due(st, rec, 0)) reason |= R_CHECK;
         if (!isfinite(rho)) reason |= R_NONFINITE;
         if (reason) { st->halt = 1; st->reason |= reason; }
     }
@@ -786,7 +792,7 @@ struct FinBiCGStabXR {
         if (st->hist && it <= st->hist_len) st->hist[it - 1] = rec;
         const double beta = ((alpha / omega) * rho_new) / rho;
         int reason = 0;
-        if (rec <= st->tol) reason |= R_CHECK;
+        if (true_test_due(st, rec, it)) reason |= R_CHECK;
         if (!(isfinite(rho_new) && isfinite(rr) && isfinite(beta))) reason |= R_NONFINITE;
         else if (rho_new == 0.0) reason |= R_BREAKDOWN;
         else { st->beta = beta; st->rho = rho_new; }

@@ -167,3 +167,19 @@ def test_warm_start_exact_solution():
     x0 = torch.from_numpy(np.linalg.solve(p.A.to_scipy().toarray(), p.b)).to(dev())
     x, info = pk.solve(Ad, bd, x0=x0, tol=1e-10)
     assert info["status"] == pk.OK and info["iterations"] == 0
+
+
+@pytest.mark.parametrize("name,scale", [("cd2d_64", None), ("cd3d_128", 32), ("rand_1m", 20000)])
+def test_stagnation_rule_bitwise(name, scale):
+    """Tolerance 1e-14, below what p-BiCGStab's recurrences sustain: the failed true-residual
+    tests, the STAGNATED status and the returned (best tested) iterate match the oracle bit
+    for bit; BiCGStab reaches the tolerance on both sides."""
+    p = g.problem(name, scale=scale)
+    ora = ctier.pbicgstab(p.A, p.b, tol=1e-14, max_iter=3000)
+    x, info, _ = gpu_solve(p.A, p.b, tol=1e-14, max_iter=3000)
+    assert info["status"] == ora["status"] == pk.STAGNATED
+    assert info["iterations"] == ora["iterations"] and info["true_checks"] == ora["true_checks"]
+    assert np.array_equal(bits(x), bits(ora["x"])) and info["true_relres"] == ora["true_relres"]
+    orb = ctier.bicgstab(p.A, p.b, tol=1e-14, max_iter=3000)
+    xb, infob, _ = gpu_solve(p.A, p.b, tol=1e-14, max_iter=3000, alg=pk.ALG_BICGSTAB)
+    assert infob["status"] == orb["status"] == pk.OK and np.array_equal(bits(xb), bits(orb["x"]))

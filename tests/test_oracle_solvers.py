@@ -196,3 +196,23 @@ def test_right_preconditioned_jacobi_invariance():
     assert r1.status == r0.status == solvers.OK
     assert abs(r1.iterations - r0.iterations) <= 1
     assert np.linalg.norm(r1.x - r0.x) <= 1e-8 * np.linalg.norm(r0.x)
+
+
+@pytest.mark.parametrize("name,scale", [("cd2d_64", None), ("cd3d_128", 32), ("rand_1m", 20000)])
+def test_stagnation_rule_tiers_agree(name, scale):
+    """A tolerance below what p-BiCGStab's recurrences sustain (1e-14): failed true-residual
+    tests, then STAGNATED well before the iteration cap with the best tested iterate --
+    identically in the Python and C tiers.  BiCGStab reaches the same tolerance."""
+    p = g.problem(name, scale=scale)
+    dot = ctier.exact_dot   # the C tier's exact dot (bit-identical to tier 1, pinned above)
+    r1 = solvers.pbicgstab(p.A, p.b, tol=1e-14, max_iter=3000, dot=dot)
+    r2 = ctier.pbicgstab(p.A, p.b, tol=1e-14, max_iter=3000)
+    assert r1.status == r2["status"] == solvers.STAGNATED
+    assert r1.iterations == r2["iterations"] < 1000
+    assert r1.true_checks == r2["true_checks"] >= 3
+    assert np.array_equal(r1.x, r2["x"]) and r1.true_relres == r2["true_relres"]
+    res = p.b - p.A.to_scipy() @ r1.x
+    assert abs(np.linalg.norm(res) / np.linalg.norm(p.b) / r1.true_relres - 1) < 1e-6  # the returned iterate's
+    b1 = solvers.bicgstab(p.A, p.b, tol=1e-14, max_iter=3000, dot=dot)
+    b2 = ctier.bicgstab(p.A, p.b, tol=1e-14, max_iter=3000)
+    assert b1.status == b2["status"] == solvers.OK and np.array_equal(b1.x, b2["x"])
