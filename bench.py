@@ -161,6 +161,12 @@ def config_leg(pk, torch, g, dev, name, reps):
     t64, i64, x64 = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000)
     out = {"n": prob.A.n, "nnz": prob.A.nnz, "host_generation_s": gen,
            "forms": precision_forms(pk, torch, A, b, xs, x64, t64, i64, reps)}
+    # FP64 references that do not depend on p-BiCGStab's attainable accuracy: residual
+    # replacement every 50 iterations, and BiCGStab (Algorithm 1)
+    for key, kw in (("pbicgstab_fp64_rr50", {"rr_period": 50}), ("bicgstab_fp64", {"alg": pk.ALG_BICGSTAB})):
+        tr, ir, xr = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, **kw)
+        out["forms"][key] = {"seconds": tr, "iterations": ir["iterations"], "true_relres": ir["true_relres"],
+                             "status": ir["status"], "rel_err_vs_xstar": rel(torch, xr, xs)}
     kern = {}
     for kname, kind in (("spmv_seq_cold", pk.SPMV_SEQ), ("spmv_vector_cold", pk.SPMV_VECTOR)):
         dt, gbs = spmv_cold(pk, torch, A, 20, kind)

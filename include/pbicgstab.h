@@ -39,10 +39,10 @@ typedef enum {
     PBCG_NOT_CONVERGED = 1,   /* max_iter reached before the true residual met tol       */
     PBCG_BREAKDOWN = 2,       /* a zero denominator (r_hat,w0), (y,y) with q != 0, omega,
                                  rho or the alpha denominator                                */
-    PBCG_STAGNATED = 3,       /* three failed true-residual tests in a row without the
-                                 true residual improving by 10%: the recursive residual
-                                 no longer describes x (tolerance below what the
-                                 recurrences sustain)                                     */
+    PBCG_STAGNATED = 3,       /* 30 failed true-residual tests in a row without a new
+                                 smallest true residual: the recursive residual no longer
+                                 describes x (tolerance below what the recurrences
+                                 sustain); x is the best tested iterate                  */
     PBCG_ERR_INVALID = -1,    /* bad argument (null pointer, n < 0, nnz mismatch, ...)     */
     PBCG_ERR_HIP = -2,        /* a HIP runtime call failed                                  */
     PBCG_ERR_NONFINITE = -3,  /* NaN/Inf in b or in a recurrence scalar                     */
@@ -195,9 +195,9 @@ int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal,
  * Algorithm 1).  x holds x0 on entry and the returned iterate on exit.  Stopping: the
  * recursive residual sqrt((r,r))/||b|| is checked every iteration; when it is <= tol
  * the true residual ||b - A x||/||b|| is evaluated and the solve stops if it is <= tol.
- * After a failed test the next one waits until the recursive residual has halved;
- * three failed tests in a row that do not lower the true residual below 0.9 x the best
- * failed one end the solve with PBCG_STAGNATED.
+ * After a failed test the next one comes 5 iterations later; 30 failed tests in a row
+ * without a new smallest true residual end the solve with PBCG_STAGNATED and x set to
+ * the iterate of the best failed test.
  * prec = PBCG_PREC_FP32_IR: FP64 iterative refinement around an FP32 p-BiCGStab (FP32
  * values, vectors and scalars, the compensated FP32 SpMV of csr_spmv_f32, plain FP32
  * dot products in a fixed reduction tree) with reliable updates.  The FP32 process

@@ -210,24 +210,24 @@ void ora_spmv(int32_t n, const int32_t* rp, const int32_t* ci, const double* val
 
 enum { S_OK = 0, S_NOT_CONVERGED = 1, S_BREAKDOWN = 2, S_STAGNATED = 3, S_ERR_NONFINITE = -3 };
 
-/* The stopping test: the true residual is tested when rec <= tol and rec has at least
- * halved since the last failed test, or (once a test has failed) 50 iterations after
- * the last failed one; a failed
- * test below 0.9 x the best failed one becomes the best (its iterate is kept in xb);
- * three failed tests in a row without that mean stagnation. */
+/* The stopping test: the first true-residual test comes when rec <= tol; after a
+ * failed test the next comes 5 iterations later; a failed test below every earlier one
+ * keeps its iterate (in xb); 30 failed tests in a row without a new best mean
+ * stagnation. */
 typedef struct { double lim, best; int stag, it_fail; double* xb; } true_test;
 static int tt_due(const true_test* t, double rec, double tol, int it) {
-    return (rec <= tol && rec <= t->lim) || (t->it_fail >= 0 && it - t->it_fail >= 50);
+    if (t->it_fail < 0) return rec <= tol;
+    return it - t->it_fail >= 5;
 }
 static int tt_failed(true_test* t, double rec, double tr, int it, const double* x, int32_t n) {
-    t->lim = 0.5 * rec;
+    (void)rec;
     t->it_fail = it;
-    if (tr < 0.9 * t->best) {
+    if (tr < t->best) {
         t->best = tr; t->stag = 0;
         memcpy(t->xb, x, sizeof(double) * (size_t)n);
         return 0;
     }
-    return ++t->stag >= 3;
+    return ++t->stag >= 30;
 }
 
 typedef struct {

@@ -26,11 +26,10 @@ Readings of Algorithm 2 (p-BiCGStab) where the printed text is garbled or silent
 Stopping (the paper states tolerances but not the norm): after each iteration
 rec = sqrt((r, r)) / ||b||; when rec <= tol the true relative residual
 sqrt((b - A x, b - A x)) / ||b|| is computed and the solve stops if it is <= tol,
-otherwise it continues.  After a failed test the next one comes when rec has halved
-since it (and is <= tol) or 50 iterations have passed; three failed tests in a row that do not bring
-the true residual below 0.9 times the best failed one end the solve with STAGNATED
-(the recursive residual has left the true one behind), returning the iterate of the
-best failed test.  ``iterations`` counts completed loop bodies.
+otherwise it continues.  After a failed test the next one comes 5 iterations later
+(whatever rec does); 30 failed tests in a row without a new smallest true residual end
+the solve with STAGNATED (the recursive residual has left the true one behind),
+returning the iterate of the best failed test.  ``iterations`` counts completed loop bodies.
 
 Breakdowns (the paper is silent): ||b|| = 0 -> x = 0, OK; (r_hat, w_0) = 0 or an
 alpha denominator = 0 or rho = 0 or omega = 0 -> BREAKDOWN; (y, y) = 0 and
@@ -98,29 +97,30 @@ class _Operator:
 class _TrueTest:
     """When the true residual is tested, and when failed tests mean stagnation.
 
-    A test is due when rec <= tol and rec has halved since the last failed test, or
-    (once a test has failed) when 50 iterations have passed since the last failed one.  A failed test whose true residual is below
-    0.9 times the best failed one so far becomes the best (its iterate is kept);
-    three failed tests in a row without that mean stagnation, and the solve returns
-    the kept iterate."""
+    The first test comes as soon as rec <= tol; after a failed test the next comes 5
+    iterations later (whatever rec does).  A failed test with a true residual below
+    every earlier one keeps its iterate; 30 failed tests in a row without a new best
+    mean stagnation, and the solve returns the kept iterate."""
 
-    EVERY = 50
+    EVERY, PATIENCE = 5, 30
 
     def __init__(self, tol):
-        self.tol, self.lim, self.best, self.stag, self.it_fail = tol, math.inf, math.inf, 0, -1
+        self.tol, self.best, self.stag, self.it_fail = tol, math.inf, 0, -1
         self.x_best = None
 
     def due(self, rec, it):
-        return (rec <= self.tol and rec <= self.lim) or (self.it_fail >= 0 and it - self.it_fail >= self.EVERY)
+        if self.it_fail < 0:
+            return rec <= self.tol
+        return it - self.it_fail >= self.EVERY
 
     def failed(self, rec, tr, it, x):
         """Record a failed test at iteration it with iterate x; True on stagnation."""
-        self.lim, self.it_fail = 0.5 * rec, it
-        if tr < 0.9 * self.best:
+        self.it_fail = it
+        if tr < self.best:
             self.best, self.stag, self.x_best = tr, 0, x.copy()
             return False
         self.stag += 1
-        return self.stag >= 3
+        return self.stag >= self.PATIENCE
 
 
 def _true_relres(A, b, x, normb, dot, spmv):

@@ -282,7 +282,6 @@ struct FnInitState {
         memset(&z, 0, sizeof(z));
         z.tol = tol; z.max_iter = max_iter; z.hist = hist; z.hist_len = hist_len;
         z.stall_window = stall_window; z.stall_hist = stall_hist;
-        z.check_lim = __longlong_as_double(0x7ff0000000000000ll);   // +inf
         z.check_it = -1;
         *st = z;
     }
@@ -314,9 +313,9 @@ struct FnScaleF {          // p = p * sigma (FP32)
     float* p; float sigma;
     __device__ void operator()(int64_t i) const { p[i] = p[i] * sigma; }
 };
-struct FnSetCheckLim {     // after a failed true-residual test
-    State* st; double lim; int it;
-    __device__ void operator()() const { st->check_lim = lim; st->check_it = it; }
+struct FnSetCheckIt {      // after a failed true-residual test at iteration it
+    State* st; int it;
+    __device__ void operator()() const { st->check_it = it; }
 };
 struct FnResume {          // clear halt flags (host decided to continue)
     State* st;
@@ -621,15 +620,15 @@ struct Driver {
             true_residual_enqueue();
             if (sync_state(&h)) return PBCG_ERR_HIP;
             if (h.true_rel <= h.tol) return PBCG_OK;
-            // failed test: the next one when rec has halved, or 50 iterations on; a test
-            // below 0.9 x the best failed one keeps its iterate; three failed tests in a
-            // row without that: stagnation, and the kept iterate is returned
-            launch_single(FnSetCheckLim{W.st, 0.5 * h.rec, h.iter}, s);
-            if (h.true_rel < 0.9 * fail_best) {
+            // failed test: the next one 5 iterations on; a new smallest true residual
+            // keeps its iterate; 30 failed tests in a row without one: stagnation, and
+            // the kept iterate is returned
+            launch_single(FnSetCheckIt{W.st, h.iter}, s);
+            if (h.true_rel < fail_best) {
                 fail_best = h.true_rel;
                 fail_stag = 0;
                 launch_ew(FnCopy{W.xbest, x}, n, nullptr, s);
-            } else if (++fail_stag >= 3) {
+            } else if (++fail_stag >= 30) {
                 launch_ew(FnCopy{x, W.xbest}, n, nullptr, s);
                 return PBCG_STAGNATED;
             }

@@ -611,10 +611,11 @@ struct FinNormB {
     }
 };
 
-// The stopping test is due when rec <= tol and rec has halved since the last failed
-// test, or (once a test has failed) 50 iterations after the last failed one.
+// The stopping test: the first true-residual test comes when rec <= tol; after a
+// failed test (check_it = its iteration) the next comes 5 iterations later.
 __device__ __forceinline__ bool true_test_due(const State* st, double rec, int it) {
-    return (rec <= st->tol && rec <= st->check_lim) || (st->check_it >= 0 && it - st->check_it >= 50);
+    if (st->check_it < 0) return rec <= st->tol;
+    return it - st->check_it >= 5;
 }
 
 // initial (r_hat, r0), (r_hat, w0), (r0, r0) -> rho, alpha0, rec

@@ -28,7 +28,7 @@ struct State {
     double alpha, beta, omega, rho;
     double rs, rz, qy, yy;
     double normb, rec, true_rel, tol;
-    double rw, rr, last_dot, check_lim;   // check_lim: rec must be <= it for a true test
+    double rw, rr, last_dot, pad0;
     int32_t iter, max_iter, halt, reason;
     int32_t hist_len, true_checks, halt_seen, stall_window;
     int32_t check_it, pad_i;   // iteration of the last failed true-residual test (-1: none)
