@@ -47,12 +47,18 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the sources of the solver kernels whose HBM traffic the counter profile
-    records (the learned-preconditioner kernels live in spai.hip and are not profiled)."""
+    """Hash of what determines the HBM traffic the counter profile records: the kernel
+    sources and the launch-shape constants of the host launchers (the driver logic in
+    capi.hip and the learned-preconditioner kernels in spai.hip do not change it)."""
     h = hashlib.sha256()
-    for f in ("capi.hip", "kernels.hpp", "state.hpp", "xdot.hpp"):
+    for f in ("kernels.hpp", "state.hpp", "xdot.hpp"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(CSRC, "capi.hip")) as fh:
+        for line in fh:
+            if line.startswith("constexpr int") and ("GRID" in line or "BLOCK" in line or "WORKERS" in line
+                                                    or "KEXP" in line):
+                h.update(line.encode())
     return h.hexdigest()[:16]
 
 

@@ -208,7 +208,8 @@ int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal,
  * or, after a breakdown or stall, restarts.  An update that does not lower the true
  * residual below the best so far (FP32 has reached its accuracy floor, about
  * u32 cond(A)), max_outer updates or max_iter FP32 iterations end in FP64 p-BiCGStab
- * from the best iterate (info->fell_back = 1).
+ * from the best iterate, with residual replacement every 50 iterations
+ * (info->fell_back = 1).
  * `info` (host) may be NULL.  Workspace: pbicgstab_workspace_bytes(n, nnz, opts).
  */
 size_t pbicgstab_workspace_bytes(int32_t n, int64_t nnz, const pbcg_opts* opts);

@@ -475,7 +475,9 @@ def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=N
     that does not lower nu below the best so far means the FP32 process has reached
     the accuracy its operator allows (about u32 cond(A) relative): after ``max_bad``
     such updates (default 1) -- or ``max_outer`` updates, or max_iter FP32 iterations
-    -- the solve finishes in FP64 p-BiCGStab from the best iterate (``fell_back`` = 1).
+    -- the solve finishes in FP64 p-BiCGStab from the best iterate with residual
+    replacement every 50 iterations (a restart from a non-smooth residual attains less
+    accuracy than the solve from b), ``fell_back`` = 1.
     (With max_bad > 1, x returns to the best iterate and the FP32 process restarts.)
     ``iterations`` counts FP32 iterations (plus the FP64 finish); ``outer_iterations``
     counts reliable updates.
@@ -501,7 +503,7 @@ def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=N
         return r64, math.sqrt(dot(r64, r64))
 
     def finish(xs, its, outer):
-        fin = pbicgstab(A, b, x0=xs, tol=tol, max_iter=max_fp64, dot=dot, spmv=spmv)
+        fin = pbicgstab(A, b, x0=xs, tol=tol, max_iter=max_fp64, dot=dot, spmv=spmv, rr_period=50)
         return Result(fin.x, fin.status, its + fin.iterations, fin.true_relres, fin.rec_relres,
                       fin.true_checks, outer_iterations=outer, fell_back=1)
 

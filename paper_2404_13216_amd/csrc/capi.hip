@@ -25,6 +25,7 @@ constexpr int IR_MAX_UPDATES = 60;    // reliable updates before the FP64 finish
 constexpr int IR_MAX_BAD = 1;         // updates that did not improve on the best before it
 constexpr double IR_DELTA = 0.1;      // default update threshold (inner_tol)
 constexpr int IR_FP64_FINISH = 10000; // iteration limit of the FP64 finish after stagnation
+constexpr int IR_FINISH_RR = 50;      // residual replacement period of that finish
 constexpr int KEXP = 3;              // expansion terms per lane in the solver kernels
 
 #define HIPCHK(expr)                              \
@@ -575,6 +576,7 @@ struct Driver {
     int fell_back = 0;     // a fallback (preconditioned) or an FP64 finish (refinement) ran
     int kind;              // SpMV kernel shape
     pbcg_csr A32;          // FP32 copy of A (refinement)
+    int rr_period = 0;             // residual replacement period of the current run
     double fail_best = INFINITY;   // best true residual of a failed stopping test
     int fail_stag = 0;             // failed tests in a row without improving on it
 
@@ -681,7 +683,7 @@ struct Driver {
                 launch_spmv_dot<1>(A, x, epi, W.site, halt, s, kind);
             }
         }
-        if (o->rr_period > 0 && it % o->rr_period == 0) enqueue_replacement();
+        if (rr_period > 0 && it % rr_period == 0) enqueue_replacement();
     }
 
     // Residual replacement after a completed iteration (skipped if the iteration halted):
@@ -897,6 +899,7 @@ struct Driver {
             launch_ew(FnCopy{x, x_best}, n, nullptr, s);
             fell_back = 1;
             max_iter = IR_FP64_FINISH;
+            rr_period = IR_FINISH_RR;   // the restart point's gap must not limit the finish
             const int st = run_fp64(h);
             inner_total += h.iter;
             return st;
@@ -1027,6 +1030,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     D.batch = opts->batch > 0 ? opts->batch : 16;
     D.kind = opts->spmv_kind;
     D.max_iter = opts->max_iter;
+    D.rr_period = opts->rr_period;
     State h{};
     int status;
     int outer = 0, inner_total = 0;
