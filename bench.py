@@ -97,9 +97,10 @@ def time_launches(fn, reps, torch):
     return float(np.median([ev[k].elapsed_time(ev[k + 1]) / 1e3 for k in range(reps)]))
 
 
-def spmv_cold(pk, torch, A, reps, kind=None):
+def spmv_cold(pk, torch, A, reps, kind=None, S=None):
     """Median duration of one SpMV launch with a 512 MB write before each (no launch is
-    served from the Infinity Cache); returns (seconds, GB/s of 12 B/nnz + 20 B/row)."""
+    served from the Infinity Cache); returns (seconds, GB/s of 12 B/nnz + 20 B/row).
+    With S (a built sliced copy of A) the sliced row-sequential kernel is timed."""
     flush = torch.empty(64 << 20, dtype=torch.float64, device=A.val.device)
     vin = torch.ones(A.n, dtype=torch.float64, device=A.val.device)
     vout = torch.empty_like(vin)
@@ -108,7 +109,10 @@ def spmv_cold(pk, torch, A, reps, kind=None):
     for it in range(reps + 1):
         flush.zero_()
         e0.record()
-        pk.csr_spmv(A, vin, vout, kind=kind)
+        if S is not None:
+            pk.csr_spmv_sliced(S, vin, vout)
+        else:
+            pk.csr_spmv(A, vin, vout, kind=kind)
         e1.record()
         e1.synchronize()
         if it:
@@ -174,10 +178,16 @@ def config_leg(pk, torch, g, dev, name, reps):
         out["forms"][key] = {"seconds": tr, "iterations": ir["iterations"], "true_relres": ir["true_relres"],
                              "status": ir["status"], "rel_err_vs_xstar": rel(torch, xr, xs)}
     kern = {}
-    for kname, kind in (("spmv_seq_cold", pk.SPMV_SEQ), ("spmv_vector_cold", pk.SPMV_VECTOR)):
-        dt, gbs = spmv_cold(pk, torch, A, 20, kind)
+    S = pk.SlicedCSR(A)
+    out["sliced"] = {"built": S.built, "entries": S.entries}
+    shapes = [("spmv_seq_cold", pk.SPMV_SEQ, None), ("spmv_vector_cold", pk.SPMV_VECTOR, None)]
+    if S.built:
+        shapes.insert(0, ("spmv_seq_sliced_cold", pk.SPMV_SEQ, S))
+    for kname, kind, sl in shapes:
+        dt, gbs = spmv_cold(pk, torch, A, 20, kind, sl)
         kern[kname] = {"us": dt * 1e6, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
     out["kernels"] = kern
+    del S
     out["forms"]["pbicgstab_fp64"]["rel_err_vs_xstar"] = rel(torch, x64, xs)
     log(f"{name}:", json.dumps(out))
     return out
@@ -293,11 +303,15 @@ def traffic_run(pk, torch, A, n, nnz, dev):
     flush = torch.ones(128 << 20, dtype=torch.float64, device=dev)
     o1 = torch.empty(1, dtype=torch.float64, device=dev)
     wse = torch.empty(pk.lib().exdot_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    S = pk.SlicedCSR(A)   # the solve's SpMV reads the sliced copy when one is built
     for _ in range(10):
         flush.sum()
         dst.copy_(src)
         flush.sum()
-        pk.csr_spmv(A, V["z"], V["v"])
+        if S.built:
+            pk.csr_spmv_sliced(S, V["z"], V["v"])
+        else:
+            pk.csr_spmv(A, V["z"], V["v"])
         flush.sum()
         pk.pbcg_phase_a(V, scal, False, dots, wsp)
         flush.sum()
@@ -383,7 +397,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cd3d_128: 3D upwind convection-diffusion 128^3, v=(30,20,10), seed 1",
                    "n": n, "nnz": nnz, "tol": 1e-10, "x0": "0", "alg": "p-BiCGStab",
-                   "dots": "exact (rounded once)", "spmv": "row-sequential CSR"},
+                   "dots": "exact (rounded once)",
+                   "spmv": "row-sequential, " + ("sliced copy (256-row slices)" if info["sliced"] & 1 else "CSR")},
         "iterations": info["iterations"],
         "true_relres": info["true_relres"],
         "rel_err_vs_xstar": err_xstar,
@@ -413,10 +428,18 @@ def main():
         dots = torch.empty(4, dtype=torch.float64, device=dev)
         wsp = torch.empty(pk.lib().pbcg_phase_workspace_bytes(n), dtype=torch.uint8, device=dev)
         spmv_bytes = 12 * nnz + 20 * n
+        # the SpMV form the solve runs: the sliced copy when one is built, else CSR
+        S = pk.SlicedCSR(A)
+
+        def spmv(vin, vout):
+            if S.built:
+                pk.csr_spmv_sliced(S, vin, vout)
+            else:
+                pk.csr_spmv(A, vin, vout)
         seq = [("phase_a", lambda: pk.pbcg_phase_a(V, scal, False, dots, wsp), 104 * n),
-               ("spmv_seq", lambda: pk.csr_spmv(A, V["z"], V["v"]), spmv_bytes),
+               ("spmv_seq", lambda: spmv(V["z"], V["v"]), spmv_bytes),
                ("phase_b", lambda: pk.pbcg_phase_b(V, scal, dots, wsp), 80 * n),
-               ("spmv_seq", lambda: pk.csr_spmv(A, V["w"], V["t"]), spmv_bytes)]
+               ("spmv_seq", lambda: spmv(V["w"], V["t"]), spmv_bytes)]
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)]
         acc = {}
         for it in range(reps + 2):
@@ -435,10 +458,14 @@ def main():
         for name, (tsum, cnt, nb) in acc.items():
             dt = tsum / cnt
             kern[name] = {"us": dt * 1e6, "bytes": nb, "GBs": nb / dt / 1e9, "launches": cnt}
+        kern["spmv_seq"]["layout"] = "sliced" if S.built else "csr"
         # SpMV kernel shapes, each launch preceded by a 512 MB write that evicts the cache
-        for name, kind in (("spmv_seq_cold", pk.SPMV_SEQ), ("spmv_vector_cold", pk.SPMV_VECTOR),
-                           ("spmv_wave_cold", pk.SPMV_WAVE)):
-            dt, gbs = spmv_cold(pk, torch, A, min(reps, 20), kind)
+        shapes = [("spmv_seq_cold", pk.SPMV_SEQ, None), ("spmv_vector_cold", pk.SPMV_VECTOR, None),
+                  ("spmv_wave_cold", pk.SPMV_WAVE, None)]
+        if S.built:
+            shapes.insert(0, ("spmv_seq_sliced_cold", pk.SPMV_SEQ, S))
+        for name, kind, sl in shapes:
+            dt, gbs = spmv_cold(pk, torch, A, min(reps, 20), kind, sl)
             kern[name] = {"us": dt * 1e6, "bytes": spmv_bytes, "GBs": gbs}
         # standalone exact dot, rotating over buffers larger than the cache: uniform
         # U[-1, 1] at 2^20, 2^24, 2^26; wide exponents (+-1000) and exactly cancelling
@@ -488,7 +515,7 @@ def main():
                            "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                            "algorithmic_bytes_per_launch": kern[dom]["bytes"],
                            "avg_launch_us": kern[dom]["us"]}
-        del V, wsp
+        del V, wsp, S
         # further legs run after the kernel table, so that they do not disturb its timings
         legs = [l for l in args.legs.split(",") if l]
         if "claim" in legs:

@@ -66,6 +66,11 @@ typedef enum { PBCG_SPMV_SEQ = 0, PBCG_SPMV_VECTOR = 1, PBCG_SPMV_WAVE = 2 } pbc
  * test of a lucky breakdown stay exact in both. */
 typedef enum { PBCG_DOTS_EXACT = 0, PBCG_DOTS_PLAIN = 1 } pbcg_dots;
 
+/* Matrix layout of the solver's row-sequential SpMVs.  AUTO: the solver copies A (and
+ * M) into the sliced layout of csr_slice when its padding stays within nnz/8 + 256
+ * entries, else it keeps CSR.  CSR: never copied.  Both give bit-identical results. */
+typedef enum { PBCG_LAYOUT_AUTO = 0, PBCG_LAYOUT_CSR = 1 } pbcg_layout;
+
 /* Square CSR matrix.  `val` points to nnz values of type `val_type`. */
 typedef struct {
     int32_t n;
@@ -110,6 +115,7 @@ typedef struct {
                                   residual gap                                                */
     int32_t true_history_len;  /* entries available in true_history                        */
     double* true_history;      /* optional device buffer                                     */
+    int32_t layout;            /* pbcg_layout (default AUTO; SEQ SpMV kind only)              */
 } pbcg_opts;
 
 /* Result summary (host struct). */
@@ -119,7 +125,7 @@ typedef struct {
     int32_t outer_iterations;  /* FP32-IR refinement steps                                   */
     int32_t true_checks;       /* true-residual evaluations                                  */
     int32_t fell_back;         /* 1 if the preconditioned solve fell back                    */
-    int32_t pad;
+    int32_t sliced;            /* bit 0: A, bit 1: M ran on a sliced copy (layout AUTO)      */
     double true_relres;        /* ||b - A x|| / ||b|| of the returned x (exact dots)         */
     double rec_relres;         /* last recursive ||r|| / ||b||                               */
     double seconds;            /* host wall time of the call                                 */
@@ -153,6 +159,42 @@ int csr_spmv_f32(const pbcg_csr* A32, const float* x, float* y, void* stream);
  * to m_type (PBCG_F64 or PBCG_F32).  A must hold FP64 values; a row without a stored
  * diagonal entry gets 1/0 = +inf.  m_out: n device values of m_type. */
 int csr_jacobi(const pbcg_csr* A, void* m_out, int32_t m_type, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Sliced copy of a CSR matrix for the row-sequential SpMV (the layout of this library,
+ * not of the paper; the products are those of csr_spmv, the paper's A p_i, A q_i ... of
+ * Algorithms 1 and 2).  Slice c holds rows 256c .. 256c+255 column-major: entry k of row
+ * 256c + t sits at slice_off[c] + 256 k + t, and every slice is padded to its longest
+ * row (padding: column 0, value 0, never used in arithmetic).  One lane per row walks
+ * its row in storage order, so csr_spmv_sliced and csr_spmv return the same bits.
+ * Pays off for matrices of near-uniform row length (stencils); the solver makes and uses
+ * one by itself (pbcg_opts.layout).
+ */
+typedef struct {
+    int64_t entries;           /* padded entry count (also set when too large to build)     */
+    const int64_t* slice_off;  /* [ceil(n/256) + 1] entry offsets; NULL: not built          */
+    const int32_t* col;        /* [entries] column indices                                  */
+    const void* val;           /* [entries] values, A's val_type                            */
+} pbcg_sliced;
+
+/* Workspace csr_slice needs for an n x n matrix with nnz entries. */
+size_t csr_slice_workspace_bytes(int32_t n, int64_t nnz);
+
+/* Builds the sliced copy of A inside `ws` (device, 256-byte aligned, at least
+ * csr_slice_workspace_bytes(n, nnz)); S (host) receives pointers into ws, valid while ws
+ * is.  When the padding exceeds nnz/8 + 256 entries nothing is copied, S->slice_off is
+ * NULL and S->entries holds the padded count: keep using CSR.  Synchronises `stream`
+ * (the padded size is read back).  Errors: PBCG_ERR_INVALID (bad A or S),
+ * PBCG_ERR_WORKSPACE, PBCG_ERR_HIP. */
+int csr_slice(const pbcg_csr* A, pbcg_sliced* S, void* ws, size_t ws_bytes, void* stream);
+
+/* y = A x as csr_spmv (bit-identical), reading the sliced copy S made by csr_slice from
+ * this A.  x, y: FP64 device vectors, x != y.  PBCG_ERR_INVALID if S was not built. */
+int csr_spmv_sliced(const pbcg_csr* A, const pbcg_sliced* S, const double* x, double* y, void* stream);
+
+/* y = A x as csr_spmv_f32 (Dot2-compensated FP32, bit-identical), reading the sliced
+ * copy S of the FP32 matrix A. */
+int csr_spmv_f32_sliced(const pbcg_csr* A, const pbcg_sliced* S, const float* x, float* y, void* stream);
 
 /* ---------------------------------------------------------------------------------
  * Exact dot product (paper Section 2, ExBLAS paragraph): *out = RN_even(sum x_i y_i)
@@ -210,7 +252,10 @@ int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal,
  * u32 cond(A)), max_outer updates or max_iter FP32 iterations end in FP64 p-BiCGStab
  * from the best iterate, with residual replacement every 50 iterations
  * (info->fell_back = 1).
- * `info` (host) may be NULL.  Workspace: pbicgstab_workspace_bytes(n, nnz, opts).
+ * `info` (host) may be NULL.  Workspace: pbicgstab_workspace_bytes(n, nnz, opts); with
+ * layout AUTO it includes room for the sliced copies of A and M (12 bytes per entry,
+ * nnz + nnz/8 + 256 entries each), which every call rebuilds (one stream
+ * synchronisation each).
  */
 size_t pbicgstab_workspace_bytes(int32_t n, int64_t nnz, const pbcg_opts* opts);
 int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_opts* opts,

@@ -26,6 +26,7 @@ ALG_PBICGSTAB, ALG_BICGSTAB = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 SPMV_SEQ, SPMV_VECTOR, SPMV_WAVE = 0, 1, 2
 DOTS_EXACT, DOTS_PLAIN = 0, 1
+LAYOUT_AUTO, LAYOUT_CSR = 0, 1
 
 _P = ctypes.c_void_p
 
@@ -44,18 +45,22 @@ class PbcgOpts(ctypes.Structure):
                 ("spmv_kind", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("dots", ctypes.c_int32), ("rr_period", ctypes.c_int32),
                 ("true_every", ctypes.c_int32), ("true_history_len", ctypes.c_int32),
-                ("true_history", ctypes.c_void_p)]
+                ("true_history", ctypes.c_void_p), ("layout", ctypes.c_int32)]
 
 
 class PbcgInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("outer_iterations", ctypes.c_int32), ("true_checks", ctypes.c_int32),
-                ("fell_back", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("sliced", ctypes.c_int32),
                 ("true_relres", ctypes.c_double), ("rec_relres", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PbcgSliced(ctypes.Structure):
+    _fields_ = [("entries", ctypes.c_int64), ("slice_off", _P), ("col", _P), ("val", _P)]
 
 
 class PbcgVectors(ctypes.Structure):
@@ -63,7 +68,8 @@ class PbcgVectors(ctypes.Structure):
 
 
 EXPORTS = [
-    "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "csr_jacobi", "exdot_workspace_bytes", "exdot", "exdot_config",
+    "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "csr_jacobi", "csr_slice_workspace_bytes", "csr_slice",
+    "csr_spmv_sliced", "csr_spmv_f32_sliced", "exdot_workspace_bytes", "exdot", "exdot_config",
     "pbcg_phase_workspace_bytes", "pbcg_phase_a", "pbcg_phase_b", "pbicgstab_workspace_bytes",
     "pbicgstab_solve", "pbcg_default_opts", "pbcg_status_string", "pbcg_abi_version",
     "spai_param_count", "spai_workspace_bytes", "spai_features", "spai_forward", "spai_infer_bf16",
@@ -88,6 +94,10 @@ def lib():
         "csr_spmv_config": (ctypes.c_int, [CP, _P, _P, i32, _P]),
         "csr_spmv_f32": (ctypes.c_int, [CP, _P, _P, _P]),
         "csr_jacobi": (ctypes.c_int, [CP, _P, i32, _P]),
+        "csr_slice_workspace_bytes": (sz, [i32, i64]),
+        "csr_slice": (ctypes.c_int, [CP, ctypes.POINTER(PbcgSliced), _P, sz, _P]),
+        "csr_spmv_sliced": (ctypes.c_int, [CP, ctypes.POINTER(PbcgSliced), _P, _P, _P]),
+        "csr_spmv_f32_sliced": (ctypes.c_int, [CP, ctypes.POINTER(PbcgSliced), _P, _P, _P]),
         "exdot_workspace_bytes": (sz, [i64]),
         "exdot": (ctypes.c_int, [i64, _P, _P, _P, _P, sz, _P]),
         "exdot_config": (ctypes.c_int, [i64, _P, _P, _P, i32, i32, i32, _P, sz, _P]),
@@ -185,6 +195,46 @@ class CSR:
     @property
     def c(self):
         return ctypes.byref(self._c)
+
+
+class SlicedCSR:
+    """Sliced copy of a device CSR (csr_slice); `built` is False when its padding is
+    too large, and the CSR form is then the one to use."""
+
+    def __init__(self, A: CSR):
+        self.A = A
+        self.ws = _workspace(lib().csr_slice_workspace_bytes(A.n, A.nnz), A.val.device)
+        self._c = PbcgSliced()
+        _check(lib().csr_slice(A.c, ctypes.byref(self._c), _ptr(self.ws), self.ws.numel(), _stream()),
+               "csr_slice")
+
+    @property
+    def built(self) -> bool:
+        return bool(self._c.slice_off)
+
+    @property
+    def entries(self) -> int:
+        return int(self._c.entries)
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def csr_spmv_sliced(S: SlicedCSR, x, y=None):
+    torch = _torch()
+    if y is None:
+        y = torch.empty(S.A.n, dtype=torch.float64, device=x.device)
+    _check(lib().csr_spmv_sliced(S.A.c, S.c, _ptr(x), _ptr(y), _stream()), "csr_spmv_sliced")
+    return y
+
+
+def csr_spmv_f32_sliced(S: SlicedCSR, x, y=None):
+    torch = _torch()
+    if y is None:
+        y = torch.empty(S.A.n, dtype=torch.float32, device=x.device)
+    _check(lib().csr_spmv_f32_sliced(S.A.c, S.c, _ptr(x), _ptr(y), _stream()), "csr_spmv_f32_sliced")
+    return y
 
 
 def csr_spmv(A: CSR, x, y=None, kind: int | None = None):

@@ -85,22 +85,76 @@ bool csr_ok(const pbcg_csr* A) {
            (A->val_type == PBCG_F64 || A->val_type == PBCG_F32);
 }
 
+// A matrix as the launchers see it: the CSR arrays and, when one was built, a sliced
+// copy with the same row order (read by the row-sequential kernels only).
+struct SliceView {
+    const int64_t* off = nullptr;
+    const int32_t* col = nullptr;
+    const void* val = nullptr;
+};
+
+struct Mat {
+    const pbcg_csr* csr = nullptr;
+    SliceView sl{};
+    Mat() = default;
+    Mat(const pbcg_csr* c) : csr(c) {}
+    Mat(const pbcg_csr* c, SliceView v) : csr(c), sl(v) {}
+    const pbcg_csr* operator->() const { return csr; }
+    explicit operator bool() const { return csr != nullptr; }
+};
+
+template <class VT>
+Sliced<VT> typed(const SliceView& v) {
+    return Sliced<VT>{v.off, v.col, (const VT*)v.val};
+}
+
+// A sliced copy is kept when its padding is at most nnz/8 + 256 entries.
+int64_t slice_cap(int64_t nnz) { return nnz + nnz / 8 + 256; }
+int nslices(int32_t n) { return (n + 255) / 256; }
+
+// Builds the sliced copy of A (n > 0) into off[nslices + 1], col[cap], val[cap] (A's
+// value type).  Returns the padded entry count -- above cap nothing was filled and the
+// caller keeps the CSR form -- or -1 on a HIP error.  Synchronises the stream once.
+int64_t build_slices(const pbcg_csr* A, int64_t* off, int32_t* col, void* val, int64_t cap, hipStream_t s) {
+    const int n = A->n, ns = nslices(n);
+    slice_width_kernel<<<ns, 256, 0, s>>>(n, A->row_ptr, off);
+    slice_scan_kernel<<<1, 1024, 0, s>>>(ns, off);
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, off + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    if (total > cap) return total;
+    if (A->val_type == PBCG_F64)
+        slice_fill_kernel<double><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const double*)A->val, off, col,
+                                                     (double*)val);
+    else
+        slice_fill_kernel<float><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const float*)A->val, off, col,
+                                                    (float*)val);
+    if (hipGetLastError() != hipSuccess) return -1;
+    return total;
+}
+
 // ---------------------------------------------------------------- launchers
 constexpr int SEQ_WORKERS = 8 * 256;   // persistent SpMV blocks: 8 resident per CU (16 KB LDS each)
+constexpr int SLICE_WORKERS = 1 << 24; // sliced-copy SpMV: one block per slice (no LDS staging)
 
 // kind: PBCG_SPMV_SEQ (rows summed left to right), PBCG_SPMV_VECTOR (L lanes per row
 // from the mean row length, tree order), PBCG_SPMV_WAVE (one wavefront per row).
 template <class VT, class XT, class AT, class Epi, class Fin = NoFin>
-void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hipStream_t s,
+void launch_spmv_t(const Mat& A, const XT* x, Epi epi, const int* halt, hipStream_t s,
                    int kind = PBCG_SPMV_SEQ, Fin fin = Fin{}) {
     const int n = A->n;
     const VT* val = (const VT*)A->val;
     if (kind == PBCG_SPMV_SEQ) {
-        const int workers = std::min((n + BLOCK - 1) / BLOCK, SEQ_WORKERS);
+        const int workers = std::min((n + BLOCK - 1) / BLOCK, A.sl.off ? SLICE_WORKERS : SEQ_WORKERS);
         const int grid = workers + (Fin::D > 0 ? 1 : 0);
-        if (grid > 0)
-            spmv_seq_kernel<VT, XT, AT, Epi, Fin><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
-                                                                          fin, halt);
+        if (grid > 0) {
+            if (A.sl.off)
+                spmv_seq_kernel<VT, XT, AT, Epi, Fin, false, true><<<grid, BLOCK, 0, s>>>(
+                    n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, typed<VT>(A.sl));
+            else
+                spmv_seq_kernel<VT, XT, AT, Epi, Fin><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
+                                                                              fin, halt, Sliced<VT>{});
+        }
         return;
     }
     if (n > 0) {
@@ -119,7 +173,7 @@ void launch_spmv_t(const pbcg_csr* A, const XT* x, Epi epi, const int* halt, hip
 
 // FP64 accumulation, values FP64 or FP32, x FP64
 template <class Epi, class Fin = NoFin>
-void launch_spmv64(const pbcg_csr* A, const double* x, Epi epi, const int* halt, hipStream_t s,
+void launch_spmv64(const Mat& A, const double* x, Epi epi, const int* halt, hipStream_t s,
                    int kind = PBCG_SPMV_SEQ, Fin fin = Fin{}) {
     if (A->val_type == PBCG_F64) launch_spmv_t<double, double, double>(A, x, epi, halt, s, kind, fin);
     else launch_spmv_t<float, double, double>(A, x, epi, halt, s, kind, fin);
@@ -128,25 +182,34 @@ void launch_spmv64(const pbcg_csr* A, const double* x, Epi epi, const int* halt,
 // FP32 row-sequential SpMV with Dot2-compensated accumulation (the refinement's FP32
 // operator; `fin` rides on block 0 as in launch_spmv_t)
 template <class Epi, class Fin = NoFin>
-void launch_spmv32c(const pbcg_csr* A, const float* x, Epi epi, const int* halt, hipStream_t s, Fin fin = Fin{}) {
+void launch_spmv32c(const Mat& A, const float* x, Epi epi, const int* halt, hipStream_t s, Fin fin = Fin{}) {
     const int n = A->n;
-    const int workers = std::min((n + BLOCK - 1) / BLOCK, SEQ_WORKERS);
+    const int workers = std::min((n + BLOCK - 1) / BLOCK, A.sl.off ? SLICE_WORKERS : SEQ_WORKERS);
     const int grid = workers + (Fin::D > 0 ? 1 : 0);
-    if (grid > 0)
-        spmv_seq_kernel<float, float, float, Epi, Fin, true><<<grid, BLOCK, 0, s>>>(
-            n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt);
+    if (grid > 0) {
+        if (A.sl.off)
+            spmv_seq_kernel<float, float, float, Epi, Fin, true, true><<<grid, BLOCK, 0, s>>>(
+                n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt, typed<float>(A.sl));
+        else
+            spmv_seq_kernel<float, float, float, Epi, Fin, true><<<grid, BLOCK, 0, s>>>(
+                n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt, Sliced<float>{});
+    }
 }
 
 template <int D, class VT, class Epi>
-void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site site, const int* halt,
+void launch_spmv_dot_t(const Mat& A, const double* x, Epi epi, xd::Site site, const int* halt,
                        hipStream_t s, int kind) {
     const int n = A->n;
     const VT* val = (const VT*)A->val;
     if (kind == PBCG_SPMV_SEQ) {
         // persistent: up to 4 blocks per CU (one dot record each)
         int grid = std::max(1, std::min(DOT_GRID_MAX, (n + BLOCK - 1) / BLOCK));
-        spmv_seq_dot_kernel<D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi, site,
-                                                                      halt);
+        if (A.sl.off)
+            spmv_seq_dot_kernel<D, KEXP, VT, Epi, true><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
+                                                                                epi, site, halt, typed<VT>(A.sl));
+        else
+            spmv_seq_dot_kernel<D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
+                                                                          site, halt, Sliced<VT>{});
         fin_kernel<XFin<D, Epi>><<<1, BLOCK, 0, s>>>(XFin<D, Epi>{epi, site, grid, halt});
         return;
     }
@@ -163,7 +226,7 @@ void launch_spmv_dot_t(const pbcg_csr* A, const double* x, Epi epi, xd::Site sit
 }
 
 template <int D, class Epi>
-void launch_spmv_dot(const pbcg_csr* A, const double* x, Epi epi, xd::Site site, const int* halt,
+void launch_spmv_dot(const Mat& A, const double* x, Epi epi, xd::Site site, const int* halt,
                      hipStream_t s, int kind = PBCG_SPMV_SEQ) {
     if (A->val_type == PBCG_F64) launch_spmv_dot_t<D, double>(A, x, epi, site, halt, s, kind);
     else launch_spmv_dot_t<D, float>(A, x, epi, site, halt, s, kind);
@@ -380,7 +443,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int n, const int* __restric
 
 extern "C" {
 
-int pbcg_abi_version(void) { return 4; }
+int pbcg_abi_version(void) { return 5; }
 
 const char* pbcg_status_string(int status) {
     switch (status) {
@@ -428,6 +491,56 @@ int csr_spmv_f32(const pbcg_csr* A, const float* x, float* y, void* stream) {
         return PBCG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     launch_spmv32c(A, x, EpiStore<float>{y}, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+size_t csr_slice_workspace_bytes(int32_t n, int64_t nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    Carver c(nullptr, SIZE_MAX);
+    c.take<int64_t>((size_t)nslices(n) + 1);
+    c.take<int32_t>((size_t)slice_cap(nnz));
+    c.take<double>((size_t)slice_cap(nnz));
+    return c.off + 256;
+}
+
+int csr_slice(const pbcg_csr* A, pbcg_sliced* S, void* ws, size_t ws_bytes, void* stream) {
+    if (!csr_ok(A) || !S) return PBCG_ERR_INVALID;
+    std::memset(S, 0, sizeof(*S));
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < csr_slice_workspace_bytes(A->n, A->nnz))
+        return PBCG_ERR_WORKSPACE;
+    if (A->n == 0) return PBCG_OK;
+    Carver c(ws, ws_bytes);
+    int64_t* off = c.take<int64_t>((size_t)nslices(A->n) + 1);
+    int32_t* col = c.take<int32_t>((size_t)slice_cap(A->nnz));
+    void* val = c.take<double>((size_t)slice_cap(A->nnz));
+    const int64_t total = build_slices(A, off, col, val, slice_cap(A->nnz), (hipStream_t)stream);
+    if (total < 0) return PBCG_ERR_HIP;
+    S->entries = total;
+    if (total <= slice_cap(A->nnz)) {
+        S->slice_off = off;
+        S->col = col;
+        S->val = val;
+    }
+    return PBCG_OK;
+}
+
+int csr_spmv_sliced(const pbcg_csr* A, const pbcg_sliced* S, const double* x, double* y, void* stream) {
+    if (!csr_ok(A) || !S || (A->n > 0 && (!x || !y || !S->slice_off || !S->col || !S->val)) ||
+        (x == y && A->n > 0))
+        return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    launch_spmv64(Mat(A, SliceView{S->slice_off, S->col, S->val}), x, EpiStore<double>{y}, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+int csr_spmv_f32_sliced(const pbcg_csr* A, const pbcg_sliced* S, const float* x, float* y, void* stream) {
+    if (!csr_ok(A) || A->val_type != PBCG_F32 || !S ||
+        (A->n > 0 && (!x || !y || !S->slice_off || !S->col || !S->val)) || (x == y && A->n > 0))
+        return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    launch_spmv32c(Mat(A, SliceView{S->slice_off, S->col, S->val}), x, EpiStore<float>{y}, nullptr, s);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
@@ -530,9 +643,16 @@ struct Work {
     TSite<double> dsite;   // partials of the ordinary (plain) FP64 dots
     double *rhat, *r, *w, *t, *p, *s, *z, *q, *y, *v, *tmp, *tmp2, *xbest, *hist;   // xbest: best tested iterate
     float *r32, *rh32, *w32, *t32, *p32, *s32, *z32, *q32, *y32, *v32, *d32, *val32;
+    int64_t *a_off, *m_off;   // sliced copies of A and M (null: not reserved)
+    int32_t *a_col, *m_col;
+    void *a_val, *m_val;
     size_t need;
     bool ok;
 };
+
+bool slicing_on(const pbcg_opts* o) {
+    return o && o->layout == PBCG_LAYOUT_AUTO && o->spmv_kind == PBCG_SPMV_SEQ;
+}
 
 Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts* o) {
     Carver c(ws, bytes);
@@ -551,7 +671,18 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
         float** v32[] = {&W.r32, &W.rh32, &W.w32, &W.t32, &W.p32, &W.s32,
                          &W.z32, &W.q32, &W.y32, &W.v32, &W.d32};
         for (float** pp : v32) *pp = c.take<float>(N);
-        W.val32 = c.take<float>((size_t)std::max<int64_t>(nnz, 1));
+        // FP32 values in CSR order, or in the sliced order when A has a sliced copy
+        W.val32 = c.take<float>((size_t)std::max<int64_t>(slicing_on(o) ? slice_cap(nnz) : nnz, 1));
+    }
+    if (slicing_on(o)) {
+        W.a_off = c.take<int64_t>((size_t)nslices(n) + 1);
+        W.a_col = c.take<int32_t>((size_t)slice_cap(nnz));
+        W.a_val = c.take<double>((size_t)slice_cap(nnz));
+        if (o->M) {
+            W.m_off = c.take<int64_t>((size_t)nslices(n) + 1);
+            W.m_col = c.take<int32_t>((size_t)slice_cap(o->M->nnz));
+            W.m_val = c.take<double>((size_t)slice_cap(o->M->nnz));
+        }
     }
     W.need = c.off + 256;
     W.ok = c.ok && W.need <= bytes;
@@ -562,8 +693,8 @@ constexpr int CONTINUE = -100;
 constexpr int STALLED = 4;   // internal status of a stalled preconditioned solve
 
 struct Driver {
-    const pbcg_csr* A;
-    const pbcg_csr* M;     // right preconditioner or null
+    Mat A;
+    Mat M;                 // right preconditioner or null
     const double* b;
     double* x;             // holds y when M != null
     const pbcg_opts* o;
@@ -575,7 +706,9 @@ struct Driver {
     int max_iter;          // iteration limit of the current run
     int fell_back = 0;     // a fallback (preconditioned) or an FP64 finish (refinement) ran
     int kind;              // SpMV kernel shape
-    pbcg_csr A32;          // FP32 copy of A (refinement)
+    pbcg_csr A32c;         // FP32 copy of A (refinement) ...
+    Mat A32;               // ... with the FP32 sliced values when A is sliced
+    int64_t a_entries = 0; // entries of A's sliced copy
     int rr_period = 0;             // residual replacement period of the current run
     double fail_best = INFINITY;   // best true residual of a failed stopping test
     int fail_stag = 0;             // failed tests in a row without improving on it
@@ -819,11 +952,11 @@ struct Driver {
                 FPhaseA<FFinOmega> pa{W.r32, W.w32, W.t32, W.v32, W.rh32, W.p32, W.s32, W.z32, W.q32, W.y32,
                                       scal, first ? 1 : 0, FFinOmega{fs}};
                 auto fa = launch_ew_fdot_deferred<4>(pa, n, W.fsite, fh, s, fseen);
-                launch_spmv32c(&A32, W.z32, EpiStore<float>{W.v32}, fseen, s, fa);
+                launch_spmv32c(A32, W.z32, EpiStore<float>{W.v32}, fseen, s, fa);
                 FPhaseB<FFinRU> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
                                    FFinRU{fs}};
                 auto fb = launch_ew_fdot_deferred<3>(pb, n, W.fsite, fh, s, fseen);
-                launch_spmv32c(&A32, W.w32, EpiStore<float>{W.t32}, fseen, s, fb);
+                launch_spmv32c(A32, W.w32, EpiStore<float>{W.t32}, fseen, s, fb);
                 first = false;
             }
             HIPCHK(hipGetLastError());
@@ -863,10 +996,16 @@ struct Driver {
         const int n = A->n;
         FState* fs = W.fst;
         launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0, 0, nullptr}, s);
-        launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
-        A32 = *A;
-        A32.val = W.val32;
-        A32.val_type = PBCG_F32;
+        A32c = *A.csr;
+        A32c.val = W.val32;
+        A32c.val_type = PBCG_F32;
+        if (A.sl.off) {   // the FP32 values in the sliced order (padding casts to 0)
+            launch_ew(FnCastVal{W.val32, (const double*)A.sl.val}, a_entries, nullptr, s);
+            A32 = Mat(&A32c, SliceView{A.sl.off, A.sl.col, W.val32});
+        } else {
+            launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
+            A32 = Mat(&A32c);
+        }
         {
             DotsOp<1, FinNormB> nb{};
             nb.a[0] = b; nb.b[0] = b; nb.fin = FinNormB{W.st};
@@ -908,15 +1047,15 @@ struct Driver {
             // rebuild the FP32 state from r / nu
             const float lim = (float)(o->tol * normb / nu);
             launch_ew(FnCastScaled{W.r32, W.r, W.st}, n, nullptr, s);
-            launch_spmv32c(&A32, W.r32, EpiStore<float>{W.w32}, nullptr, s);
-            launch_spmv32c(&A32, W.w32, EpiStore<float>{W.t32}, nullptr, s);
+            launch_spmv32c(A32, W.r32, EpiStore<float>{W.w32}, nullptr, s);
+            launch_spmv32c(A32, W.w32, EpiStore<float>{W.t32}, nullptr, s);
             launch_single(FnSetFState{fs, lim}, s);
             FState hf{};
             if (!restart) {
                 launch_ew(FnScaleF{W.p32, sigma}, n, nullptr, s);
-                launch_spmv32c(&A32, W.p32, EpiStore<float>{W.s32}, nullptr, s);
-                launch_spmv32c(&A32, W.s32, EpiStore<float>{W.z32}, nullptr, s);
-                launch_spmv32c(&A32, W.z32, EpiStore<float>{W.v32}, nullptr, s);
+                launch_spmv32c(A32, W.p32, EpiStore<float>{W.s32}, nullptr, s);
+                launch_spmv32c(A32, W.s32, EpiStore<float>{W.z32}, nullptr, s);
+                launch_spmv32c(A32, W.z32, EpiStore<float>{W.v32}, nullptr, s);
                 FDotsOp<4, FFinReplace> d{};
                 d.a[0] = W.rh32; d.b[0] = W.r32;
                 d.a[1] = W.rh32; d.b[1] = W.w32;
@@ -1031,6 +1170,24 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     D.kind = opts->spmv_kind;
     D.max_iter = opts->max_iter;
     D.rr_period = opts->rr_period;
+    int sliced = 0;   // bit 0: A, bit 1: M use a sliced copy
+    if (slicing_on(opts)) {
+        const int64_t ta = build_slices(A, W.a_off, W.a_col, W.a_val, slice_cap(A->nnz), D.s);
+        if (ta < 0) return PBCG_ERR_HIP;
+        if (ta <= slice_cap(A->nnz)) {
+            D.A.sl = SliceView{W.a_off, W.a_col, W.a_val};
+            D.a_entries = ta;
+            sliced |= 1;
+        }
+        if (opts->M) {
+            const int64_t tm = build_slices(opts->M, W.m_off, W.m_col, W.m_val, slice_cap(opts->M->nnz), D.s);
+            if (tm < 0) return PBCG_ERR_HIP;
+            if (tm <= slice_cap(opts->M->nnz)) {
+                D.M.sl = SliceView{W.m_off, W.m_col, W.m_val};
+                sliced |= 2;
+            }
+        }
+    }
     State h{};
     int status;
     int outer = 0, inner_total = 0;
@@ -1075,6 +1232,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         info->status = status;
         info->iterations = opts->prec == PBCG_PREC_FP32_IR ? inner_total : h.iter + iters_before;
         info->fell_back = fell_back;
+        info->sliced = sliced;
         info->outer_iterations = outer;
         info->true_checks = h.true_checks;
         info->true_relres = zr ? 0.0 : h.true_rel;

@@ -3,7 +3,8 @@
 //  * spmv_seq_kernel   row-sequential CSR SpMV: every row is summed left to right by
 //                      one lane (the summation order of the plain definition of A.x),
 //                      with the block's val/col range staged through LDS by coalesced
-//                      loads in chunks; XCD-aware block -> row-range mapping.
+//                      loads in chunks; XCD-aware block -> row-range mapping.  SL: the
+//                      same sums read from a sliced (column-major, 256-row slice) copy.
 //  * spmv_kernel       vector-CSR SpMV: L lanes per row (L = 2..32 from the mean row
 //                      length, or L = 64: one wavefront per row), coalesced val/col
 //                      reads, xor-butterfly row reduction (same bits in every lane).
@@ -169,6 +170,60 @@ spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ c
     if (lane == 0) epi(row, s);
 }
 
+// Sliced copy of a CSR matrix (built by slice_width/scan/fill below): slice c holds rows
+// 256c .. 256c+255 column-major, entry k of the row in lane t at off[c] + 256 k + t,
+// padded to the slice's longest row (padding: col 0, value 0, never read for arithmetic).
+template <class VT>
+struct Sliced {
+    const int64_t* off = nullptr;   // [nslice + 1] entry offsets; null: use the CSR arrays
+    const int32_t* col = nullptr;
+    const VT* val = nullptr;
+};
+
+constexpr int SLICE_UNROLL = 8;   // entries of a row loaded ahead of their additions
+
+// One lane's row of slice c of a sliced copy (len entries, storage order): s (and the
+// Dot2 compensation cmp when COMP) accumulate exactly as in the staged path below.
+template <class VT, class XT, class AT, bool COMP>
+__device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, int len, const XT* __restrict__ x,
+                                          AT& s, AT& cmp) {
+    constexpr int U = SLICE_UNROLL, R = 256;
+    const int64_t base = sl.off[c];
+    const int w = (int)((sl.off[c + 1] - base) / R);
+    const VT* __restrict__ vp = sl.val + base + t;
+    const int32_t* __restrict__ cp = sl.col + base + t;
+    for (int k0 = 0; k0 < w; k0 += U) {
+        VT av[U];
+        int32_t cv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            av[u] = VT(0);
+            cv[u] = 0;
+            if (k0 + u < w) { av[u] = vp[(int64_t)(k0 + u) * R]; cv[u] = cp[(int64_t)(k0 + u) * R]; }
+        }
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = (k0 + u < len) ? x[cv[u]] : XT(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u < len) {
+                const AT a = (AT)av[u], xx = (AT)xv[u];
+                const AT prod = a * xx;
+                if constexpr (COMP) {
+                    const float pe = fmaf(a, xx, -prod);
+                    const float sn = s + prod;
+                    const float bb = sn - s;
+                    const float err = (s - (sn - bb)) + (prod - bb);
+                    s = sn;
+                    cmp = cmp + (err + pe);
+                } else {
+                    s = s + prod;
+                }
+            }
+        }
+    }
+}
+
 // Row-sequential SpMV engine (persistent, product-staged).
 //
 // Rows are taken in chunks of R = blockDim.x rows, one row per lane, and every row is
@@ -183,14 +238,20 @@ spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ c
 // (hardware block b runs on XCD b % 8), so the x planes a stencil row touches are
 // shared in that XCD's L2.
 //
+// With a sliced copy (SL, view in sl) a chunk is one slice: each lane walks its own row with
+// unit-stride (coalesced) val/col loads across the slice and gathers x for the entries
+// of its row; no LDS and no barriers.  Neighbouring lanes hold neighbouring rows, so
+// a stencil's gathers of one entry position are coalesced as well.  The additions are
+// the same as in the staged path (storage order), so the results are bit-identical.
+//
 // COMP (float only): compensated accumulation, algorithm Dot2 of Ogita, Rump and Oishi
 // (2005) in storage order -- the window holds (p, e) with p = fl(a x) and the exact
 // product error e = fma(a, x, -p); each lane runs TwoSum(s, p) and adds err + e into a
 // compensation c; the row's value is fl(s + c).  All arithmetic is float32.
-template <int CAP, class VT, class XT, class AT, class Body, bool COMP = false>
+template <int CAP, class VT, class XT, class AT, class Body, bool COMP = false, bool SL = false>
 __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const XT* __restrict__ x,
-                                          int bfirst, int G, AT* sprod, Body& body) {
+                                          int bfirst, int G, AT* sprod, Body& body, Sliced<VT> sl = {}) {
     static_assert(!COMP || (sizeof(AT) == 4 && sizeof(VT) == 4 && sizeof(XT) == 4), "Dot2 path is float32");
     constexpr int R = 256;            // blockDim.x
     constexpr int PER = CAP / R;
@@ -213,49 +274,53 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
     const int t = threadIdx.x;
     for (int c = cbeg + bi; c < cend; c += gper) {
         const int r0 = c * R, r1 = min(r0 + R, n), row = r0 + t;
-        const int A0 = rp[r0], A1 = rp[r1];
         int RA = 0, RB = 0;
         if (row < r1) { RA = rp[row]; RB = rp[row + 1]; }
         AT s = AT(0), cmp = AT(0);
-        for (int w = A0; w < A1; w += CAP) {
-            const int we = min(w + CAP, A1);
-            VT pv[PER];
-            int32_t pc[PER];
+        if constexpr (SL) {
+            slice_row<VT, XT, AT, COMP>(sl, c, t, RB - RA, x, s, cmp);
+        } else {
+            const int A0 = rp[r0], A1 = rp[r1];
+            for (int w = A0; w < A1; w += CAP) {
+                const int we = min(w + CAP, A1);
+                VT pv[PER];
+                int32_t pc[PER];
 #pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int k = w + t + j * R;
-                if (k < we) { pv[j] = val[k]; pc[j] = ci[k]; }
-            }
+                for (int j = 0; j < PER; ++j) {
+                    const int k = w + t + j * R;
+                    if (k < we) { pv[j] = val[k]; pc[j] = ci[k]; }
+                }
 #pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int k = w + t + j * R;
-                if (k < we) {
-                    const AT a = (AT)pv[j], xv = (AT)x[pc[j]];
-                    AT prod = a * xv;
-                    if constexpr (COMP) {
-                        float2* sp2 = (float2*)sprod;
-                        sp2[k - w] = make_float2(prod, fmaf(a, xv, -prod));
-                    } else {
-                        sprod[k - w] = prod;
+                for (int j = 0; j < PER; ++j) {
+                    const int k = w + t + j * R;
+                    if (k < we) {
+                        const AT a = (AT)pv[j], xv = (AT)x[pc[j]];
+                        AT prod = a * xv;
+                        if constexpr (COMP) {
+                            float2* sp2 = (float2*)sprod;
+                            sp2[k - w] = make_float2(prod, fmaf(a, xv, -prod));
+                        } else {
+                            sprod[k - w] = prod;
+                        }
                     }
                 }
-            }
-            __syncthreads();
-            const int ka = max(RA, w), kb = min(RB, we);
-            if constexpr (COMP) {
-                const float2* sp2 = (const float2*)sprod;
-                for (int k = ka; k < kb; ++k) {
-                    const float2 pe = sp2[k - w];
-                    const float sn = s + pe.x;
-                    const float bb = sn - s;
-                    const float err = (s - (sn - bb)) + (pe.x - bb);
-                    s = sn;
-                    cmp = cmp + (err + pe.y);
+                __syncthreads();
+                const int ka = max(RA, w), kb = min(RB, we);
+                if constexpr (COMP) {
+                    const float2* sp2 = (const float2*)sprod;
+                    for (int k = ka; k < kb; ++k) {
+                        const float2 pe = sp2[k - w];
+                        const float sn = s + pe.x;
+                        const float bb = sn - s;
+                        const float err = (s - (sn - bb)) + (pe.x - bb);
+                        s = sn;
+                        cmp = cmp + (err + pe.y);
+                    }
+                } else {
+                    for (int k = ka; k < kb; ++k) s = s + sprod[k - w];
                 }
-            } else {
-                for (int k = ka; k < kb; ++k) s = s + sprod[k - w];
+                __syncthreads();
             }
-            __syncthreads();
         }
         if constexpr (COMP) s = s + cmp;
         if (row < r1) body(row, s);
@@ -272,12 +337,13 @@ struct StoreBody {
 };
 
 // grid = worker blocks (+1 when block 0 carries a finalize role)
-template <class VT, class XT, class AT, class Epi, class Fin, bool COMP = false>
+template <class VT, class XT, class AT, class Epi, class Fin, bool COMP = false, bool SL = false>
 __global__ void __launch_bounds__(256)
 spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt) {
+                const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt,
+                Sliced<VT> sl) {
     if (halt && *halt) return;
-    constexpr int STAGE = SEQ_CAP * (int)sizeof(AT) * (COMP ? 2 : 1);
+    constexpr int STAGE = SL ? 16 : SEQ_CAP * (int)sizeof(AT) * (COMP ? 2 : 1);
     constexpr int SMEM = Fin::SMEM > STAGE ? Fin::SMEM : STAGE;
     __shared__ __align__(16) unsigned char smem[SMEM];
     int bfirst = 0;
@@ -289,8 +355,65 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
         bfirst = 1;
     }
     StoreBody<Epi> body{epi};
-    seq_stage<SEQ_CAP, VT, XT, AT, StoreBody<Epi>, COMP>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst,
-                                                          (AT*)smem, body);
+    seq_stage<SEQ_CAP, VT, XT, AT, StoreBody<Epi>, COMP, SL>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst,
+                                                              (AT*)smem, body, sl);
+}
+
+// Sliced copy, step 1: off[c + 1] = 256 * (longest row of slice c), off[0] = 0.
+__global__ void __launch_bounds__(256) slice_width_kernel(int n, const int32_t* __restrict__ rp,
+                                                          int64_t* __restrict__ off) {
+    __shared__ int sh[4];
+    const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
+    int len = row < n ? rp[row + 1] - rp[row] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o));
+    if ((t & 63) == 0) sh[t >> 6] = len;
+    __syncthreads();
+    if (t == 0) {
+        off[c + 1] = 256LL * max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+        if (c == 0) off[0] = 0;
+    }
+}
+
+// Step 2 (one block of 1024): off[1..ns] -> inclusive prefix sums.
+__global__ void __launch_bounds__(1024) slice_scan_kernel(int ns, int64_t* __restrict__ off) {
+    __shared__ int64_t sh[1024];
+    const int t = threadIdx.x;
+    const int per = (ns + 1023) / 1024;
+    const int64_t a = 1 + (int64_t)t * per, b = min(a + per, (int64_t)ns + 1);
+    int64_t sum = 0;
+    for (int64_t i = a; i < b; ++i) sum += off[i];
+    sh[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? sh[t - 1] : 0;
+    for (int64_t i = a; i < b; ++i) {
+        run += off[i];
+        off[i] = run;
+    }
+}
+
+// Step 3: copy every row into its slice (lane t of block c: row 256c + t).
+template <class VT>
+__global__ void __launch_bounds__(256) slice_fill_kernel(int n, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci, const VT* __restrict__ val,
+                                                         const int64_t* __restrict__ off, int32_t* __restrict__ scol,
+                                                         VT* __restrict__ sval) {
+    const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
+    const int64_t base = off[c];
+    const int w = (int)((off[c + 1] - base) / 256);
+    int a = 0, len = 0;
+    if (row < n) { a = rp[row]; len = rp[row + 1] - a; }
+    for (int k = 0; k < w; ++k) {
+        const int64_t i = base + (int64_t)k * 256 + t;
+        if (k < len) { scol[i] = ci[a + k]; sval[i] = val[a + k]; }
+        else { scol[i] = 0; sval[i] = VT(0); }
+    }
 }
 
 // ----------------------------------------------------------------------------- dot sites
@@ -407,14 +530,14 @@ struct DotBody {
     }
 };
 
-template <int D, int K, class VT, class Epi>
+template <int D, int K, class VT, class Epi, bool SL = false>
 __global__ void __launch_bounds__(256)
 spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const VT* __restrict__ val, const double* __restrict__ x, Epi epi,
-                    xd::Site site, const int* halt) {
+                    xd::Site site, const int* halt, Sliced<VT> sl) {
     if (halt && *halt) return;
     XD_SHARED(D)
-    __shared__ double sprod[SEQ_CAP];
+    __shared__ double sprod[SL ? 2 : SEQ_CAP];
     xd::block_init<D>(sh_acc, sh_flags);
     epi.load();
     double e[D][K];
@@ -423,7 +546,8 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 #pragma unroll
         for (int k = 0; k < K; ++k) e[d][k] = 0.0;
     DotBody<D, K, Epi> body{epi, e, sh_acc, sh_flags};
-    seq_stage<SEQ_CAP, VT, double, double>(n, rp, ci, val, x, 0, (int)gridDim.x, sprod, body);
+    seq_stage<SEQ_CAP, VT, double, double, DotBody<D, K, Epi>, false, SL>(n, rp, ci, val, x, 0, (int)gridDim.x,
+                                                                            sprod, body, sl);
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
 }

@@ -1,0 +1,134 @@
+"""GPU sliced copies (csr_slice) vs the oracle.
+
+The sliced layout stores slices of 256 rows column-major and pads each slice to its
+longest row; one lane walks one row in storage order, so the products must be
+bit-identical to the oracle's row-sequential SpMV (FP64, and FP32 with Dot2).  The
+padded size is an integer fixed by the row lengths: it must equal the host count
+exactly, and the copy is built exactly when that count is within nnz + nnz/8 + 256.
+A solve with the sliced copy must return the same bits as one on CSR.
+"""
+import numpy as np
+import pytest
+
+import paper_2404_13216_amd as pk
+import synthgen as g
+from oracle import ctier
+from oracle.spmv import spmv, spmv_f32
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def padded_entries(A):
+    """Host count of the sliced size: 256 x the longest row of every slice of 256 rows."""
+    lens = np.diff(A.row_ptr.astype(np.int64))
+    ns = (A.n + 255) // 256
+    lp = np.zeros(ns * 256, dtype=np.int64)
+    lp[:A.n] = lens
+    return int(256 * lp.reshape(ns, 256).max(axis=1).sum())
+
+
+def expect_built(A):
+    return padded_entries(A) <= A.nnz + A.nnz // 8 + 256
+
+
+def ragged(n, lens, seed):
+    rng = np.random.default_rng(seed)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(n, size=int(k), replace=False)) for k in lens] +
+                        [np.zeros(0, dtype=np.int64)]).astype(np.int32)
+    return g.CSR(n, rp, ci, rng.standard_normal(int(rp[-1])))
+
+
+def cases():
+    out = [(name, g.problem(name, scale=sc).A) for name, sc in
+           (("cd2d_64", None), ("cd3d_128", 20), ("cd3d_256_var", 17), ("spai_eval_128", 9), ("rand_1m", 50000))]
+    rng = np.random.default_rng(7)
+    # ragged tail (n not a multiple of 256), empty rows, lengths 6..7 (built)
+    lens = rng.integers(6, 8, 1000)
+    lens[::97] = 0
+    out.append(("ragged_1000", ragged(1000, lens, 1)))
+    out.append(("tiny_37", ragged(37, rng.integers(0, 2, 37), 2)))          # one partial slice (built)
+    lens = rng.integers(5, 8, 1000)
+    lens[::17] = 0
+    out.append(("ragged_unbuilt", ragged(1000, lens, 5)))                     # padding above nnz/8 + 256
+    out.append(("all_empty", ragged(300, np.zeros(300, dtype=np.int64), 3)))  # nnz = 0
+    lens = np.full(2000, 4)
+    lens[300] = 1500                                                          # one long row
+    out.append(("one_long_row", ragged(2000, lens, 4)))
+    return out
+
+
+@pytest.mark.parametrize("name,A", cases(), ids=[c[0] for c in cases()])
+def test_sliced_spmv_bitwise(name, A):
+    dA = pk.CSR.from_host(A)
+    S = pk.SlicedCSR(dA)
+    assert S.entries == padded_entries(A)
+    assert S.built == expect_built(A)
+    x = np.random.default_rng(11).uniform(-1, 1, A.n)
+    ref = spmv(A, x)
+    if not S.built:
+        with pytest.raises(pk.LibError):
+            pk.csr_spmv_sliced(S, to_dev(x))
+        return
+    y = pk.csr_spmv_sliced(S, to_dev(x)).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
+    y2 = pk.csr_spmv(dA, to_dev(x)).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), y2.view(np.uint64))
+    # FP32 values: the FP64-accumulating product and the Dot2 FP32 product
+    import torch
+    A32 = dA.with_values(dA.val.to(torch.float32))
+    S32 = pk.SlicedCSR(A32)
+    assert S32.built and S32.entries == S.entries
+    A32h = g.CSR(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32).astype(np.float64))
+    y = pk.csr_spmv_sliced(S32, to_dev(x)).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), spmv(A32h, x).view(np.uint64))
+    x32 = x.astype(np.float32)
+    A32o = g.CSR(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32))
+    y32 = pk.csr_spmv_f32_sliced(S32, to_dev(x32)).cpu().numpy()
+    assert np.array_equal(y32.view(np.uint32), spmv_f32(A32o, x32).view(np.uint32))
+
+
+def test_sliced_spmv_full_size_128():
+    """128^3 (2,097,152 rows): every row bit-identical to the C oracle."""
+    p = g.problem("cd3d_128")
+    S = pk.SlicedCSR(pk.CSR.from_host(p.A))
+    assert S.built and S.entries == padded_entries(p.A)
+    x = np.random.default_rng(5).uniform(-1, 1, p.A.n)
+    y = pk.csr_spmv_sliced(S, to_dev(x)).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), ctier.spmv(p.A, x).view(np.uint64))
+
+
+@pytest.mark.parametrize("name,scale,prec", [("cd3d_128", 20, pk.PREC_FP64), ("cd2d_64", None, pk.PREC_FP64),
+                                             ("cd3d_128", 20, pk.PREC_FP32_IR), ("rand_1m", 20000, pk.PREC_FP64)])
+def test_solve_same_bits_with_and_without_slices(name, scale, prec):
+    p = g.problem(name, scale=scale)
+    A = pk.CSR.from_host(p.A)
+    b = to_dev(p.b)
+    xa, ia = pk.solve(A, b, tol=1e-10, prec=prec)
+    xc, ic = pk.solve(A, b, tol=1e-10, prec=prec, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == (1 if expect_built(p.A) else 0)
+    assert ic["sliced"] == 0
+    for k in ("status", "iterations", "outer_iterations", "true_checks"):
+        assert ia[k] == ic[k], k
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+
+
+def test_preconditioned_solve_slices_m():
+    """Jacobi M (diagonal) and an M on A's pattern are sliced as well."""
+    p = g.problem("cd3d_128", scale=20)
+    A = pk.CSR.from_host(p.A)
+    b = to_dev(p.b)
+    J = pk.jacobi(A)
+    xa, ia = pk.solve(A, b, M=J, tol=1e-10)
+    xc, ic = pk.solve(A, b, M=J, tol=1e-10, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == 3 and ic["sliced"] == 0
+    assert ia["iterations"] == ic["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+    # M on A's pattern: scaled copy of A's values
+    M = A.with_values(A.val * 0.5)
+    xa, ia = pk.solve(A, b, M=M, tol=1e-10, max_iter=50)
+    xc, ic = pk.solve(A, b, M=M, tol=1e-10, max_iter=50, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == 3
+    assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))

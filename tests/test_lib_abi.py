@@ -35,7 +35,7 @@ def test_all_declared_symbols_exported():
 def _c_layout(tmp_path):
     """sizeof / offsetof of every field, printed by a C program compiled against the header."""
     structs = {"pbcg_csr": pk.PbcgCsr, "pbcg_opts": pk.PbcgOpts, "pbcg_info": pk.PbcgInfo,
-               "pbcg_vectors": pk.PbcgVectors}
+               "pbcg_vectors": pk.PbcgVectors, "pbcg_sliced": pk.PbcgSliced}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pbicgstab.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -56,7 +56,7 @@ def test_struct_layout_matches_header(tmp_path):
         assert lay[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert lay[(cname, f)] == getattr(py, f).offset, (cname, f)
-    assert pk.lib().pbcg_abi_version() == 4
+    assert pk.lib().pbcg_abi_version() == 5
 
 
 def test_status_strings_and_defaults():
@@ -81,6 +81,15 @@ def test_host_argument_checks_without_gpu():
     assert L.pbicgstab_solve(ctypes.byref(good), 1, 1, ctypes.byref(o), None, None, 0, None) == pk.ERR_WORKSPACE
     o.tol = -1.0
     assert L.pbicgstab_solve(ctypes.byref(good), 1, 1, ctypes.byref(o), None, 256, 1 << 20, None) == pk.ERR_INVALID
+    # sliced copies: bad matrix, missing workspace, unbuilt copy
+    S = pk.PbcgSliced()
+    assert L.csr_slice(None, ctypes.byref(S), None, 0, None) == pk.ERR_INVALID
+    assert L.csr_slice(ctypes.byref(good), None, None, 0, None) == pk.ERR_INVALID
+    assert L.csr_slice(ctypes.byref(good), ctypes.byref(S), None, 0, None) == pk.ERR_WORKSPACE
+    assert L.csr_slice(ctypes.byref(good), ctypes.byref(S), 256, 16, None) == pk.ERR_WORKSPACE
+    assert L.csr_spmv_sliced(ctypes.byref(good), ctypes.byref(S), 8, 16, None) == pk.ERR_INVALID
+    assert L.csr_spmv_sliced(ctypes.byref(good), None, 8, 16, None) == pk.ERR_INVALID
+    assert L.csr_spmv_f32_sliced(ctypes.byref(good), ctypes.byref(S), 8, 16, None) == pk.ERR_INVALID  # F64 values
 
 
 def test_workspace_sizes_monotone():
@@ -92,3 +101,12 @@ def test_workspace_sizes_monotone():
     o.prec = pk.PREC_FP32_IR
     c = L.pbicgstab_workspace_bytes(100000, 500000, ctypes.byref(o))
     assert c >= b + 11 * 100000 * 4 + 500000 * 4
+    # the sliced copy (layout AUTO, the default): 12 bytes per entry of nnz + nnz/8 + 256
+    o.prec = pk.PREC_FP64
+    o.layout = pk.LAYOUT_CSR
+    d = L.pbicgstab_workspace_bytes(100000, 500000, ctypes.byref(o))
+    assert b - d >= 12 * (500000 + 500000 // 8 + 256) + 8 * (100000 // 256 + 1)
+    o.spmv_kind, o.layout = pk.SPMV_VECTOR, pk.LAYOUT_AUTO     # only the row-sequential kernels slice
+    assert L.pbicgstab_workspace_bytes(100000, 500000, ctypes.byref(o)) == d
+    assert L.csr_slice_workspace_bytes(100000, 500000) >= 12 * (500000 + 500000 // 8 + 256)
+    assert L.csr_slice_workspace_bytes(-1, 0) == 0
