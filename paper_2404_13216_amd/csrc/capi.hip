@@ -689,6 +689,19 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
     return W;
 }
 
+// Bytes an iteration keeps re-reading: the matrices (each SpMV reads them whole) and the
+// Krylov vectors.  Above the 256 MB Infinity Cache the phases stream their outputs past the
+// caches (non-temporal stores); below it the whole iteration can stay cache-resident and
+// plain stores are faster.
+constexpr double INFINITY_CACHE_BYTES = 256.0 * 1024 * 1024;
+
+double matrix_bytes(const pbcg_csr* A, int64_t sliced_entries, int value_bytes) {
+    if (!A) return 0.0;
+    const double entries = sliced_entries > 0 ? (double)sliced_entries : (double)A->nnz;
+    return entries * (value_bytes + 4) + 4.0 * ((double)A->n + 1) +
+           (sliced_entries > 0 ? 8.0 * (nslices(A->n) + 1) : 0.0);
+}
+
 constexpr int CONTINUE = -100;
 constexpr int STALLED = 4;   // internal status of a stalled preconditioned solve
 
@@ -709,6 +722,8 @@ struct Driver {
     pbcg_csr A32c;         // FP32 copy of A (refinement) ...
     Mat A32;               // ... with the FP32 sliced values when A is sliced
     int64_t a_entries = 0; // entries of A's sliced copy
+    bool nt64 = false;     // stream the FP64 phase outputs past the caches ...
+    bool nt32 = false;     // ... and the FP32 ones (working set above the Infinity Cache)
     int rr_period = 0;             // residual replacement period of the current run
     double fail_best = INFINITY;   // best true residual of a failed stopping test
     int fail_stag = 0;             // failed tests in a row without improving on it
@@ -788,15 +803,21 @@ struct Driver {
     }
 
     void enqueue_iteration_p(bool first) {
+        if (nt64) enqueue_iteration_p_t<true>(first);
+        else enqueue_iteration_p_t<false>(first);
+    }
+
+    template <bool NT>
+    void enqueue_iteration_p_t(bool first) {
         const int n = A->n;
         const double* scal = &W.st->alpha;
-        PhaseA<FinOmega> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
-                            FinOmega{W.st, 1}};
-        PhaseB<FinPhaseB> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
+        PhaseA<FinOmega, NT> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
+                                FinOmega{W.st, 1}};
+        PhaseB<FinPhaseB, NT> pb{x, W.p, W.q, W.y, W.t, W.v, W.rhat, W.r, W.w, scal, FinPhaseB{W.st}};
         if (o->dots == PBCG_DOTS_PLAIN) {
-            auto fa = launch_ew_fdot_deferred<4>(ElemOf<PhaseA<FinOmega>>{pa}, n, W.dsite, halt, s, seen);
+            auto fa = launch_ew_fdot_deferred<4>(ElemOf<PhaseA<FinOmega, NT>>{pa}, n, W.dsite, halt, s, seen);
             op(W.z, W.v, fa, seen);
-            auto fb = launch_ew_fdot_deferred<3>(ElemOf<PhaseB<FinPhaseB>>{pb}, n, W.dsite, halt, s, seen);
+            auto fb = launch_ew_fdot_deferred<3>(ElemOf<PhaseB<FinPhaseB, NT>>{pb}, n, W.dsite, halt, s, seen);
             op(W.w, W.t, fb, seen);
             return;
         }
@@ -933,15 +954,27 @@ struct Driver {
         }
     }
 
+    // One FP32 iteration: phase A, v = A z, phase B, t = A w.
+    template <bool NT>
+    void enqueue_iteration_f32(bool first) {
+        const int n = A->n;
+        FState* fs = W.fst;
+        const float* scal = &fs->alpha;
+        FPhaseA<FFinOmega, NT> pa{W.r32, W.w32, W.t32, W.v32, W.rh32, W.p32, W.s32, W.z32, W.q32, W.y32,
+                                  scal, first ? 1 : 0, FFinOmega{fs}};
+        auto fa = launch_ew_fdot_deferred<4>(pa, n, W.fsite, &fs->halt, s, &fs->halt_seen);
+        launch_spmv32c(A32, W.z32, EpiStore<float>{W.v32}, &fs->halt_seen, s, fa);
+        FPhaseB<FFinRU, NT> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
+                               FFinRU{fs}};
+        auto fb = launch_ew_fdot_deferred<3>(pb, n, W.fsite, &fs->halt, s, &fs->halt_seen);
+        launch_spmv32c(A32, W.w32, EpiStore<float>{W.t32}, &fs->halt_seen, s, fb);
+    }
+
     // FP32 p-BiCGStab (Algorithm 2) on A32 with right-hand side W.r32, x0 = 0 -> W.d32.
     // FP32 iterations (phase A, v = A z, phase B, t = A w) until a finalizer sets a stop
     // reason; returns the final FState in hf.
     int run_fp32(FState& hf, bool first) {
-        const int n = A->n;
         FState* fs = W.fst;
-        int* fh = &fs->halt;
-        int* fseen = &fs->halt_seen;
-        const float* scal = &fs->alpha;
         int polled = 0, batches = 0;
         const long long limit = (long long)std::max(o->max_iter, 1) + 4LL * batch + 64;
         long long enqueued = 0;
@@ -949,14 +982,8 @@ struct Driver {
             if (enqueued > limit) return PBCG_ERR_HIP;   // a stop reason must have come (MAXIT)
             enqueued += batch;
             for (int k = 0; k < batch; ++k) {
-                FPhaseA<FFinOmega> pa{W.r32, W.w32, W.t32, W.v32, W.rh32, W.p32, W.s32, W.z32, W.q32, W.y32,
-                                      scal, first ? 1 : 0, FFinOmega{fs}};
-                auto fa = launch_ew_fdot_deferred<4>(pa, n, W.fsite, fh, s, fseen);
-                launch_spmv32c(A32, W.z32, EpiStore<float>{W.v32}, fseen, s, fa);
-                FPhaseB<FFinRU> pb{W.d32, W.p32, W.q32, W.y32, W.t32, W.v32, W.rh32, W.r32, W.w32, scal,
-                                   FFinRU{fs}};
-                auto fb = launch_ew_fdot_deferred<3>(pb, n, W.fsite, fh, s, fseen);
-                launch_spmv32c(A32, W.w32, EpiStore<float>{W.t32}, fseen, s, fb);
+                if (nt32) enqueue_iteration_f32<true>(first);
+                else enqueue_iteration_f32<false>(first);
                 first = false;
             }
             HIPCHK(hipGetLastError());
@@ -1171,6 +1198,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     D.max_iter = opts->max_iter;
     D.rr_period = opts->rr_period;
     int sliced = 0;   // bit 0: A, bit 1: M use a sliced copy
+    int64_t m_entries = 0;
     if (slicing_on(opts)) {
         const int64_t ta = build_slices(A, W.a_off, W.a_col, W.a_val, slice_cap(A->nnz), D.s);
         if (ta < 0) return PBCG_ERR_HIP;
@@ -1184,9 +1212,21 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
             if (tm < 0) return PBCG_ERR_HIP;
             if (tm <= slice_cap(opts->M->nnz)) {
                 D.M.sl = SliceView{W.m_off, W.m_col, W.m_val};
+                m_entries = tm;
                 sliced |= 2;
             }
         }
+    }
+    {
+        const int64_t ma = (sliced & 1) ? D.a_entries : 0;
+        const int vb = A->val_type == PBCG_F64 ? 8 : 4;
+        double ws64 = matrix_bytes(A, ma, vb) + 12.0 * 8.0 * A->n;
+        if (opts->M) {
+            const int64_t mm = (sliced & 2) ? m_entries : 0;
+            ws64 += matrix_bytes(opts->M, mm, opts->M->val_type == PBCG_F64 ? 8 : 4) + 8.0 * A->n;
+        }
+        D.nt64 = ws64 > INFINITY_CACHE_BYTES;
+        D.nt32 = matrix_bytes(A, ma, 4) + 11.0 * 4.0 * A->n > INFINITY_CACHE_BYTES;
     }
     State h{};
     int status;

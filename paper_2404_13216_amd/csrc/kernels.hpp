@@ -623,8 +623,17 @@ __global__ void single_kernel(F f) {
 }
 
 // ============================================================================= p-BiCGStab ops
+// Store of a phase output.  NT: non-temporal (streamed past the caches), chosen when the
+// iteration's working set exceeds the Infinity Cache, so that the matrix and the vectors
+// read again in the same iteration are not evicted by outputs read only later.
+template <bool NT, class T>
+__device__ __forceinline__ void put(T* p, int64_t i, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p + i);
+    else p[i] = v;
+}
+
 // Phase A (Algorithm 2, the p, s, z, q, y updates) + (q,y), (y,y), (r_hat,s), (r_hat,z).
-template <class Fin>
+template <class Fin, bool NT = false>
 struct PhaseA {
     const double* r; const double* w; const double* t; const double* v; const double* rhat;
     double* p; double* s; double* z; double* q; double* y;
@@ -651,7 +660,7 @@ struct PhaseA {
         }
         const double qi = ri - alpha * si;
         const double yi = wi - alpha * zi;
-        p[i] = pi; s[i] = si; z[i] = zi; q[i] = qi; y[i] = yi;
+        put<NT>(p, i, pi); put<NT>(s, i, si); put<NT>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
         const double rh = in[3];
         xa[0] = qi; ya[0] = yi;
         xa[1] = yi; ya[1] = yi;
@@ -662,7 +671,7 @@ struct PhaseA {
 };
 
 // Phase B (x, r, w updates) + (r_hat,r), (r_hat,w), (r,r).
-template <class Fin>
+template <class Fin, bool NT = false>
 struct PhaseB {
     double* x; const double* p; const double* q; const double* y; const double* t; const double* v;
     const double* rhat; double* r; double* w;
@@ -680,7 +689,7 @@ struct PhaseB {
         const double xi = (in[0] + alpha * in[1]) + omega * qi;
         const double ri = qi - omega * yi;
         const double wi = yi - omega * (in[4] - alpha * in[5]);
-        x[i] = xi; r[i] = ri; w[i] = wi;
+        put<NT>(x, i, xi); put<NT>(r, i, ri); put<NT>(w, i, wi);
         const double rh = in[6];
         xa[0] = rh; ya[0] = ri;
         xa[1] = rh; ya[1] = wi;
@@ -947,7 +956,7 @@ struct OpBiCGStabXR {
 };
 
 // ============================================================================= FP32 inner solver ops
-template <class Fin>
+template <class Fin, bool NT = false>
 struct FPhaseA {
     const float* r; const float* w; const float* t; const float* v; const float* rhat;
     float* p; float* s; float* z; float* q; float* y;
@@ -966,7 +975,7 @@ struct FPhaseA {
         }
         const float qi = ri - alpha * si;
         const float yi = wi - alpha * zi;
-        p[i] = pi; s[i] = si; z[i] = zi; q[i] = qi; y[i] = yi;
+        put<NT>(p, i, pi); put<NT>(s, i, si); put<NT>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
         const float rh = rhat[i];
         xa[0] = qi; ya[0] = yi;
         xa[1] = yi; ya[1] = yi;
@@ -976,7 +985,7 @@ struct FPhaseA {
     __device__ __forceinline__ void finalize(const float* d) { fin(d); }
 };
 
-template <class Fin>
+template <class Fin, bool NT = false>
 struct FPhaseB {
     float* x; const float* p; const float* q; const float* y; const float* t; const float* v;
     const float* rhat; float* r; float* w; const float* scal; Fin fin;
@@ -987,7 +996,7 @@ struct FPhaseB {
         const float xi = (x[i] + alpha * p[i]) + omega * qi;
         const float ri = qi - omega * yi;
         const float wi = yi - omega * (t[i] - alpha * v[i]);
-        x[i] = xi; r[i] = ri; w[i] = wi;
+        put<NT>(x, i, xi); put<NT>(r, i, ri); put<NT>(w, i, wi);
         const float rh = rhat[i];
         xa[0] = rh; ya[0] = ri;
         xa[1] = rh; ya[1] = wi;
