@@ -308,15 +308,17 @@ struct FnAxpyState {      // x = x + alpha p  (alpha from state)
     double* x; const double* p; const State* st;
     __device__ void operator()(int64_t i) const { x[i] = x[i] + st->alpha * p[i]; }
 };
+template <bool NT>
 struct FnQ {              // q = r - alpha s
     double* q; const double* r; const double* s; const double* scal;
-    __device__ void operator()(int64_t i) const { q[i] = r[i] - scal[0] * s[i]; }
+    __device__ void operator()(int64_t i) const { put<NT>(q, i, get<NT>(r, i) - scal[0] * get<NT>(s, i)); }
 };
+template <bool NT>
 struct FnPUpdate {        // p = r + beta (p - omega s), skipped before the first iteration
     double* p; const double* r; const double* s; const State* st;
     __device__ void operator()(int64_t i) const {
         if (st->iter == 0) return;
-        p[i] = r[i] + st->beta * (p[i] - st->omega * s[i]);
+        put<NT>(p, i, get<NT>(r, i) + st->beta * (get<NT, double>(p, i) - st->omega * get<NT>(s, i)));
     }
 };
 struct FnCastScaled {     // r32 = fp32(r / nu)
@@ -852,13 +854,19 @@ struct Driver {
     }
 
     void enqueue_iteration_b() {
+        if (nt64) enqueue_iteration_b_t<true>();
+        else enqueue_iteration_b_t<false>();
+    }
+
+    template <bool NT>
+    void enqueue_iteration_b_t() {
         const int n = A->n;
         const double* scal = &W.st->alpha;
-        launch_ew(FnPUpdate{W.p, W.r, W.s, W.st}, n, halt, s);
-        launch_spmv_dot<1>(A, W.p, EpiSDot{W.s, W.rhat, FinAlphaB{W.st}}, W.site, halt, s, kind);
-        launch_ew(FnQ{W.q, W.r, W.s, scal}, n, halt, s);
-        launch_spmv_dot<2>(A, W.q, EpiYDot{W.y, W.q, FinOmega{W.st, 0}}, W.site, halt, s, kind);
-        OpBiCGStabXR ox{x, W.p, W.q, W.y, W.rhat, W.r, scal, FinBiCGStabXR{W.st}};
+        launch_ew(FnPUpdate<NT>{W.p, W.r, W.s, W.st}, n, halt, s);
+        launch_spmv_dot<1>(A, W.p, EpiSDot<NT>{W.s, W.rhat, FinAlphaB{W.st}}, W.site, halt, s, kind);
+        launch_ew(FnQ<NT>{W.q, W.r, W.s, scal}, n, halt, s);
+        launch_spmv_dot<2>(A, W.q, EpiYDot<NT>{W.y, W.q, FinOmega{W.st, 0}}, W.site, halt, s, kind);
+        OpBiCGStabXR<NT> ox{x, W.p, W.q, W.y, W.rhat, W.r, scal, FinBiCGStabXR{W.st}};
         launch_ew_dot<2>(ox, n, W.site, halt, s);
     }
 

@@ -623,9 +623,15 @@ __global__ void single_kernel(F f) {
 }
 
 // ============================================================================= p-BiCGStab ops
-// Store of a phase output.  NT: non-temporal (streamed past the caches), chosen when the
-// iteration's working set exceeds the Infinity Cache, so that the matrix and the vectors
-// read again in the same iteration are not evicted by outputs read only later.
+// Loads and stores of the phases' vectors.  NT: non-temporal (streamed past the caches),
+// chosen when the iteration's working set exceeds the Infinity Cache: the vectors then
+// do not evict the matrix, which both SpMVs of the iteration read whole.
+template <bool NT, class T>
+__device__ __forceinline__ T get(const T* p, int64_t i) {
+    if constexpr (NT) return __builtin_nontemporal_load(p + i);
+    else return p[i];
+}
+
 template <bool NT, class T>
 __device__ __forceinline__ void put(T* p, int64_t i, T v) {
     if constexpr (NT) __builtin_nontemporal_store(v, p + i);
@@ -645,8 +651,11 @@ struct PhaseA {
     static constexpr int NIN = 8;
     __device__ __forceinline__ void load() { alpha = scal[0]; beta = scal[1]; omega = scal[2]; }
     __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
-        in[0] = r[i]; in[1] = w[i]; in[2] = t[i]; in[3] = rhat[i];
-        if (!first) { in[4] = p[i]; in[5] = s[i]; in[6] = z[i]; in[7] = v[i]; }
+        in[0] = get<NT>(r, i); in[1] = get<NT>(w, i); in[2] = get<NT>(t, i); in[3] = get<NT>(rhat, i);
+        if (!first) {
+            in[4] = get<NT, double>(p, i); in[5] = get<NT, double>(s, i);
+            in[6] = get<NT, double>(z, i); in[7] = get<NT>(v, i);
+        }
     }
     __device__ __forceinline__ void st(int64_t i, const double (&in)[NIN], double (&xa)[4], double (&ya)[4]) {
         const double ri = in[0], wi = in[1], ti = in[2];
@@ -682,7 +691,8 @@ struct PhaseB {
     static constexpr int NIN = 7;
     __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
     __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
-        in[0] = x[i]; in[1] = p[i]; in[2] = q[i]; in[3] = y[i]; in[4] = t[i]; in[5] = v[i]; in[6] = rhat[i];
+        in[0] = get<NT, double>(x, i); in[1] = get<NT>(p, i); in[2] = get<NT>(q, i); in[3] = get<NT>(y, i);
+        in[4] = get<NT>(t, i); in[5] = get<NT>(v, i); in[6] = get<NT>(rhat, i);
     }
     __device__ __forceinline__ void st(int64_t i, const double (&in)[NIN], double (&xa)[3], double (&ya)[3]) {
         const double qi = in[2], yi = in[3];
@@ -891,22 +901,24 @@ struct FinAlphaB {
     }
 };
 
+template <bool NT = false>
 struct EpiSDot {
     double* s; const double* rhat; FinAlphaB fin;
     __device__ __forceinline__ void load() {}
     __device__ __forceinline__ void row(int i, double v, double (&xa)[1], double (&ya)[1]) {
-        s[i] = v; xa[0] = rhat[i]; ya[0] = v;
+        put<NT>(s, i, v); xa[0] = get<NT>(rhat, i); ya[0] = v;
     }
     __device__ __forceinline__ void finalize(const double* d) { fin(d); }
 };
 
 // y = A q with (q,y), (y,y)
+template <bool NT = false>
 struct EpiYDot {
     double* y; const double* q; FinOmega fin;
     __device__ __forceinline__ void load() {}
     __device__ __forceinline__ void row(int i, double v, double (&xa)[2], double (&ya)[2]) {
-        y[i] = v;
-        double qi = q[i];
+        put<NT>(y, i, v);
+        double qi = get<NT>(q, i);
         xa[0] = qi; ya[0] = v;
         xa[1] = v; ya[1] = v;
     }
@@ -935,6 +947,7 @@ struct FinBiCGStabXR {
     }
 };
 
+template <bool NT = false>
 struct OpBiCGStabXR {
     double* x; const double* p; const double* q; const double* y; const double* rhat; double* r;
     const double* scal; FinBiCGStabXR fin;
@@ -942,13 +955,14 @@ struct OpBiCGStabXR {
     static constexpr int NIN = 5;
     __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
     __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
-        in[0] = x[i]; in[1] = p[i]; in[2] = q[i]; in[3] = y[i]; in[4] = rhat[i];
+        in[0] = get<NT, double>(x, i); in[1] = get<NT>(p, i); in[2] = get<NT>(q, i); in[3] = get<NT>(y, i);
+        in[4] = get<NT>(rhat, i);
     }
     __device__ __forceinline__ void st(int64_t i, const double (&in)[NIN], double (&xa)[2], double (&ya)[2]) {
         const double qi = in[2];
         const double xi = (in[0] + alpha * in[1]) + omega * qi;
         const double ri = qi - omega * in[3];
-        x[i] = xi; r[i] = ri;
+        put<NT>(x, i, xi); put<NT>(r, i, ri);
         xa[0] = in[4]; ya[0] = ri;
         xa[1] = ri; ya[1] = ri;
     }
@@ -964,11 +978,12 @@ struct FPhaseA {
     float alpha, beta, omega;
     __device__ __forceinline__ void load() { alpha = scal[0]; beta = scal[1]; omega = scal[2]; }
     __device__ __forceinline__ void elem(int64_t i, float (&xa)[4], float (&ya)[4]) {
-        const float ri = r[i], wi = w[i], ti = t[i];
+        const float ri = get<NT>(r, i), wi = get<NT>(w, i), ti = get<NT>(t, i);
         float pi, si, zi;
         if (first) { pi = ri; si = wi; zi = ti; }
         else {
-            const float pp = p[i], sp = s[i], zp = z[i], vp = v[i];
+            const float pp = get<NT, float>(p, i), sp = get<NT, float>(s, i), zp = get<NT, float>(z, i),
+                        vp = get<NT>(v, i);
             pi = ri + beta * (pp - omega * sp);
             si = wi + beta * (sp - omega * zp);
             zi = ti + beta * (zp - omega * vp);
@@ -976,7 +991,7 @@ struct FPhaseA {
         const float qi = ri - alpha * si;
         const float yi = wi - alpha * zi;
         put<NT>(p, i, pi); put<NT>(s, i, si); put<NT>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
-        const float rh = rhat[i];
+        const float rh = get<NT>(rhat, i);
         xa[0] = qi; ya[0] = yi;
         xa[1] = yi; ya[1] = yi;
         xa[2] = rh; ya[2] = si;
@@ -992,12 +1007,12 @@ struct FPhaseB {
     float alpha, omega;
     __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
     __device__ __forceinline__ void elem(int64_t i, float (&xa)[3], float (&ya)[3]) {
-        const float qi = q[i], yi = y[i];
-        const float xi = (x[i] + alpha * p[i]) + omega * qi;
+        const float qi = get<NT>(q, i), yi = get<NT>(y, i);
+        const float xi = (get<NT, float>(x, i) + alpha * get<NT>(p, i)) + omega * qi;
         const float ri = qi - omega * yi;
-        const float wi = yi - omega * (t[i] - alpha * v[i]);
+        const float wi = yi - omega * (get<NT>(t, i) - alpha * get<NT>(v, i));
         put<NT>(x, i, xi); put<NT>(r, i, ri); put<NT>(w, i, wi);
-        const float rh = rhat[i];
+        const float rh = get<NT>(rhat, i);
         xa[0] = rh; ya[0] = ri;
         xa[1] = rh; ya[1] = wi;
         xa[2] = ri; ya[2] = ri;
