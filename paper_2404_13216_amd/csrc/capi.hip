@@ -308,17 +308,18 @@ struct FnAxpyState {      // x = x + alpha p  (alpha from state)
     double* x; const double* p; const State* st;
     __device__ void operator()(int64_t i) const { x[i] = x[i] + st->alpha * p[i]; }
 };
+// (BiCGStab) q and p are the operands of the SpMV that follows: plain stores
 template <bool NT>
 struct FnQ {              // q = r - alpha s
     double* q; const double* r; const double* s; const double* scal;
-    __device__ void operator()(int64_t i) const { put<NT>(q, i, get<NT>(r, i) - scal[0] * get<NT>(s, i)); }
+    __device__ void operator()(int64_t i) const { q[i] = get<NT>(r, i) - scal[0] * get<NT>(s, i); }
 };
 template <bool NT>
 struct FnPUpdate {        // p = r + beta (p - omega s), skipped before the first iteration
     double* p; const double* r; const double* s; const State* st;
     __device__ void operator()(int64_t i) const {
         if (st->iter == 0) return;
-        put<NT>(p, i, get<NT>(r, i) + st->beta * (get<NT, double>(p, i) - st->omega * get<NT>(s, i)));
+        p[i] = get<NT>(r, i) + st->beta * (get<NT, double>(p, i) - st->omega * get<NT>(s, i));
     }
 };
 struct FnCastScaled {     // r32 = fp32(r / nu)

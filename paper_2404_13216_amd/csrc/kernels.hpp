@@ -625,7 +625,8 @@ __global__ void single_kernel(F f) {
 // ============================================================================= p-BiCGStab ops
 // Loads and stores of the phases' vectors.  NT: non-temporal (streamed past the caches),
 // chosen when the iteration's working set exceeds the Infinity Cache: the vectors then
-// do not evict the matrix, which both SpMVs of the iteration read whole.
+// do not evict the matrix, which both SpMVs of the iteration read whole.  The operand of
+// the SpMV that follows a phase (z, w) keeps plain stores: that SpMV gathers it next.
 template <bool NT, class T>
 __device__ __forceinline__ T get(const T* p, int64_t i) {
     if constexpr (NT) return __builtin_nontemporal_load(p + i);
@@ -669,7 +670,7 @@ struct PhaseA {
         }
         const double qi = ri - alpha * si;
         const double yi = wi - alpha * zi;
-        put<NT>(p, i, pi); put<NT>(s, i, si); put<NT>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
+        put<NT>(p, i, pi); put<NT>(s, i, si); put<false>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
         const double rh = in[3];
         xa[0] = qi; ya[0] = yi;
         xa[1] = yi; ya[1] = yi;
@@ -699,7 +700,7 @@ struct PhaseB {
         const double xi = (in[0] + alpha * in[1]) + omega * qi;
         const double ri = qi - omega * yi;
         const double wi = yi - omega * (in[4] - alpha * in[5]);
-        put<NT>(x, i, xi); put<NT>(r, i, ri); put<NT>(w, i, wi);
+        put<NT>(x, i, xi); put<NT>(r, i, ri); put<false>(w, i, wi);
         const double rh = in[6];
         xa[0] = rh; ya[0] = ri;
         xa[1] = rh; ya[1] = wi;
@@ -990,7 +991,7 @@ struct FPhaseA {
         }
         const float qi = ri - alpha * si;
         const float yi = wi - alpha * zi;
-        put<NT>(p, i, pi); put<NT>(s, i, si); put<NT>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
+        put<NT>(p, i, pi); put<NT>(s, i, si); put<false>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
         const float rh = get<NT>(rhat, i);
         xa[0] = qi; ya[0] = yi;
         xa[1] = yi; ya[1] = yi;
@@ -1011,7 +1012,7 @@ struct FPhaseB {
         const float xi = (get<NT, float>(x, i) + alpha * get<NT>(p, i)) + omega * qi;
         const float ri = qi - omega * yi;
         const float wi = yi - omega * (get<NT>(t, i) - alpha * get<NT>(v, i));
-        put<NT>(x, i, xi); put<NT>(r, i, ri); put<NT>(w, i, wi);
+        put<NT>(x, i, xi); put<NT>(r, i, ri); put<false>(w, i, wi);
         const float rh = get<NT>(rhat, i);
         xa[0] = rh; ya[0] = ri;
         xa[1] = rh; ya[1] = wi;
