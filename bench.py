@@ -18,9 +18,11 @@ Also reported (outside the timed steps):
     the learned M (setup time stated separately);
   * plain FP64 vs FP32-IR on the random unsymmetric n = 10^6 matrix and on the 256^3
     variable-diffusivity matrix;
-  * per-kernel bandwidth of the SpMV kernels, phase A / phase B and the standalone exact
-    dot (HIP events on the launch stream), the roofline of the dominant kernel, and the
-    CPU oracle timed on this host.
+  * per-kernel durations of the solve's four kernels (phase A, v = A z, phase B, t = A w)
+    from HIP events that the kernels' own dispatches stamp inside the timed solves, and
+    from them the roofline of the dominant kernel (the SpMV);
+  * micro-benchmarks (HIP events around every launch): the SpMV kernel shapes on a cold
+    cache and the standalone exact dot; and the CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--solve-only]
                        [--legs claim,learned,rand_1m,cd3d_256_var] [--epochs 30]
@@ -40,6 +42,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 CSRC = os.path.join(ROOT, "paper_2404_13216_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cd3d_128.md")
+KEV = 128  # iterations of each timed solve whose kernels carry timing events
 
 
 def log(*a):
@@ -287,11 +290,12 @@ def learned_leg(pk, torch, g, dev, reps, epochs):
     return out
 
 
-def traffic_run(pk, torch, A, n, nnz, dev):
+def traffic_run(pk, torch, A, b, n, nnz, dev):
     """Kernels whose HBM bytes rocprofv3 counters measure: a 256 MiB device copy (the
     calibration: 256 MiB read, 256 MiB written), the SpMV, phase A / phase B and the
-    standalone exact dot on the 128^3 workload; each launched 10 times, with a 1 GiB read
-    between launches so that no launch is served from the Infinity Cache."""
+    standalone exact dot on the 128^3 workload, each launched 10 times with a 1 GiB read
+    between launches so that no launch is served from the Infinity Cache; then one
+    complete solve, whose kernels run as in the timed steps."""
     rng = np.random.default_rng(1)
     V = {k: torch.from_numpy(rng.standard_normal(n) * 1e-3).to(dev) for k in
          ("x", "r", "rhat", "w", "t", "p", "s", "z", "q", "y", "v")}
@@ -319,7 +323,13 @@ def traffic_run(pk, torch, A, n, nnz, dev):
         flush.sum()
         pk.exdot(V["r"], V["w"], o1, wse)
     torch.cuda.synchronize()
-    log("traffic run done")
+    del V, S, flush, src, dst
+    torch.cuda.empty_cache()
+    solver = pk.Solver(A, tol=1e-10, max_iter=10000)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    _, info = solver.solve(b, x)
+    torch.cuda.synchronize()
+    log(f"traffic run done (solve: {info['iterations']} iterations, status {info['status']})")
 
 
 def main():
@@ -354,7 +364,7 @@ def main():
     log(f"workload cd3d_128 n={n} nnz={nnz} built in {time.time() - t0:.1f}s")
 
     if args.traffic_run:
-        traffic_run(pk, torch, A, n, nnz, dev)
+        traffic_run(pk, torch, A, b, n, nnz, dev)
         return
 
     solver = pk.Solver(A, tol=1e-10, max_iter=10000)
@@ -381,6 +391,32 @@ def main():
     err_xstar = (torch.linalg.norm(x - xs) / torch.linalg.norm(xs)).item()
     log(f"p-BiCGStab: {sec * 1e3:.2f} ms/solve, {info['iterations']} iterations, "
         f"true relres {info['true_relres']:.3e}")
+    # kernel durations: one more solve, identical to the timed ones, whose kernels of
+    # iterations 1..KEV carry HIP events stamped by the kernels' own dispatches
+    # (hipExtLaunchKernel; no markers between kernels, so the launches keep their spacing)
+    tsolver = pk.Solver(A, kernel_events=KEV, tol=1e-10, max_iter=10000)
+    xk = torch.zeros(n, dtype=torch.float64, device=dev)
+    _, kinfo = tsolver.solve(b, xk)
+    assert kinfo["iterations"] == info["iterations"] and torch.equal(xk, x)
+    ktimes = tsolver.kernel_times()
+    del tsolver, xk
+    used = max(1, min(KEV, info["iterations"] - 2 * solver.opts.batch))
+    spmv_bytes = 12 * nnz + 20 * n
+    roles = {"phase_a": 104 * n, "spmv_az": spmv_bytes, "phase_b": 80 * n, "spmv_aw": spmv_bytes}
+    kern = {}
+    for name, nb in roles.items():
+        ts = np.array(ktimes[name][:used])
+        kern[name] = {"us": float(ts.mean() * 1e6), "median_us": float(np.median(ts) * 1e6),
+                      "min_us": float(ts.min() * 1e6), "max_us": float(ts.max() * 1e6),
+                      "bytes": nb, "GBs": nb / ts.mean() / 1e9, "launches": int(ts.size)}
+    both = np.array(ktimes["spmv_az"][:used] + ktimes["spmv_aw"][:used])
+    kern["spmv_seq"] = {"us": float(both.mean() * 1e6), "median_us": float(np.median(both) * 1e6),
+                        "bytes": spmv_bytes, "GBs": spmv_bytes / both.mean() / 1e9, "launches": int(both.size),
+                        "layout": "sliced" if info["sliced"] & 1 else "csr"}
+    for v in kern.values():
+        v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
+    iter_kernels_us = sum(kern[k]["us"] for k in roles)
+    log("kernels in the solve:", json.dumps(kern))
 
     out = {
         "metric": "time to true rel. residual 1e-10 (plain FP64 p-BiCGStab, exact dots)",
@@ -403,7 +439,22 @@ def main():
         "true_relres": info["true_relres"],
         "rel_err_vs_xstar": err_xstar,
         "us_per_iteration": sec / max(info["iterations"], 1) * 1e6,
+        "kernels_in_solve": kern,
+        "iteration_kernel_us": iter_kernels_us,
     }
+    # dominant kernel of the iteration: the SpMV (two launches per iteration)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        txt = open(TRAFFIC_FILE).read()
+        blob = txt[txt.index("```json") + 7: txt.index("```", txt.index("```json") + 7)]
+        tr = json.loads(blob)
+        if tr.get("source_hash") == kernel_source_hash() and "spmv_seq" in tr.get("kernels", {}):
+            traffic = tr["kernels"]["spmv_seq"]["bytes_per_launch"]
+    out["roofline"] = {"kernel": "spmv_seq", "bound": "hbm", "achieved": kern["spmv_seq"]["GBs"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["spmv_seq"]["GBs"] / HBM_PEAK_GBS,
+                       "traffic": traffic, "algorithmic_bytes_per_launch": spmv_bytes,
+                       "avg_launch_us": kern["spmv_seq"]["us"], "launches": kern["spmv_seq"]["launches"],
+                       "timing": "HIP events stamped by the kernel dispatches of iterations 1..%d of a solve identical to the timed ones" % used}
 
     if not args.solve_only:
         forms = {}
@@ -415,50 +466,11 @@ def main():
         out["forms"] = forms
         log("forms:", json.dumps(forms))
 
-        # per-kernel bandwidth (algorithmic bytes / average launch duration), measured by
-        # replaying one p-BiCGStab iteration (phase A, v = A z, phase B, t = A w) on
-        # workload-sized vectors with HIP events around every launch on the launch stream;
-        # the iteration's working set (~400 MB) exceeds the 256 MB Infinity Cache.
+        # micro-benchmarks outside the solve (HIP events around every launch on the
+        # launch stream): the SpMV kernel shapes on a cold cache and the standalone exact dot
         kern = {}
         reps = args.reps
-        rng = np.random.default_rng(1)
-        V = {k: torch.from_numpy(rng.standard_normal(n) * 1e-3).to(dev) for k in
-             ("x", "r", "rhat", "w", "t", "p", "s", "z", "q", "y", "v")}
-        scal = torch.tensor([0.5, 0.25, 0.75], dtype=torch.float64, device=dev)
-        dots = torch.empty(4, dtype=torch.float64, device=dev)
-        wsp = torch.empty(pk.lib().pbcg_phase_workspace_bytes(n), dtype=torch.uint8, device=dev)
-        spmv_bytes = 12 * nnz + 20 * n
-        # the SpMV form the solve runs: the sliced copy when one is built, else CSR
         S = pk.SlicedCSR(A)
-
-        def spmv(vin, vout):
-            if S.built:
-                pk.csr_spmv_sliced(S, vin, vout)
-            else:
-                pk.csr_spmv(A, vin, vout)
-        seq = [("phase_a", lambda: pk.pbcg_phase_a(V, scal, False, dots, wsp), 104 * n),
-               ("spmv_seq", lambda: spmv(V["z"], V["v"]), spmv_bytes),
-               ("phase_b", lambda: pk.pbcg_phase_b(V, scal, dots, wsp), 80 * n),
-               ("spmv_seq", lambda: spmv(V["w"], V["t"]), spmv_bytes)]
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)]
-        acc = {}
-        for it in range(reps + 2):
-            hold_stream(torch, 1e-3)
-            ev[0].record()
-            for k, (name, fn, nb) in enumerate(seq):
-                fn()
-                ev[k + 1].record()
-            ev[-1].synchronize()
-            if it < 2:
-                continue
-            for k, (name, fn, nb) in enumerate(seq):
-                acc.setdefault(name, [0.0, 0, nb])
-                acc[name][0] += ev[k].elapsed_time(ev[k + 1]) / 1e3
-                acc[name][1] += 1
-        for name, (tsum, cnt, nb) in acc.items():
-            dt = tsum / cnt
-            kern[name] = {"us": dt * 1e6, "bytes": nb, "GBs": nb / dt / 1e9, "launches": cnt}
-        kern["spmv_seq"]["layout"] = "sliced" if S.built else "csr"
         # SpMV kernel shapes, each launch preceded by a 512 MB write that evicts the cache
         shapes = [("spmv_seq_cold", pk.SPMV_SEQ, None), ("spmv_vector_cold", pk.SPMV_VECTOR, None),
                   ("spmv_wave_cold", pk.SPMV_WAVE, None)]
@@ -497,25 +509,9 @@ def main():
             del bufs
         for k, v in kern.items():
             v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
-        out["kernels"] = kern
-        log("kernels:", json.dumps(kern))
-        # dominant kernel per iteration: SpMV runs twice per iteration
-        per_iter = {"spmv_seq": 2 * kern["spmv_seq"]["us"], "phase_a": kern["phase_a"]["us"],
-                    "phase_b": kern["phase_b"]["us"]}
-        out["iteration_kernel_us"] = per_iter
-        dom = max(per_iter, key=per_iter.get)
-        traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            txt = open(TRAFFIC_FILE).read()
-            blob = txt[txt.index("```json") + 7: txt.index("```", txt.index("```json") + 7)]
-            tr = json.loads(blob)
-            if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
-                traffic = tr["kernels"][dom]["bytes_per_launch"]
-        out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": kern[dom]["GBs"], "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-                           "algorithmic_bytes_per_launch": kern[dom]["bytes"],
-                           "avg_launch_us": kern[dom]["us"]}
-        del V, wsp, S
+        out["micro_kernels"] = kern
+        log("micro kernels:", json.dumps(kern))
+        del S
         # further legs run after the kernel table, so that they do not disturb its timings
         legs = [l for l in args.legs.split(",") if l]
         if "claim" in legs:

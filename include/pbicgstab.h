@@ -116,6 +116,15 @@ typedef struct {
     int32_t true_history_len;  /* entries available in true_history                        */
     double* true_history;      /* optional device buffer                                     */
     int32_t layout;            /* pbcg_layout (default AUTO; SEQ SpMV kind only)              */
+    int32_t kernel_events_len; /* entries of kernel_events (a multiple of 8; 0: none)          */
+    void* const* kernel_events;/* optional host array of hipEvent_t, created by the caller
+                                  with timing enabled (measurement only).  FP64 p-BiCGStab
+                                  with exact dots and no M: the four kernels of iteration
+                                  j = 1 .. kernel_events_len/8 (phase A, v = A z, phase B,
+                                  t = A w) are launched with hipExtLaunchKernel, which stamps
+                                  events [8(j-1) + 2k] and [8(j-1) + 2k + 1] with kernel k's
+                                  start and end; events of iterations that do not run keep
+                                  their previous state.  Results are unaffected.            */
 } pbcg_opts;
 
 /* Result summary (host struct). */

@@ -45,7 +45,8 @@ class PbcgOpts(ctypes.Structure):
                 ("spmv_kind", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("dots", ctypes.c_int32), ("rr_period", ctypes.c_int32),
                 ("true_every", ctypes.c_int32), ("true_history_len", ctypes.c_int32),
-                ("true_history", ctypes.c_void_p), ("layout", ctypes.c_int32)]
+                ("true_history", ctypes.c_void_p), ("layout", ctypes.c_int32),
+                ("kernel_events_len", ctypes.c_int32), ("kernel_events", ctypes.POINTER(ctypes.c_void_p))]
 
 
 class PbcgInfo(ctypes.Structure):
@@ -360,10 +361,23 @@ def default_opts(**kw) -> PbcgOpts:
 class Solver:
     """Holds a workspace for repeated solves with one matrix and option set."""
 
-    def __init__(self, A: CSR, M: CSR | None = None, history: int = 0, **opts):
+    KERNELS = ("phase_a", "spmv_az", "phase_b", "spmv_aw")
+
+    def __init__(self, A: CSR, M: CSR | None = None, history: int = 0, kernel_events: int = 0, **opts):
         torch = _torch()
         self.A, self.M = A, M
         self.opts = default_opts(**opts)
+        # measurement: start/end events of the four kernels of iterations 1..kernel_events
+        # (FP64 p-BiCGStab, exact dots, no M), stamped by the kernels' own dispatches
+        self._events = []
+        if kernel_events:
+            self._events = [torch.cuda.Event(enable_timing=True) for _ in range(8 * kernel_events)]
+            for e in self._events:      # creates the HIP events
+                e.record()
+            torch.cuda.synchronize()
+            self._ev_ptrs = (ctypes.c_void_p * len(self._events))(*[e.cuda_event for e in self._events])
+            self.opts.kernel_events = ctypes.cast(self._ev_ptrs, ctypes.POINTER(ctypes.c_void_p))
+            self.opts.kernel_events_len = len(self._events)
         self._M_ref = M
         if M is not None:
             self.opts.M = ctypes.pointer(M._c)
@@ -380,6 +394,17 @@ class Solver:
             self.opts.true_history_len = cap
         nb = lib().pbicgstab_workspace_bytes(A.n, A.nnz, ctypes.byref(self.opts))
         self.ws = _workspace(nb, A.val.device)
+
+    def kernel_times(self):
+        """Durations (seconds) of the timed kernels of the last solve, per kernel role."""
+        torch = _torch()
+        torch.cuda.synchronize()
+        ev = self._events
+        out = {k: [] for k in self.KERNELS}
+        for j in range(len(ev) // 8):
+            for k, name in enumerate(self.KERNELS):
+                out[name].append(ev[8 * j + 2 * k].elapsed_time(ev[8 * j + 2 * k + 1]) / 1e3)
+        return out
 
     def solve(self, b, x=None, r_out=None):
         torch = _torch()

@@ -1,6 +1,7 @@
 // C-ABI of libpbicgstab.so: argument checks, workspace layout, kernel launches and
 // the host driver of the solvers.  See include/pbicgstab.h for the contract.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <chrono>
@@ -26,6 +27,7 @@ constexpr int IR_MAX_BAD = 1;         // updates that did not improve on the bes
 constexpr double IR_DELTA = 0.1;      // default update threshold (inner_tol)
 constexpr int IR_FP64_FINISH = 10000; // iteration limit of the FP64 finish after stagnation
 constexpr int IR_FINISH_RR = 50;      // residual replacement period of that finish
+constexpr int IR_BATCH = 4;           // FP32 iterations enqueued between status polls (at most)
 constexpr int KEXP = 3;              // expansion terms per lane in the solver kernels
 
 #define HIPCHK(expr)                              \
@@ -134,6 +136,22 @@ int64_t build_slices(const pbcg_csr* A, int64_t* off, int32_t* col, void* val, i
 }
 
 // ---------------------------------------------------------------- launchers
+// Kernel timing for measurement: when a pair of events is pending, the next launch
+// through klaunch goes through hipExtLaunchKernel, which stamps the events with that
+// kernel's own start and end (no markers between kernels, so back-to-back launches keep
+// their spacing).  Per host thread; consumed by one launch.
+thread_local hipEvent_t g_kev[2] = {nullptr, nullptr};
+
+template <typename... KArgs, typename... Args>
+void klaunch(void (*k)(KArgs...), dim3 grid, dim3 block, size_t smem, hipStream_t s, Args... args) {
+    if (g_kev[0]) {
+        hipExtLaunchKernelGGL(k, grid, block, (std::uint32_t)smem, s, g_kev[0], g_kev[1], 0u, KArgs(args)...);
+        g_kev[0] = g_kev[1] = nullptr;
+    } else {
+        k<<<grid, block, smem, s>>>(KArgs(args)...);
+    }
+}
+
 constexpr int SEQ_WORKERS = 8 * 256;   // persistent SpMV blocks: 8 resident per CU (16 KB LDS each)
 constexpr int SLICE_WORKERS = 1 << 24; // sliced-copy SpMV: one block per slice (no LDS staging)
 
@@ -149,11 +167,11 @@ void launch_spmv_t(const Mat& A, const XT* x, Epi epi, const int* halt, hipStrea
         const int grid = workers + (Fin::D > 0 ? 1 : 0);
         if (grid > 0) {
             if (A.sl.off)
-                spmv_seq_kernel<VT, XT, AT, Epi, Fin, false, true><<<grid, BLOCK, 0, s>>>(
-                    n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, typed<VT>(A.sl));
+                klaunch(spmv_seq_kernel<VT, XT, AT, Epi, Fin, false, true>, grid, BLOCK, 0, s,
+                        n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, typed<VT>(A.sl));
             else
-                spmv_seq_kernel<VT, XT, AT, Epi, Fin><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
-                                                                              fin, halt, Sliced<VT>{});
+                klaunch(spmv_seq_kernel<VT, XT, AT, Epi, Fin>, grid, BLOCK, 0, s,
+                        n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, Sliced<VT>{});
         }
         return;
     }
@@ -248,7 +266,7 @@ XFin<D, Op, GM> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const in
         }
 #undef EW_CASE
     } else {
-        ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen);
+        klaunch(ew_dot_kernel<D, KEXP, Op>, grid, block, 0, s, op, n, site, halt, seen);
     }
     return XFin<D, Op, GM>{op, site, grid, halt};
 }
@@ -446,7 +464,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int n, const int* __restric
 
 extern "C" {
 
-int pbcg_abi_version(void) { return 5; }
+int pbcg_abi_version(void) { return 6; }
 
 const char* pbcg_status_string(int status) {
     switch (status) {
@@ -805,13 +823,13 @@ struct Driver {
         return CONTINUE;
     }
 
-    void enqueue_iteration_p(bool first) {
-        if (nt64) enqueue_iteration_p_t<true>(first);
-        else enqueue_iteration_p_t<false>(first);
+    void enqueue_iteration_p(bool first, long long it) {
+        if (nt64) enqueue_iteration_p_t<true>(first, it);
+        else enqueue_iteration_p_t<false>(first, it);
     }
 
     template <bool NT>
-    void enqueue_iteration_p_t(bool first) {
+    void enqueue_iteration_p_t(bool first, long long it) {
         const int n = A->n;
         const double* scal = &W.st->alpha;
         PhaseA<FinOmega, NT> pa{W.r, W.w, W.t, W.v, W.rhat, W.p, W.s, W.z, W.q, W.y, scal, first ? 1 : 0,
@@ -824,10 +842,24 @@ struct Driver {
             op(W.w, W.t, fb, seen);
             return;
         }
+        hipEvent_t* ev = kernel_events(it);
+        if (ev) { g_kev[0] = ev[0]; g_kev[1] = ev[1]; }
         auto fa = launch_ew_dot_deferred<4, DOT_GRID_DEFAULT>(pa, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
+        if (ev) { g_kev[0] = ev[2]; g_kev[1] = ev[3]; }
         op(W.z, W.v, fa, seen);           // v = A z; omega is finalized by its block 0
+        if (ev) { g_kev[0] = ev[4]; g_kev[1] = ev[5]; }
         auto fb = launch_ew_dot_deferred<3, DOT_GRID_DEFAULT>(pb, n, W.site, halt, s, 0, DOT_BLOCK, KEXP, seen);
+        if (ev) { g_kev[0] = ev[6]; g_kev[1] = ev[7]; }
         op(W.w, W.t, fb, seen);           // t = A w; beta, alpha finalized by its block 0
+        g_kev[0] = g_kev[1] = nullptr;
+    }
+
+    // The caller's timing events for iteration `it` (0-based; iteration 0 copies instead
+    // of updating and is not timed), or null.
+    hipEvent_t* kernel_events(long long it) const {
+        if (!o->kernel_events || o->kernel_events_len < 8 || M || o->dots != PBCG_DOTS_EXACT) return nullptr;
+        if (it < 1 || it > o->kernel_events_len / 8) return nullptr;
+        return (hipEvent_t*)o->kernel_events + 8 * (it - 1);
     }
 
     // After completed iteration `it` (skipped if it halted): the periodic true residual
@@ -929,12 +961,15 @@ struct Driver {
         // device-side halts end the loop; this bound only guards against a broken state
         const long long limit = (long long)max_iter + 4LL * batch + 64;
         long long enqueued = 0;
+        int nb = batch;         // after a failed true-residual test the solve halts every 5
+                                // iterations: batches of 5 keep the no-op launches queued
+                                // behind each halt to one batch
         while (true) {
             if (enqueued > limit) return PBCG_ERR_HIP;
-            enqueued += batch;
-            for (int k = 0; k < batch; ++k) {
+            enqueued += nb;
+            for (int k = 0; k < nb; ++k) {
                 if (bicg) enqueue_iteration_b();
-                else enqueue_iteration_p(first);
+                else enqueue_iteration_p(first, it_enq);
                 first = false;
                 ++it_enq;
                 if (!bicg) enqueue_after_iteration(it_enq);
@@ -952,6 +987,7 @@ struct Driver {
                     if (sync_state(&h)) return PBCG_ERR_HIP;   // later batches were no-ops
                     int r = handle_halt(h);
                     if (r != CONTINUE) return r;
+                    if (h.reason & R_CHECK) nb = std::min(batch, 5);
                     launch_single(FnResume{W.st}, s);
                     polled = batches;
                     enqueued = h.iter;  // batches queued behind the halt were no-ops
@@ -985,12 +1021,15 @@ struct Driver {
     int run_fp32(FState& hf, bool first) {
         FState* fs = W.fst;
         int polled = 0, batches = 0;
-        const long long limit = (long long)std::max(o->max_iter, 1) + 4LL * batch + 64;
+        // short batches: every reliable update halts the FP32 run, and the iterations
+        // queued behind a halt (up to two batches) run as no-op launches
+        const int nb = std::min(batch, IR_BATCH);
+        const long long limit = (long long)std::max(o->max_iter, 1) + 4LL * nb + 64;
         long long enqueued = 0;
         while (true) {
             if (enqueued > limit) return PBCG_ERR_HIP;   // a stop reason must have come (MAXIT)
-            enqueued += batch;
-            for (int k = 0; k < batch; ++k) {
+            enqueued += nb;
+            for (int k = 0; k < nb; ++k) {
                 if (nt32) enqueue_iteration_f32<true>(first);
                 else enqueue_iteration_f32<false>(first);
                 first = false;
@@ -1173,6 +1212,9 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     if (!csr_ok(A) || !opts) return PBCG_ERR_INVALID;
     if (A->n > 0 && (!b || !x)) return PBCG_ERR_INVALID;
     if (opts->max_iter < 0 || !(opts->tol >= 0.0)) return PBCG_ERR_INVALID;
+    if (opts->kernel_events_len < 0 || opts->kernel_events_len % 8 != 0 ||
+        (opts->kernel_events_len > 0 && !opts->kernel_events))
+        return PBCG_ERR_INVALID;
     if (opts->alg != PBCG_ALG_PBICGSTAB && opts->alg != PBCG_ALG_BICGSTAB) return PBCG_ERR_INVALID;
     if (opts->prec != PBCG_PREC_FP64 && opts->prec != PBCG_PREC_FP32_IR) return PBCG_ERR_INVALID;
     if (opts->M && (!csr_ok(opts->M) || opts->M->n != A->n)) return PBCG_ERR_INVALID;

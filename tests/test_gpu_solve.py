@@ -183,3 +183,24 @@ def test_stagnation_rule_bitwise(name, scale):
     orb = ctier.bicgstab(p.A, p.b, tol=1e-14, max_iter=3000)
     xb, infob, _ = gpu_solve(p.A, p.b, tol=1e-14, max_iter=3000, alg=pk.ALG_BICGSTAB)
     assert infob["status"] == orb["status"] == pk.OK and np.array_equal(bits(xb), bits(orb["x"]))
+
+
+def test_kernel_events_leave_the_solve_unchanged():
+    """Timing events stamped by the kernels' own dispatches (a measurement option) change
+    nothing: same iterate bits as the oracle's and as an untimed solve; every timed kernel
+    has a positive duration shorter than the whole solve."""
+    p = g.problem("cd3d_128", scale=48)
+    ref = ctier.pbicgstab(p.A, p.b, tol=1e-10, max_iter=10000)
+    x0, i0, _ = gpu_solve(p.A, p.b, tol=1e-10)
+    Ad = pk.CSR.from_host(p.A)
+    s = pk.Solver(Ad, kernel_events=16, tol=1e-10)
+    x1, i1 = s.solve(to_dev(p.b))
+    x1 = x1.cpu().numpy()
+    assert i1["status"] == i0["status"] == pk.OK and i1["iterations"] == i0["iterations"] == ref["iterations"]
+    assert np.array_equal(bits(x1), bits(x0))
+    assert np.array_equal(bits(x1), bits(ref["x"]))
+    kt = s.kernel_times()
+    assert set(kt) == set(pk.Solver.KERNELS)
+    for name, ts in kt.items():
+        assert len(ts) == 16
+        assert all(0.0 < t < i1["seconds"] for t in ts), (name, ts)

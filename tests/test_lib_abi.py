@@ -56,7 +56,7 @@ def test_struct_layout_matches_header(tmp_path):
         assert lay[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert lay[(cname, f)] == getattr(py, f).offset, (cname, f)
-    assert pk.lib().pbcg_abi_version() == 5
+    assert pk.lib().pbcg_abi_version() == 6
 
 
 def test_status_strings_and_defaults():
@@ -80,6 +80,12 @@ def test_host_argument_checks_without_gpu():
     good = pk.PbcgCsr(4, 0, 4, 1, 1, 1)  # fake non-null pointers: never dereferenced on the host
     assert L.pbicgstab_solve(ctypes.byref(good), 1, 1, ctypes.byref(o), None, None, 0, None) == pk.ERR_WORKSPACE
     o.tol = -1.0
+    assert L.pbicgstab_solve(ctypes.byref(good), 1, 1, ctypes.byref(o), None, 256, 1 << 20, None) == pk.ERR_INVALID
+    # kernel timing events: a multiple of 8, with an array
+    o = pk.default_opts()
+    o.kernel_events_len = 4
+    assert L.pbicgstab_solve(ctypes.byref(good), 1, 1, ctypes.byref(o), None, 256, 1 << 20, None) == pk.ERR_INVALID
+    o.kernel_events_len = 8
     assert L.pbicgstab_solve(ctypes.byref(good), 1, 1, ctypes.byref(o), None, 256, 1 << 20, None) == pk.ERR_INVALID
     # sliced copies: bad matrix, missing workspace, unbuilt copy
     S = pk.PbcgSliced()
