@@ -84,6 +84,7 @@ struct NoFin {
 template <int D_, class Op, int GM = DOT_GMAX>
 struct XFin {                       // exact dots
     static constexpr int D = D_;
+    static constexpr int BLOCK = 1024;  // threads of its own kernel (any count works)
     static constexpr int SMEM = 32 + 4 * xd::NCH * 8 + 16 + 32 + 2 * GM * 4 * 2;
     Op op;
     xd::Site site;
@@ -105,6 +106,7 @@ struct XFin {                       // exact dots
 template <class T, int D_, class Op>
 struct TFin {                       // plain dots in a fixed tree
     static constexpr int D = D_;
+    static constexpr int BLOCK = 256;   // the tree is defined for 256 threads
     static constexpr int SMEM = (4 + 4 * 256) * (int)sizeof(T);
     Op op;
     TSite<T> site;
@@ -122,7 +124,7 @@ template <int D, class Op>
 using FFin = TFin<float, D, Op>;
 
 template <class Fin>
-__global__ void __launch_bounds__(256) fin_kernel(Fin fin) {
+__global__ void __launch_bounds__(Fin::BLOCK) fin_kernel(Fin fin) {
     __shared__ __align__(16) unsigned char smem[Fin::SMEM];
     fin.run(smem);
 }
@@ -184,7 +186,9 @@ constexpr int SLICE_UNROLL = 8;   // entries of a row loaded ahead of their addi
 
 // One lane's row of slice c of a sliced copy (len entries, storage order): s (and the
 // Dot2 compensation cmp when COMP) accumulate exactly as in the staged path below.
-template <class VT, class XT, class AT, bool COMP>
+// MNT: the slice's values and columns are read with non-temporal loads (a matrix larger than
+// the Infinity Cache streams past it instead of evicting the vectors).
+template <class VT, class XT, class AT, bool COMP, bool MNT = false>
 __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, int len, const XT* __restrict__ x,
                                           AT& s, AT& cmp) {
     constexpr int U = SLICE_UNROLL, R = 256;
@@ -199,7 +203,15 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
         for (int u = 0; u < U; ++u) {
             av[u] = VT(0);
             cv[u] = 0;
-            if (k0 + u < w) { av[u] = vp[(int64_t)(k0 + u) * R]; cv[u] = cp[(int64_t)(k0 + u) * R]; }
+            if (k0 + u < w) {
+                if constexpr (MNT) {
+                    av[u] = __builtin_nontemporal_load(vp + (int64_t)(k0 + u) * R);
+                    cv[u] = __builtin_nontemporal_load(cp + (int64_t)(k0 + u) * R);
+                } else {
+                    av[u] = vp[(int64_t)(k0 + u) * R];
+                    cv[u] = cp[(int64_t)(k0 + u) * R];
+                }
+            }
         }
         XT xv[U];
 #pragma unroll
@@ -248,7 +260,7 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
 // (2005) in storage order -- the window holds (p, e) with p = fl(a x) and the exact
 // product error e = fma(a, x, -p); each lane runs TwoSum(s, p) and adds err + e into a
 // compensation c; the row's value is fl(s + c).  All arithmetic is float32.
-template <int CAP, class VT, class XT, class AT, class Body, bool COMP = false, bool SL = false>
+template <int CAP, class VT, class XT, class AT, class Body, bool COMP = false, bool SL = false, bool MNT = false>
 __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const XT* __restrict__ x,
                                           int bfirst, int G, AT* sprod, Body& body, Sliced<VT> sl = {}) {
@@ -278,7 +290,7 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
         if (row < r1) { RA = rp[row]; RB = rp[row + 1]; }
         AT s = AT(0), cmp = AT(0);
         if constexpr (SL) {
-            slice_row<VT, XT, AT, COMP>(sl, c, t, RB - RA, x, s, cmp);
+            slice_row<VT, XT, AT, COMP, MNT>(sl, c, t, RB - RA, x, s, cmp);
         } else {
             const int A0 = rp[r0], A1 = rp[r1];
             for (int w = A0; w < A1; w += CAP) {
@@ -337,7 +349,7 @@ struct StoreBody {
 };
 
 // grid = worker blocks (+1 when block 0 carries a finalize role)
-template <class VT, class XT, class AT, class Epi, class Fin, bool COMP = false, bool SL = false>
+template <class VT, class XT, class AT, class Epi, class Fin, bool COMP = false, bool SL = false, bool MNT = false>
 __global__ void __launch_bounds__(256)
 spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                 const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt,
@@ -355,8 +367,8 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
         bfirst = 1;
     }
     StoreBody<Epi> body{epi};
-    seq_stage<SEQ_CAP, VT, XT, AT, StoreBody<Epi>, COMP, SL>(n, rp, ci, val, x, bfirst, (int)gridDim.x - bfirst,
-                                                              (AT*)smem, body, sl);
+    seq_stage<SEQ_CAP, VT, XT, AT, StoreBody<Epi>, COMP, SL, MNT>(n, rp, ci, val, x, bfirst,
+                                                                   (int)gridDim.x - bfirst, (AT*)smem, body, sl);
 }
 
 // Sliced copy, step 1: off[c + 1] = 256 * (longest row of slice c), off[0] = 0.
@@ -530,7 +542,7 @@ struct DotBody {
     }
 };
 
-template <int D, int K, class VT, class Epi, bool SL = false>
+template <int D, int K, class VT, class Epi, bool SL = false, bool MNT = false>
 __global__ void __launch_bounds__(256)
 spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const VT* __restrict__ val, const double* __restrict__ x, Epi epi,
@@ -546,8 +558,8 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 #pragma unroll
         for (int k = 0; k < K; ++k) e[d][k] = 0.0;
     DotBody<D, K, Epi> body{epi, e, sh_acc, sh_flags};
-    seq_stage<SEQ_CAP, VT, double, double, DotBody<D, K, Epi>, false, SL>(n, rp, ci, val, x, 0, (int)gridDim.x,
-                                                                            sprod, body, sl);
+    seq_stage<SEQ_CAP, VT, double, double, DotBody<D, K, Epi>, false, SL, MNT>(n, rp, ci, val, x, 0,
+                                                                                 (int)gridDim.x, sprod, body, sl);
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
 }

@@ -362,15 +362,29 @@ __device__ void reduce_records(const Site& site, int G, long long* fin, short* h
     for (int i = tid; i < D * NCH; i += blockDim.x) fin[i] = 0;
     if (tid < D) { fl[tid] = 0u; rng[2 * tid] = NCH; rng[2 * tid + 1] = -1; }
     __syncthreads();
-    for (int j = tid; j < G * D; j += blockDim.x) {
-        RecHdr h = site.hdr[j];
-        hlo[j] = (short)h.lo;
-        hhi[j] = (short)h.hi;
-        const int d = j % D;
-        if (h.flags) atomicOr(&fl[d], h.flags);
-        if (h.lo <= h.hi) {
-            atomicMin(&rng[2 * d], h.lo);
-            atomicMax(&rng[2 * d + 1], h.hi);
+    // headers: every load of a thread is issued before the first use (one round of memory
+    // latency instead of one per header); HB covers G * D <= GMAX * D with 1024 threads
+    constexpr int HB = (GMAX * D) / 1024 < 1 ? 1 : ((GMAX * D) / 1024 > 8 ? 8 : (GMAX * D) / 1024);
+    for (int j0 = tid; j0 < G * D; j0 += HB * blockDim.x) {
+        RecHdr h[HB];
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+            const int j = j0 + u * blockDim.x;
+            if (j < G * D) h[u] = site.hdr[j];
+        }
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+            const int j = j0 + u * blockDim.x;
+            if (j < G * D) {
+                hlo[j] = (short)h[u].lo;
+                hhi[j] = (short)h[u].hi;
+                const int d = j % D;
+                if (h[u].flags) atomicOr(&fl[d], h[u].flags);
+                if (h[u].lo <= h[u].hi) {
+                    atomicMin(&rng[2 * d], h[u].lo);
+                    atomicMax(&rng[2 * d + 1], h[u].hi);
+                }
+            }
         }
     }
     __syncthreads();
@@ -384,7 +398,7 @@ __device__ void reduce_records(const Site& site, int G, long long* fin, short* h
         off[d + 1] = off[d] + G * Wd[d];
     }
     const int items = off[D];
-    constexpr int U = 8;
+    constexpr int U = 8;    // with the finalize kernel's 1024 threads: 8192 chunk loads per round
     for (int j0 = tid; j0 < items; j0 += U * blockDim.x) {
         long long v[U];
         int slot[U];

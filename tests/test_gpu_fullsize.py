@@ -5,7 +5,8 @@ computed one by one in the oracle's order) otherwise.
 * random 10^6 (17.8M nonzeros, rows up to 400): FP64 SpMV and the Dot2 FP32 SpMV bit
   for bit on every row; 20 p-BiCGStab iterations bit for bit against the C oracle.
 * 256^3 variable diffusivity (117M nonzeros): both SpMVs bit for bit on 20,000 sampled
-  rows; 5 p-BiCGStab iterations bit for bit against the C oracle.
+  rows; 5 p-BiCGStab iterations bit for bit against the C oracle (the solve's sliced copy,
+  1.4 GB, is larger than the Infinity Cache and is read with non-temporal loads).
 * held-out 128^3 learned-preconditioner matrix: features on every nonzero against the
   float64 oracle; bf16 inference against the oracle's emulation on 50,000 sampled
   nonzeros.
