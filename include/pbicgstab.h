@@ -119,7 +119,8 @@ typedef struct {
     int32_t kernel_events_len; /* entries of kernel_events (a multiple of 8; 0: none)          */
     void* const* kernel_events;/* optional host array of hipEvent_t, created by the caller
                                   with timing enabled (measurement only).  FP64 p-BiCGStab
-                                  with exact dots and no M: the four kernels of iteration
+                                  with exact dots, no M and the row-sequential SpMV (the
+                                  default kind): the four kernels of iteration
                                   j = 1 .. kernel_events_len/8 (phase A, v = A z, phase B,
                                   t = A w) are launched with hipExtLaunchKernel, which stamps
                                   events [8(j-1) + 2k] and [8(j-1) + 2k + 1] with kernel k's

@@ -868,7 +868,9 @@ struct Driver {
     // The caller's timing events for iteration `it` (0-based; iteration 0 copies instead
     // of updating and is not timed), or null.
     hipEvent_t* kernel_events(long long it) const {
-        if (!o->kernel_events || o->kernel_events_len < 8 || M || o->dots != PBCG_DOTS_EXACT) return nullptr;
+        if (!o->kernel_events || o->kernel_events_len < 8 || M || o->dots != PBCG_DOTS_EXACT ||
+            kind != PBCG_SPMV_SEQ)
+            return nullptr;
         if (it < 1 || it > o->kernel_events_len / 8) return nullptr;
         return (hipEvent_t*)o->kernel_events + 8 * (it - 1);
     }
