@@ -401,7 +401,10 @@ def main():
     ktimes = tsolver.kernel_times()
     del tsolver, xk
     used = max(1, min(KEV, info["iterations"] - 2 * solver.opts.batch))
-    spmv_bytes = 12 * nnz + 20 * n
+    # the SpMV's bytes: 8-byte value + column entry per nonzero (4 bytes, or 2 when the
+    # sliced copy stores 16-bit column offsets), x once, y, row pointers: 20 bytes per row
+    col_bytes = 2 if info["sliced"] & 4 else 4
+    spmv_bytes = (8 + col_bytes) * nnz + 20 * n
     roles = {"phase_a": 104 * n, "spmv_az": spmv_bytes, "phase_b": 80 * n, "spmv_aw": spmv_bytes}
     kern = {}
     for name, nb in roles.items():
@@ -434,7 +437,8 @@ def main():
         "config": {"workload": "cd3d_128: 3D upwind convection-diffusion 128^3, v=(30,20,10), seed 1",
                    "n": n, "nnz": nnz, "tol": 1e-10, "x0": "0", "alg": "p-BiCGStab",
                    "dots": "exact (rounded once)",
-                   "spmv": "row-sequential, " + ("sliced copy (256-row slices)" if info["sliced"] & 1 else "CSR")},
+                   "spmv": "row-sequential, " + ("sliced copy (256-row slices%s)" % (
+                       ", 16-bit column offsets" if info["sliced"] & 4 else "") if info["sliced"] & 1 else "CSR")},
         "iterations": info["iterations"],
         "true_relres": info["true_relres"],
         "rel_err_vs_xstar": err_xstar,
@@ -453,6 +457,7 @@ def main():
     out["roofline"] = {"kernel": "spmv_seq", "bound": "hbm", "achieved": kern["spmv_seq"]["GBs"],
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["spmv_seq"]["GBs"] / HBM_PEAK_GBS,
                        "traffic": traffic, "algorithmic_bytes_per_launch": spmv_bytes,
+                       "algorithmic_bytes": "%d per nonzero + 20 per row" % (8 + col_bytes),
                        "avg_launch_us": kern["spmv_seq"]["us"], "launches": kern["spmv_seq"]["launches"],
                        "timing": "HIP events stamped by the kernel dispatches of iterations 1..%d of a solve identical to the timed ones" % used}
 
@@ -478,7 +483,7 @@ def main():
             shapes.insert(0, ("spmv_seq_sliced_cold", pk.SPMV_SEQ, S))
         for name, kind, sl in shapes:
             dt, gbs = spmv_cold(pk, torch, A, min(reps, 20), kind, sl)
-            kern[name] = {"us": dt * 1e6, "bytes": spmv_bytes, "GBs": gbs}
+            kern[name] = {"us": dt * 1e6, "bytes": 12 * nnz + 20 * n, "GBs": gbs}   # 32-bit columns
         # standalone exact dot, rotating over buffers larger than the cache: uniform
         # U[-1, 1] at 2^20, 2^24, 2^26; wide exponents (+-1000) and exactly cancelling
         # (ill-conditioned) inputs at 2^24

@@ -91,10 +91,22 @@ bool csr_ok(const pbcg_csr* A) {
 // copy with the same row order (read by the row-sequential kernels only).
 struct SliceView {
     const int64_t* off = nullptr;
-    const int32_t* col = nullptr;
+    const int32_t* col = nullptr;   // 32-bit columns, or 16-bit offsets col - row when d16
     const void* val = nullptr;
     bool nt = false;    // matrix larger than the Infinity Cache: stream it (non-temporal loads)
+    bool d16 = false;   // column entries are 16-bit offsets
 };
+
+// the runtime layout of a sliced copy -> the kernels' compile-time layout flags
+template <class F>
+void with_slf(const SliceView& v, F&& f) {
+    switch ((v.nt ? SL_NT : 0) | (v.d16 ? SL_D16 : 0)) {
+        case 0: f(std::integral_constant<int, 0>{}); break;
+        case SL_NT: f(std::integral_constant<int, SL_NT>{}); break;
+        case SL_D16: f(std::integral_constant<int, SL_D16>{}); break;
+        default: f(std::integral_constant<int, SL_NT | SL_D16>{}); break;
+    }
+}
 
 struct Mat {
     const pbcg_csr* csr = nullptr;
@@ -115,23 +127,36 @@ Sliced<VT> typed(const SliceView& v) {
 int64_t slice_cap(int64_t nnz) { return nnz + nnz / 8 + 256; }
 int nslices(int32_t n) { return (n + 255) / 256; }
 
-// Builds the sliced copy of A (n > 0) into off[nslices + 1], col[cap], val[cap] (A's
-// value type).  Returns the padded entry count -- above cap nothing was filled and the
-// caller keeps the CSR form -- or -1 on a HIP error.  Synchronises the stream once.
-int64_t build_slices(const pbcg_csr* A, int64_t* off, int32_t* col, void* val, int64_t cap, hipStream_t s) {
+// Builds the sliced copy of A (n > 0) into off[nslices + 2] (the last entry is scratch),
+// col[cap], val[cap] (A's value type).  With allow16 and every |col - row| <= 32767 the
+// column entries are stored as 16-bit offsets (*d16 = true).  Returns the padded entry
+// count -- above cap nothing was filled and the caller keeps the CSR form -- or -1 on a
+// HIP error.  Synchronises the stream once.
+int64_t build_slices(const pbcg_csr* A, int64_t* off, int32_t* col, void* val, int64_t cap, hipStream_t s,
+                     bool allow16, bool* d16) {
     const int n = A->n, ns = nslices(n);
-    slice_width_kernel<<<ns, 256, 0, s>>>(n, A->row_ptr, off);
+    *d16 = false;
+    slice_clear_kernel<<<1, 1, 0, s>>>(off + ns + 1);
+    slice_width_kernel<<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, off, off + ns + 1);
     slice_scan_kernel<<<1, 1024, 0, s>>>(ns, off);
-    int64_t total = 0;
-    if (hipMemcpyAsync(&total, off + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    int64_t tm[2] = {0, 0};   // padded entries, largest |col - row|
+    if (hipMemcpyAsync(tm, off + ns, sizeof(tm), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
     if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    const int64_t total = tm[0];
     if (total > cap) return total;
-    if (A->val_type == PBCG_F64)
-        slice_fill_kernel<double><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const double*)A->val, off, col,
-                                                     (double*)val);
-    else
-        slice_fill_kernel<float><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const float*)A->val, off, col,
-                                                    (float*)val);
+    *d16 = allow16 && tm[1] <= 32767;
+    auto fill = [&](auto vt, auto d) {
+        using VT = decltype(vt);
+        slice_fill_kernel<VT, decltype(d)::value><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const VT*)A->val,
+                                                                     off, col, (VT*)val);
+    };
+    if (A->val_type == PBCG_F64) {
+        if (*d16) fill(double{}, std::true_type{});
+        else fill(double{}, std::false_type{});
+    } else {
+        if (*d16) fill(float{}, std::true_type{});
+        else fill(float{}, std::false_type{});
+    }
     if (hipGetLastError() != hipSuccess) return -1;
     return total;
 }
@@ -167,12 +192,11 @@ void launch_spmv_t(const Mat& A, const XT* x, Epi epi, const int* halt, hipStrea
         const int workers = std::min((n + BLOCK - 1) / BLOCK, A.sl.off ? SLICE_WORKERS : SEQ_WORKERS);
         const int grid = workers + (Fin::D > 0 ? 1 : 0);
         if (grid > 0) {
-            if (A.sl.off && A.sl.nt)
-                klaunch(spmv_seq_kernel<VT, XT, AT, Epi, Fin, false, true, true>, grid, BLOCK, 0, s,
-                        n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, typed<VT>(A.sl));
-            else if (A.sl.off)
-                klaunch(spmv_seq_kernel<VT, XT, AT, Epi, Fin, false, true>, grid, BLOCK, 0, s,
-                        n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, typed<VT>(A.sl));
+            if (A.sl.off)
+                with_slf(A.sl, [&](auto m) {
+                    klaunch(spmv_seq_kernel<VT, XT, AT, Epi, Fin, false, true, decltype(m)::value>, grid, BLOCK, 0,
+                            s, n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, typed<VT>(A.sl));
+                });
             else
                 klaunch(spmv_seq_kernel<VT, XT, AT, Epi, Fin>, grid, BLOCK, 0, s,
                         n, A->row_ptr, A->col_idx, val, x, epi, fin, halt, Sliced<VT>{});
@@ -209,12 +233,11 @@ void launch_spmv32c(const Mat& A, const float* x, Epi epi, const int* halt, hipS
     const int workers = std::min((n + BLOCK - 1) / BLOCK, A.sl.off ? SLICE_WORKERS : SEQ_WORKERS);
     const int grid = workers + (Fin::D > 0 ? 1 : 0);
     if (grid > 0) {
-        if (A.sl.off && A.sl.nt)
-            spmv_seq_kernel<float, float, float, Epi, Fin, true, true, true><<<grid, BLOCK, 0, s>>>(
-                n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt, typed<float>(A.sl));
-        else if (A.sl.off)
-            spmv_seq_kernel<float, float, float, Epi, Fin, true, true><<<grid, BLOCK, 0, s>>>(
-                n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt, typed<float>(A.sl));
+        if (A.sl.off)
+            with_slf(A.sl, [&](auto m) {
+                spmv_seq_kernel<float, float, float, Epi, Fin, true, true, decltype(m)::value><<<grid, BLOCK, 0, s>>>(
+                    n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt, typed<float>(A.sl));
+            });
         else
             spmv_seq_kernel<float, float, float, Epi, Fin, true><<<grid, BLOCK, 0, s>>>(
                 n, A->row_ptr, A->col_idx, (const float*)A->val, x, epi, fin, halt, Sliced<float>{});
@@ -229,12 +252,11 @@ void launch_spmv_dot_t(const Mat& A, const double* x, Epi epi, xd::Site site, co
     if (kind == PBCG_SPMV_SEQ) {
         // persistent: up to 4 blocks per CU (one dot record each)
         int grid = std::max(1, std::min(DOT_GRID_MAX, (n + BLOCK - 1) / BLOCK));
-        if (A.sl.off && A.sl.nt)
-            spmv_seq_dot_kernel<D, KEXP, VT, Epi, true, true><<<grid, BLOCK, 0, s>>>(
-                n, A->row_ptr, A->col_idx, val, x, epi, site, halt, typed<VT>(A.sl));
-        else if (A.sl.off)
-            spmv_seq_dot_kernel<D, KEXP, VT, Epi, true><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x,
-                                                                                epi, site, halt, typed<VT>(A.sl));
+        if (A.sl.off)
+            with_slf(A.sl, [&](auto m) {
+                spmv_seq_dot_kernel<D, KEXP, VT, Epi, true, decltype(m)::value><<<grid, BLOCK, 0, s>>>(
+                    n, A->row_ptr, A->col_idx, val, x, epi, site, halt, typed<VT>(A.sl));
+            });
         else
             spmv_seq_dot_kernel<D, KEXP, VT, Epi><<<grid, BLOCK, 0, s>>>(n, A->row_ptr, A->col_idx, val, x, epi,
                                                                           site, halt, Sliced<VT>{});
@@ -529,7 +551,7 @@ int csr_spmv_f32(const pbcg_csr* A, const float* x, float* y, void* stream) {
 size_t csr_slice_workspace_bytes(int32_t n, int64_t nnz) {
     if (n < 0 || nnz < 0) return 0;
     Carver c(nullptr, SIZE_MAX);
-    c.take<int64_t>((size_t)nslices(n) + 1);
+    c.take<int64_t>((size_t)nslices(n) + 2);
     c.take<int32_t>((size_t)slice_cap(nnz));
     c.take<double>((size_t)slice_cap(nnz));
     return c.off + 256;
@@ -542,10 +564,11 @@ int csr_slice(const pbcg_csr* A, pbcg_sliced* S, void* ws, size_t ws_bytes, void
         return PBCG_ERR_WORKSPACE;
     if (A->n == 0) return PBCG_OK;
     Carver c(ws, ws_bytes);
-    int64_t* off = c.take<int64_t>((size_t)nslices(A->n) + 1);
+    int64_t* off = c.take<int64_t>((size_t)nslices(A->n) + 2);
     int32_t* col = c.take<int32_t>((size_t)slice_cap(A->nnz));
     void* val = c.take<double>((size_t)slice_cap(A->nnz));
-    const int64_t total = build_slices(A, off, col, val, slice_cap(A->nnz), (hipStream_t)stream);
+    bool d16 = false;   // the public copy keeps 32-bit columns
+    const int64_t total = build_slices(A, off, col, val, slice_cap(A->nnz), (hipStream_t)stream, false, &d16);
     if (total < 0) return PBCG_ERR_HIP;
     S->entries = total;
     if (total <= slice_cap(A->nnz)) {
@@ -706,11 +729,11 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
         W.val32 = c.take<float>((size_t)std::max<int64_t>(slicing_on(o) ? slice_cap(nnz) : nnz, 1));
     }
     if (slicing_on(o)) {
-        W.a_off = c.take<int64_t>((size_t)nslices(n) + 1);
+        W.a_off = c.take<int64_t>((size_t)nslices(n) + 2);
         W.a_col = c.take<int32_t>((size_t)slice_cap(nnz));
         W.a_val = c.take<double>((size_t)slice_cap(nnz));
         if (o->M) {
-            W.m_off = c.take<int64_t>((size_t)nslices(n) + 1);
+            W.m_off = c.take<int64_t>((size_t)nslices(n) + 2);
             W.m_col = c.take<int32_t>((size_t)slice_cap(o->M->nnz));
             W.m_val = c.take<double>((size_t)slice_cap(o->M->nnz));
         }
@@ -726,10 +749,10 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
 // plain stores are faster.
 constexpr double INFINITY_CACHE_BYTES = 256.0 * 1024 * 1024;
 
-double matrix_bytes(const pbcg_csr* A, int64_t sliced_entries, int value_bytes) {
+double matrix_bytes(const pbcg_csr* A, int64_t sliced_entries, int value_bytes, bool d16 = false) {
     if (!A) return 0.0;
     const double entries = sliced_entries > 0 ? (double)sliced_entries : (double)A->nnz;
-    return entries * (value_bytes + 4) + 4.0 * ((double)A->n + 1) +
+    return entries * (value_bytes + (d16 ? 2 : 4)) + 4.0 * ((double)A->n + 1) +
            (sliced_entries > 0 ? 8.0 * (nslices(A->n) + 1) : 0.0);
 }
 
@@ -1089,7 +1112,7 @@ struct Driver {
         A32c.val_type = PBCG_F32;
         if (A.sl.off) {   // the FP32 values in the sliced order (padding casts to 0)
             launch_ew(FnCastVal{W.val32, (const double*)A.sl.val}, a_entries, nullptr, s);
-            A32 = Mat(&A32c, SliceView{A.sl.off, A.sl.col, W.val32, mnt32});
+            A32 = Mat(&A32c, SliceView{A.sl.off, A.sl.col, W.val32, mnt32, A.sl.d16});
         } else {
             launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
             A32 = Mat(&A32c);
@@ -1264,18 +1287,22 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     int sliced = 0;   // bit 0: A, bit 1: M use a sliced copy
     int64_t m_entries = 0;
     if (slicing_on(opts)) {
-        const int64_t ta = build_slices(A, W.a_off, W.a_col, W.a_val, slice_cap(A->nnz), D.s);
+        bool a16 = false, m16 = false;
+        const int64_t ta = build_slices(A, W.a_off, W.a_col, W.a_val, slice_cap(A->nnz), D.s, true, &a16);
         if (ta < 0) return PBCG_ERR_HIP;
         if (ta <= slice_cap(A->nnz)) {
             D.A.sl = SliceView{W.a_off, W.a_col, W.a_val};
+            D.A.sl.d16 = a16;
             D.a_entries = ta;
             sliced |= 1;
         }
         if (opts->M) {
-            const int64_t tm = build_slices(opts->M, W.m_off, W.m_col, W.m_val, slice_cap(opts->M->nnz), D.s);
+            const int64_t tm = build_slices(opts->M, W.m_off, W.m_col, W.m_val, slice_cap(opts->M->nnz), D.s, true,
+                                            &m16);
             if (tm < 0) return PBCG_ERR_HIP;
             if (tm <= slice_cap(opts->M->nnz)) {
                 D.M.sl = SliceView{W.m_off, W.m_col, W.m_val};
+                D.M.sl.d16 = m16;
                 m_entries = tm;
                 sliced |= 2;
             }
@@ -1284,19 +1311,23 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     {
         const int64_t ma = (sliced & 1) ? D.a_entries : 0;
         const int vb = A->val_type == PBCG_F64 ? 8 : 4;
-        double ws64 = matrix_bytes(A, ma, vb) + 12.0 * 8.0 * A->n;
+        const bool a16 = D.A.sl.d16, m16 = D.M.sl.d16;
+        double ws64 = matrix_bytes(A, ma, vb, a16) + 12.0 * 8.0 * A->n;
         if (opts->M) {
             const int64_t mm = (sliced & 2) ? m_entries : 0;
-            ws64 += matrix_bytes(opts->M, mm, opts->M->val_type == PBCG_F64 ? 8 : 4) + 8.0 * A->n;
+            ws64 += matrix_bytes(opts->M, mm, opts->M->val_type == PBCG_F64 ? 8 : 4, m16) + 8.0 * A->n;
         }
         D.nt64 = ws64 > INFINITY_CACHE_BYTES;
-        D.nt32 = matrix_bytes(A, ma, 4) + 11.0 * 4.0 * A->n > INFINITY_CACHE_BYTES;
+        D.nt32 = matrix_bytes(A, ma, 4, a16) + 11.0 * 4.0 * A->n > INFINITY_CACHE_BYTES;
         // a matrix that does not fit the cache at all streams past it as well (measured on
         // 256^3: 1.79 -> 1.69 s; a matrix that fits stays resident instead)
-        D.A.sl.nt = (sliced & 1) && matrix_bytes(A, ma, vb) > INFINITY_CACHE_BYTES;
-        D.mnt32 = (sliced & 1) && matrix_bytes(A, ma, 4) > INFINITY_CACHE_BYTES;
+        D.A.sl.nt = (sliced & 1) && matrix_bytes(A, ma, vb, a16) > INFINITY_CACHE_BYTES;
+        D.mnt32 = (sliced & 1) && matrix_bytes(A, ma, 4, a16) > INFINITY_CACHE_BYTES;
         if (opts->M && (sliced & 2))
-            D.M.sl.nt = matrix_bytes(opts->M, m_entries, opts->M->val_type == PBCG_F64 ? 8 : 4) > INFINITY_CACHE_BYTES;
+            D.M.sl.nt = matrix_bytes(opts->M, m_entries, opts->M->val_type == PBCG_F64 ? 8 : 4, m16) >
+                        INFINITY_CACHE_BYTES;
+        if (a16) sliced |= 4;
+        if (m16) sliced |= 8;
     }
     State h{};
     int status;

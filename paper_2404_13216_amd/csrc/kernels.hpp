@@ -186,16 +186,23 @@ constexpr int SLICE_UNROLL = 8;   // entries of a row loaded ahead of their addi
 
 // One lane's row of slice c of a sliced copy (len entries, storage order): s (and the
 // Dot2 compensation cmp when COMP) accumulate exactly as in the staged path below.
-// MNT: the slice's values and columns are read with non-temporal loads (a matrix larger than
-// the Infinity Cache streams past it instead of evicting the vectors).
-template <class VT, class XT, class AT, bool COMP, bool MNT = false>
+// Layout flags SLF of a sliced copy: SL_NT -- the slice's values and column entries are read
+// with non-temporal loads (a matrix larger than the Infinity Cache streams past it instead
+// of evicting the vectors); SL_D16 -- the column entries are 16-bit offsets col - row (every
+// offset of the matrix fits), two bytes per entry less than absolute 32-bit columns.
+constexpr int SL_NT = 1, SL_D16 = 2;
+
+template <class VT, class XT, class AT, bool COMP, int SLF = 0>
 __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, int len, const XT* __restrict__ x,
                                           AT& s, AT& cmp) {
     constexpr int U = SLICE_UNROLL, R = 256;
+    constexpr bool MNT = (SLF & SL_NT) != 0, D16 = (SLF & SL_D16) != 0;
     const int64_t base = sl.off[c];
     const int w = (int)((sl.off[c + 1] - base) / R);
+    const int row = c * R + t;
     const VT* __restrict__ vp = sl.val + base + t;
     const int32_t* __restrict__ cp = sl.col + base + t;
+    const int16_t* __restrict__ dp = (const int16_t*)sl.col + base + t;
     for (int k0 = 0; k0 < w; k0 += U) {
         VT av[U];
         int32_t cv[U];
@@ -204,12 +211,15 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
             av[u] = VT(0);
             cv[u] = 0;
             if (k0 + u < w) {
+                const int64_t o = (int64_t)(k0 + u) * R;
                 if constexpr (MNT) {
-                    av[u] = __builtin_nontemporal_load(vp + (int64_t)(k0 + u) * R);
-                    cv[u] = __builtin_nontemporal_load(cp + (int64_t)(k0 + u) * R);
+                    av[u] = __builtin_nontemporal_load(vp + o);
+                    if constexpr (D16) cv[u] = row + (int)__builtin_nontemporal_load(dp + o);
+                    else cv[u] = __builtin_nontemporal_load(cp + o);
                 } else {
-                    av[u] = vp[(int64_t)(k0 + u) * R];
-                    cv[u] = cp[(int64_t)(k0 + u) * R];
+                    av[u] = vp[o];
+                    if constexpr (D16) cv[u] = row + (int)dp[o];
+                    else cv[u] = cp[o];
                 }
             }
         }
@@ -260,7 +270,7 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
 // (2005) in storage order -- the window holds (p, e) with p = fl(a x) and the exact
 // product error e = fma(a, x, -p); each lane runs TwoSum(s, p) and adds err + e into a
 // compensation c; the row's value is fl(s + c).  All arithmetic is float32.
-template <int CAP, class VT, class XT, class AT, class Body, bool COMP = false, bool SL = false, bool MNT = false>
+template <int CAP, class VT, class XT, class AT, class Body, bool COMP = false, bool SL = false, int SLF = 0>
 __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                           const VT* __restrict__ val, const XT* __restrict__ x,
                                           int bfirst, int G, AT* sprod, Body& body, Sliced<VT> sl = {}) {
@@ -290,7 +300,7 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
         if (row < r1) { RA = rp[row]; RB = rp[row + 1]; }
         AT s = AT(0), cmp = AT(0);
         if constexpr (SL) {
-            slice_row<VT, XT, AT, COMP, MNT>(sl, c, t, RB - RA, x, s, cmp);
+            slice_row<VT, XT, AT, COMP, SLF>(sl, c, t, RB - RA, x, s, cmp);
         } else {
             const int A0 = rp[r0], A1 = rp[r1];
             for (int w = A0; w < A1; w += CAP) {
@@ -349,7 +359,7 @@ struct StoreBody {
 };
 
 // grid = worker blocks (+1 when block 0 carries a finalize role)
-template <class VT, class XT, class AT, class Epi, class Fin, bool COMP = false, bool SL = false, bool MNT = false>
+template <class VT, class XT, class AT, class Epi, class Fin, bool COMP = false, bool SL = false, int SLF = 0>
 __global__ void __launch_bounds__(256)
 spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                 const VT* __restrict__ val, const XT* __restrict__ x, Epi epi, Fin fin, const int* halt,
@@ -367,23 +377,36 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
         bfirst = 1;
     }
     StoreBody<Epi> body{epi};
-    seq_stage<SEQ_CAP, VT, XT, AT, StoreBody<Epi>, COMP, SL, MNT>(n, rp, ci, val, x, bfirst,
+    seq_stage<SEQ_CAP, VT, XT, AT, StoreBody<Epi>, COMP, SL, SLF>(n, rp, ci, val, x, bfirst,
                                                                    (int)gridDim.x - bfirst, (AT*)smem, body, sl);
 }
 
-// Sliced copy, step 1: off[c + 1] = 256 * (longest row of slice c), off[0] = 0.
+// Sliced copy, step 0: clear the largest-offset slot (off[nslice + 1]).
+__global__ void slice_clear_kernel(int64_t* __restrict__ slot) { *slot = 0; }
+
+// Step 1: off[c + 1] = 256 * (longest row of slice c), off[0] = 0; maxd = max |col - row|.
 __global__ void __launch_bounds__(256) slice_width_kernel(int n, const int32_t* __restrict__ rp,
-                                                          int64_t* __restrict__ off) {
-    __shared__ int sh[4];
+                                                          const int32_t* __restrict__ ci,
+                                                          int64_t* __restrict__ off, int64_t* __restrict__ maxd) {
+    __shared__ int sh[4], shd[4];
     const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
-    int len = row < n ? rp[row + 1] - rp[row] : 0;
+    int len = 0, d = 0;
+    if (row < n) {
+        const int a = rp[row], b = rp[row + 1];
+        len = b - a;
+        for (int k = a; k < b; ++k) d = max(d, abs(ci[k] - row));
+    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o));
-    if ((t & 63) == 0) sh[t >> 6] = len;
+    for (int o = 32; o > 0; o >>= 1) {
+        len = max(len, __shfl_xor(len, o));
+        d = max(d, __shfl_xor(d, o));
+    }
+    if ((t & 63) == 0) { sh[t >> 6] = len; shd[t >> 6] = d; }
     __syncthreads();
     if (t == 0) {
         off[c + 1] = 256LL * max(max(sh[0], sh[1]), max(sh[2], sh[3]));
         if (c == 0) off[0] = 0;
+        atomicMax((unsigned long long*)maxd, (unsigned long long)max(max(shd[0], shd[1]), max(shd[2], shd[3])));
     }
 }
 
@@ -410,8 +433,9 @@ __global__ void __launch_bounds__(1024) slice_scan_kernel(int ns, int64_t* __res
     }
 }
 
-// Step 3: copy every row into its slice (lane t of block c: row 256c + t).
-template <class VT>
+// Step 3: copy every row into its slice (lane t of block c: row 256c + t); D16: the column
+// entries as 16-bit offsets col - row (the caller checked that every offset fits).
+template <class VT, bool D16>
 __global__ void __launch_bounds__(256) slice_fill_kernel(int n, const int32_t* __restrict__ rp,
                                                          const int32_t* __restrict__ ci, const VT* __restrict__ val,
                                                          const int64_t* __restrict__ off, int32_t* __restrict__ scol,
@@ -421,10 +445,12 @@ __global__ void __launch_bounds__(256) slice_fill_kernel(int n, const int32_t* _
     const int w = (int)((off[c + 1] - base) / 256);
     int a = 0, len = 0;
     if (row < n) { a = rp[row]; len = rp[row + 1] - a; }
+    int16_t* dcol = (int16_t*)scol;
     for (int k = 0; k < w; ++k) {
         const int64_t i = base + (int64_t)k * 256 + t;
-        if (k < len) { scol[i] = ci[a + k]; sval[i] = val[a + k]; }
-        else { scol[i] = 0; sval[i] = VT(0); }
+        if constexpr (D16) dcol[i] = k < len ? (int16_t)(ci[a + k] - row) : (int16_t)0;
+        else scol[i] = k < len ? ci[a + k] : 0;
+        sval[i] = k < len ? val[a + k] : VT(0);
     }
 }
 
@@ -542,7 +568,7 @@ struct DotBody {
     }
 };
 
-template <int D, int K, class VT, class Epi, bool SL = false, bool MNT = false>
+template <int D, int K, class VT, class Epi, bool SL = false, int SLF = 0>
 __global__ void __launch_bounds__(256)
 spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const VT* __restrict__ val, const double* __restrict__ x, Epi epi,
@@ -558,7 +584,7 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 #pragma unroll
         for (int k = 0; k < K; ++k) e[d][k] = 0.0;
     DotBody<D, K, Epi> body{epi, e, sh_acc, sh_flags};
-    seq_stage<SEQ_CAP, VT, double, double, DotBody<D, K, Epi>, false, SL, MNT>(n, rp, ci, val, x, 0,
+    seq_stage<SEQ_CAP, VT, double, double, DotBody<D, K, Epi>, false, SL, SLF>(n, rp, ci, val, x, 0,
                                                                                  (int)gridDim.x, sprod, body, sl);
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);

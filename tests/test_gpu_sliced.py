@@ -32,6 +32,29 @@ def expect_built(A):
     return padded_entries(A) <= A.nnz + A.nnz // 8 + 256
 
 
+def max_offset(A):
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr.astype(np.int64)))
+    return int(np.abs(A.col_idx.astype(np.int64) - rows).max()) if A.nnz else 0
+
+
+def expect_sliced_bits(A):
+    """info['sliced'] of a solve with layout AUTO: bit 0 when A's sliced copy is built,
+    bit 2 when its columns are stored as 16-bit offsets (every |col - row| <= 32767)."""
+    if not expect_built(A):
+        return 0
+    return 1 | (4 if max_offset(A) <= 32767 else 0)
+
+
+def with_long_range_entry(A, value):
+    """A with one extra entry in row 0 at the last column (offset n - 1)."""
+    k = int(A.row_ptr[1])
+    ci = np.insert(A.col_idx, k, A.n - 1).astype(np.int32)
+    val = np.insert(A.val, k, value)
+    rp = A.row_ptr.astype(np.int64).copy()
+    rp[1:] += 1
+    return g.CSR(A.n, rp.astype(np.int32), ci, val)
+
+
 def ragged(n, lens, seed):
     rng = np.random.default_rng(seed)
     rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
@@ -107,7 +130,7 @@ def test_solve_same_bits_with_and_without_slices(name, scale, prec):
     b = to_dev(p.b)
     xa, ia = pk.solve(A, b, tol=1e-10, prec=prec)
     xc, ic = pk.solve(A, b, tol=1e-10, prec=prec, layout=pk.LAYOUT_CSR)
-    assert ia["sliced"] == (1 if expect_built(p.A) else 0)
+    assert ia["sliced"] == expect_sliced_bits(p.A)
     assert ic["sliced"] == 0
     for k in ("status", "iterations", "outer_iterations", "true_checks"):
         assert ia[k] == ic[k], k
@@ -122,13 +145,35 @@ def test_preconditioned_solve_slices_m():
     J = pk.jacobi(A)
     xa, ia = pk.solve(A, b, M=J, tol=1e-10)
     xc, ic = pk.solve(A, b, M=J, tol=1e-10, layout=pk.LAYOUT_CSR)
-    assert ia["sliced"] == 3 and ic["sliced"] == 0
+    assert ia["sliced"] == 1 | 2 | 4 | 8 and ic["sliced"] == 0   # both copies with 16-bit offsets
     assert ia["iterations"] == ic["iterations"]
     assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
     # M on A's pattern: scaled copy of A's values
     M = A.with_values(A.val * 0.5)
     xa, ia = pk.solve(A, b, M=M, tol=1e-10, max_iter=50)
     xc, ic = pk.solve(A, b, M=M, tol=1e-10, max_iter=50, layout=pk.LAYOUT_CSR)
-    assert ia["sliced"] == 3
+    assert ia["sliced"] == 1 | 2 | 4 | 8
     assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
     assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", [pk.PREC_FP64, pk.PREC_FP32_IR])
+def test_solve_sliced_32bit_columns(prec):
+    """One entry at offset n - 1 > 32767 keeps the sliced copy's 32-bit columns; the solve
+    must still return the same bits as on CSR (and as the oracle in FP64)."""
+    p = g.problem("cd2d_64", scale=200)                    # n = 40,000
+    Ah = with_long_range_entry(p.A, -1e-3 * p.A.val[0])
+    assert max_offset(Ah) == Ah.n - 1 > 32767 and expect_built(Ah)
+    xs = np.random.default_rng(3).uniform(-1, 1, Ah.n)
+    bh = spmv(Ah, xs)
+    A = pk.CSR.from_host(Ah)
+    b = to_dev(bh)
+    xa, ia = pk.solve(A, b, tol=1e-10, max_iter=60, prec=prec)
+    xc, ic = pk.solve(A, b, tol=1e-10, max_iter=60, prec=prec, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == 1 and ic["sliced"] == 0
+    assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+    if prec == pk.PREC_FP64:
+        ora = ctier.pbicgstab(Ah, bh, tol=1e-10, max_iter=60)
+        assert ora["iterations"] == ia["iterations"]
+        assert np.array_equal(xa.cpu().numpy().view(np.uint64), ora["x"].view(np.uint64))
