@@ -402,7 +402,7 @@ def main():
     del tsolver, xk
     used = max(1, min(KEV, info["iterations"] - 2 * solver.opts.batch))
     # the SpMV's bytes: 8-byte value + column entry per nonzero (4 bytes, or 2 when the
-    # sliced copy stores 16-bit column offsets), x once, y, row pointers: 20 bytes per row
+    # sliced copy stores 16-bit column residuals), x once, y, row pointers: 20 bytes per row
     col_bytes = 2 if info["sliced"] & 4 else 4
     spmv_bytes = (8 + col_bytes) * nnz + 20 * n
     roles = {"phase_a": 104 * n, "spmv_az": spmv_bytes, "phase_b": 80 * n, "spmv_aw": spmv_bytes}
@@ -438,7 +438,7 @@ def main():
                    "n": n, "nnz": nnz, "tol": 1e-10, "x0": "0", "alg": "p-BiCGStab",
                    "dots": "exact (rounded once)",
                    "spmv": "row-sequential, " + ("sliced copy (256-row slices%s)" % (
-                       ", 16-bit column offsets" if info["sliced"] & 4 else "") if info["sliced"] & 1 else "CSR")},
+                       ", 16-bit column residuals" if info["sliced"] & 4 else "") if info["sliced"] & 1 else "CSR")},
         "iterations": info["iterations"],
         "true_relres": info["true_relres"],
         "rel_err_vs_xstar": err_xstar,

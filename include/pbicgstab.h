@@ -68,8 +68,9 @@ typedef enum { PBCG_DOTS_EXACT = 0, PBCG_DOTS_PLAIN = 1 } pbcg_dots;
 
 /* Matrix layout of the solver's row-sequential SpMVs.  AUTO: the solver copies A (and
  * M) into the sliced layout of csr_slice when its padding stays within nnz/8 + 256
- * entries, else it keeps CSR; the copy stores the column entries as 16-bit offsets
- * col - row when every |col - row| <= 32767 (2 bytes per entry less).  CSR: never
+ * entries, else it keeps CSR; the copy stores each column entry as a 16-bit residual
+ * col - row - base, with one 32-bit base per slice and entry position (the smallest
+ * col - row there), when every residual fits (2 bytes per entry less).  CSR: never
  * copied.  All give bit-identical results. */
 typedef enum { PBCG_LAYOUT_AUTO = 0, PBCG_LAYOUT_CSR = 1 } pbcg_layout;
 
@@ -138,7 +139,7 @@ typedef struct {
     int32_t true_checks;       /* true-residual evaluations                                  */
     int32_t fell_back;         /* 1 if the preconditioned solve fell back                    */
     int32_t sliced;            /* bit 0: A, bit 1: M ran on a sliced copy (layout AUTO);
-                                  bit 2: A's, bit 3: M's copy holds 16-bit column offsets   */
+                                  bit 2: A's, bit 3: M's copy holds 16-bit column residuals */
     double true_relres;        /* ||b - A x|| / ||b|| of the returned x (exact dots)         */
     double rec_relres;         /* last recursive ||r|| / ||b||                               */
     double seconds;            /* host wall time of the call                                 */

@@ -91,10 +91,11 @@ bool csr_ok(const pbcg_csr* A) {
 // copy with the same row order (read by the row-sequential kernels only).
 struct SliceView {
     const int64_t* off = nullptr;
-    const int32_t* col = nullptr;   // 32-bit columns, or 16-bit offsets col - row when d16
+    const int32_t* col = nullptr;   // 32-bit columns, or 16-bit residuals when d16
     const void* val = nullptr;
     bool nt = false;    // matrix larger than the Infinity Cache: stream it (non-temporal loads)
-    bool d16 = false;   // column entries are 16-bit offsets
+    bool d16 = false;   // column entries are 16-bit residuals from a per-position base
+    const int32_t* base = nullptr;  // per slice and position (d16)
 };
 
 // the runtime layout of a sliced copy -> the kernels' compile-time layout flags
@@ -120,7 +121,7 @@ struct Mat {
 
 template <class VT>
 Sliced<VT> typed(const SliceView& v) {
-    return Sliced<VT>{v.off, v.col, (const VT*)v.val};
+    return Sliced<VT>{v.off, v.col, (const VT*)v.val, v.base};
 }
 
 // A sliced copy is kept when its padding is at most nnz/8 + 256 entries.
@@ -128,27 +129,31 @@ int64_t slice_cap(int64_t nnz) { return nnz + nnz / 8 + 256; }
 int nslices(int32_t n) { return (n + 255) / 256; }
 
 // Builds the sliced copy of A (n > 0) into off[nslices + 2] (the last entry is scratch),
-// col[cap], val[cap] (A's value type).  With allow16 and every |col - row| <= 32767 the
-// column entries are stored as 16-bit offsets (*d16 = true).  Returns the padded entry
-// count -- above cap nothing was filled and the caller keeps the CSR form -- or -1 on a
-// HIP error.  Synchronises the stream once.
-int64_t build_slices(const pbcg_csr* A, int64_t* off, int32_t* col, void* val, int64_t cap, hipStream_t s,
-                     bool allow16, bool* d16) {
+// col[cap], val[cap] (A's value type) and, with allow16, sbase[cap / 256 + 1].  With
+// allow16 and every residual col - row - base[c][k] within 16 bits the column entries are
+// stored as 16-bit residuals (*d16 = true).  Returns the padded entry count -- above cap
+// nothing was filled and the caller keeps the CSR form -- or -1 on a HIP error.
+// Synchronises the stream once.
+int64_t build_slices(const pbcg_csr* A, int64_t* off, int32_t* col, void* val, int32_t* sbase, int64_t cap,
+                     hipStream_t s, bool allow16, bool* d16) {
     const int n = A->n, ns = nslices(n);
     *d16 = false;
     slice_clear_kernel<<<1, 1, 0, s>>>(off + ns + 1);
-    slice_width_kernel<<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, off, off + ns + 1);
+    slice_width_kernel<<<ns, 256, 0, s>>>(n, A->row_ptr, off);
     slice_scan_kernel<<<1, 1024, 0, s>>>(ns, off);
-    int64_t tm[2] = {0, 0};   // padded entries, largest |col - row|
+    if (allow16)
+        slice_base_kernel<<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, off, cap, sbase,
+                                             (unsigned long long*)(off + ns + 1));
+    int64_t tm[2] = {0, 0};   // padded entries, residual-overflow flag
     if (hipMemcpyAsync(tm, off + ns, sizeof(tm), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
     if (hipStreamSynchronize(s) != hipSuccess) return -1;
     const int64_t total = tm[0];
     if (total > cap) return total;
-    *d16 = allow16 && tm[1] <= 32767;
+    *d16 = allow16 && tm[1] == 0;
     auto fill = [&](auto vt, auto d) {
         using VT = decltype(vt);
         slice_fill_kernel<VT, decltype(d)::value><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const VT*)A->val,
-                                                                     off, col, (VT*)val);
+                                                                     off, sbase, col, (VT*)val);
     };
     if (A->val_type == PBCG_F64) {
         if (*d16) fill(double{}, std::true_type{});
@@ -568,7 +573,8 @@ int csr_slice(const pbcg_csr* A, pbcg_sliced* S, void* ws, size_t ws_bytes, void
     int32_t* col = c.take<int32_t>((size_t)slice_cap(A->nnz));
     void* val = c.take<double>((size_t)slice_cap(A->nnz));
     bool d16 = false;   // the public copy keeps 32-bit columns
-    const int64_t total = build_slices(A, off, col, val, slice_cap(A->nnz), (hipStream_t)stream, false, &d16);
+    const int64_t total = build_slices(A, off, col, val, nullptr, slice_cap(A->nnz), (hipStream_t)stream, false,
+                                       &d16);
     if (total < 0) return PBCG_ERR_HIP;
     S->entries = total;
     if (total <= slice_cap(A->nnz)) {
@@ -698,7 +704,7 @@ struct Work {
     double *rhat, *r, *w, *t, *p, *s, *z, *q, *y, *v, *tmp, *tmp2, *xbest, *hist;   // xbest: best tested iterate
     float *r32, *rh32, *w32, *t32, *p32, *s32, *z32, *q32, *y32, *v32, *d32, *val32;
     int64_t *a_off, *m_off;   // sliced copies of A and M (null: not reserved)
-    int32_t *a_col, *m_col;
+    int32_t *a_col, *m_col, *a_base, *m_base;
     void *a_val, *m_val;
     size_t need;
     bool ok;
@@ -732,10 +738,12 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
         W.a_off = c.take<int64_t>((size_t)nslices(n) + 2);
         W.a_col = c.take<int32_t>((size_t)slice_cap(nnz));
         W.a_val = c.take<double>((size_t)slice_cap(nnz));
+        W.a_base = c.take<int32_t>((size_t)(slice_cap(nnz) / 256 + 1));
         if (o->M) {
             W.m_off = c.take<int64_t>((size_t)nslices(n) + 2);
             W.m_col = c.take<int32_t>((size_t)slice_cap(o->M->nnz));
             W.m_val = c.take<double>((size_t)slice_cap(o->M->nnz));
+            W.m_base = c.take<int32_t>((size_t)(slice_cap(o->M->nnz) / 256 + 1));
         }
     }
     W.need = c.off + 256;
@@ -1112,7 +1120,7 @@ struct Driver {
         A32c.val_type = PBCG_F32;
         if (A.sl.off) {   // the FP32 values in the sliced order (padding casts to 0)
             launch_ew(FnCastVal{W.val32, (const double*)A.sl.val}, a_entries, nullptr, s);
-            A32 = Mat(&A32c, SliceView{A.sl.off, A.sl.col, W.val32, mnt32, A.sl.d16});
+            A32 = Mat(&A32c, SliceView{A.sl.off, A.sl.col, W.val32, mnt32, A.sl.d16, A.sl.base});
         } else {
             launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
             A32 = Mat(&A32c);
@@ -1288,21 +1296,23 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     int64_t m_entries = 0;
     if (slicing_on(opts)) {
         bool a16 = false, m16 = false;
-        const int64_t ta = build_slices(A, W.a_off, W.a_col, W.a_val, slice_cap(A->nnz), D.s, true, &a16);
+        const int64_t ta = build_slices(A, W.a_off, W.a_col, W.a_val, W.a_base, slice_cap(A->nnz), D.s, true, &a16);
         if (ta < 0) return PBCG_ERR_HIP;
         if (ta <= slice_cap(A->nnz)) {
             D.A.sl = SliceView{W.a_off, W.a_col, W.a_val};
             D.A.sl.d16 = a16;
+            D.A.sl.base = W.a_base;
             D.a_entries = ta;
             sliced |= 1;
         }
         if (opts->M) {
-            const int64_t tm = build_slices(opts->M, W.m_off, W.m_col, W.m_val, slice_cap(opts->M->nnz), D.s, true,
-                                            &m16);
+            const int64_t tm = build_slices(opts->M, W.m_off, W.m_col, W.m_val, W.m_base, slice_cap(opts->M->nnz),
+                                            D.s, true, &m16);
             if (tm < 0) return PBCG_ERR_HIP;
             if (tm <= slice_cap(opts->M->nnz)) {
                 D.M.sl = SliceView{W.m_off, W.m_col, W.m_val};
                 D.M.sl.d16 = m16;
+                D.M.sl.base = W.m_base;
                 m_entries = tm;
                 sliced |= 2;
             }

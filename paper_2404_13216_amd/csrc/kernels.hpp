@@ -19,6 +19,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include "state.hpp"
@@ -178,18 +179,22 @@ spmv_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ c
 template <class VT>
 struct Sliced {
     const int64_t* off = nullptr;   // [nslice + 1] entry offsets; null: use the CSR arrays
-    const int32_t* col = nullptr;
+    const int32_t* col = nullptr;   // 32-bit columns, or (SL_D16) 16-bit residuals
     const VT* val = nullptr;
+    const int32_t* base = nullptr;  // SL_D16: per slice and position, at off[c] / 256 + k
 };
 
 constexpr int SLICE_UNROLL = 8;   // entries of a row loaded ahead of their additions
+static_assert(64 % SLICE_UNROLL == 0, "the base broadcast covers whole unrolled steps");
 
 // One lane's row of slice c of a sliced copy (len entries, storage order): s (and the
 // Dot2 compensation cmp when COMP) accumulate exactly as in the staged path below.
 // Layout flags SLF of a sliced copy: SL_NT -- the slice's values and column entries are read
 // with non-temporal loads (a matrix larger than the Infinity Cache streams past it instead
-// of evicting the vectors); SL_D16 -- the column entries are 16-bit offsets col - row (every
-// offset of the matrix fits), two bytes per entry less than absolute 32-bit columns.
+// of evicting the vectors); SL_D16 -- entry k of row r in slice c stores the 16-bit residual
+// col - r - base[c][k], where base[c][k] is the smallest col - r at position k over the
+// slice's rows (every residual of the matrix fits in 16 bits): two bytes per entry less
+// than 32-bit columns.  On a stencil each position holds one or two neighbour offsets.
 constexpr int SL_NT = 1, SL_D16 = 2;
 
 template <class VT, class XT, class AT, bool COMP, int SLF = 0>
@@ -202,10 +207,19 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
     const int row = c * R + t;
     const VT* __restrict__ vp = sl.val + base + t;
     const int32_t* __restrict__ cp = sl.col + base + t;
-    const int16_t* __restrict__ dp = (const int16_t*)sl.col + base + t;
+    const uint16_t* __restrict__ dp = (const uint16_t*)sl.col + base + t;
+    const int32_t* __restrict__ bp = sl.base + base / R;
+    int bv = 0;   // D16: bases of positions 64j .. 64j + 63, lane l holding position 64j + l
     for (int k0 = 0; k0 < w; k0 += U) {
+        if constexpr (D16) {
+            if ((k0 & 63) == 0) {   // one coalesced load per 64 positions (U divides 64)
+                const int kk = k0 + (threadIdx.x & 63);
+                bv = kk < w ? bp[kk] : 0;
+            }
+        }
         VT av[U];
         int32_t cv[U];
+        // all loads of the step are issued before any of them is used
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             av[u] = VT(0);
@@ -214,14 +228,19 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
                 const int64_t o = (int64_t)(k0 + u) * R;
                 if constexpr (MNT) {
                     av[u] = __builtin_nontemporal_load(vp + o);
-                    if constexpr (D16) cv[u] = row + (int)__builtin_nontemporal_load(dp + o);
+                    if constexpr (D16) cv[u] = __builtin_nontemporal_load(dp + o);
                     else cv[u] = __builtin_nontemporal_load(cp + o);
                 } else {
                     av[u] = vp[o];
-                    if constexpr (D16) cv[u] = row + (int)dp[o];
+                    if constexpr (D16) cv[u] = dp[o];
                     else cv[u] = cp[o];
                 }
             }
+        }
+        if constexpr (D16) {   // residual -> column
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k0 + u < w) cv[u] += row + __builtin_amdgcn_readlane(bv, (k0 + u) & 63);
         }
         XT xv[U];
 #pragma unroll
@@ -381,32 +400,22 @@ spmv_seq_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict
                                                                    (int)gridDim.x - bfirst, (AT*)smem, body, sl);
 }
 
-// Sliced copy, step 0: clear the largest-offset slot (off[nslice + 1]).
+// Sliced copy, step 0: clear the residual-overflow flag (off[nslice + 1]).
 __global__ void slice_clear_kernel(int64_t* __restrict__ slot) { *slot = 0; }
 
-// Step 1: off[c + 1] = 256 * (longest row of slice c), off[0] = 0; maxd = max |col - row|.
+// Step 1: off[c + 1] = 256 * (longest row of slice c), off[0] = 0.
 __global__ void __launch_bounds__(256) slice_width_kernel(int n, const int32_t* __restrict__ rp,
-                                                          const int32_t* __restrict__ ci,
-                                                          int64_t* __restrict__ off, int64_t* __restrict__ maxd) {
-    __shared__ int sh[4], shd[4];
+                                                          int64_t* __restrict__ off) {
+    __shared__ int sh[4];
     const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
-    int len = 0, d = 0;
-    if (row < n) {
-        const int a = rp[row], b = rp[row + 1];
-        len = b - a;
-        for (int k = a; k < b; ++k) d = max(d, abs(ci[k] - row));
-    }
+    int len = row < n ? rp[row + 1] - rp[row] : 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        len = max(len, __shfl_xor(len, o));
-        d = max(d, __shfl_xor(d, o));
-    }
-    if ((t & 63) == 0) { sh[t >> 6] = len; shd[t >> 6] = d; }
+    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o));
+    if ((t & 63) == 0) sh[t >> 6] = len;
     __syncthreads();
     if (t == 0) {
         off[c + 1] = 256LL * max(max(sh[0], sh[1]), max(sh[2], sh[3]));
         if (c == 0) off[0] = 0;
-        atomicMax((unsigned long long*)maxd, (unsigned long long)max(max(shd[0], shd[1]), max(shd[2], shd[3])));
     }
 }
 
@@ -433,23 +442,62 @@ __global__ void __launch_bounds__(1024) slice_scan_kernel(int ns, int64_t* __res
     }
 }
 
+// Step 2b (after the scan; only when the copy fits its cap): base[off[c] / 256 + k] = the
+// smallest col - row at position k over the rows of slice c that have one (0 if none);
+// sets *over when a residual would exceed 16 bits.
+__global__ void __launch_bounds__(256) slice_base_kernel(int n, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci,
+                                                         const int64_t* __restrict__ off, int64_t cap,
+                                                         int32_t* __restrict__ base,
+                                                         unsigned long long* __restrict__ over) {
+    __shared__ int smin[4], smax[4];
+    const int ns = gridDim.x;
+    if (off[ns] > cap) return;        // the copy is not built
+    const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
+    const int64_t b0 = off[c];
+    const int w = (int)((off[c + 1] - b0) / 256);
+    int a = 0, len = 0;
+    if (row < n) { a = rp[row]; len = rp[row + 1] - a; }
+    bool bad = false;
+    for (int k = 0; k < w; ++k) {
+        int lo = INT_MAX, hi = INT_MIN;
+        if (k < len) lo = hi = ci[a + k] - row;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o));
+            hi = max(hi, __shfl_xor(hi, o));
+        }
+        if ((t & 63) == 0) { smin[t >> 6] = lo; smax[t >> 6] = hi; }
+        __syncthreads();
+        lo = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
+        hi = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+        __syncthreads();
+        if (t == 0) base[b0 / 256 + k] = lo == INT_MAX ? 0 : lo;
+        if (lo != INT_MAX && (int64_t)hi - (int64_t)lo > 65535) bad = true;
+    }
+    if (t == 0 && bad) atomicOr(over, 1ull);
+}
+
 // Step 3: copy every row into its slice (lane t of block c: row 256c + t); D16: the column
-// entries as 16-bit offsets col - row (the caller checked that every offset fits).
+// entries as 16-bit residuals col - row - base[c][k] (the caller checked that all fit).
 template <class VT, bool D16>
 __global__ void __launch_bounds__(256) slice_fill_kernel(int n, const int32_t* __restrict__ rp,
                                                          const int32_t* __restrict__ ci, const VT* __restrict__ val,
-                                                         const int64_t* __restrict__ off, int32_t* __restrict__ scol,
-                                                         VT* __restrict__ sval) {
+                                                         const int64_t* __restrict__ off,
+                                                         const int32_t* __restrict__ sbase,
+                                                         int32_t* __restrict__ scol, VT* __restrict__ sval) {
     const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
     const int64_t base = off[c];
     const int w = (int)((off[c + 1] - base) / 256);
     int a = 0, len = 0;
     if (row < n) { a = rp[row]; len = rp[row + 1] - a; }
-    int16_t* dcol = (int16_t*)scol;
+    uint16_t* dcol = (uint16_t*)scol;
     for (int k = 0; k < w; ++k) {
         const int64_t i = base + (int64_t)k * 256 + t;
-        if constexpr (D16) dcol[i] = k < len ? (int16_t)(ci[a + k] - row) : (int16_t)0;
-        else scol[i] = k < len ? ci[a + k] : 0;
+        if constexpr (D16)
+            dcol[i] = k < len ? (uint16_t)(ci[a + k] - row - sbase[base / 256 + k]) : (uint16_t)0;
+        else
+            scol[i] = k < len ? ci[a + k] : 0;
         sval[i] = k < len ? val[a + k] : VT(0);
     }
 }

@@ -32,17 +32,28 @@ def expect_built(A):
     return padded_entries(A) <= A.nnz + A.nnz // 8 + 256
 
 
-def max_offset(A):
-    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr.astype(np.int64)))
-    return int(np.abs(A.col_idx.astype(np.int64) - rows).max()) if A.nnz else 0
+def max_spread(A):
+    """Largest spread of col - row over the rows of one 256-row slice at one entry position
+    (the solver's copy holds 16-bit residuals from each position's minimum when <= 65535)."""
+    lens = np.diff(A.row_ptr.astype(np.int64))
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), lens)
+    pos = np.arange(A.nnz, dtype=np.int64) - np.repeat(A.row_ptr[:-1].astype(np.int64), lens)
+    d = A.col_idx.astype(np.int64) - rows
+    key = (rows // 256) * (int(lens.max()) + 1 if A.nnz else 1) + pos
+    if not A.nnz:
+        return 0
+    order = np.argsort(key, kind="stable")
+    k, dv = key[order], d[order]
+    starts = np.concatenate([[0], np.nonzero(np.diff(k))[0] + 1])
+    return int((np.maximum.reduceat(dv, starts) - np.minimum.reduceat(dv, starts)).max())
 
 
 def expect_sliced_bits(A):
     """info['sliced'] of a solve with layout AUTO: bit 0 when A's sliced copy is built,
-    bit 2 when its columns are stored as 16-bit offsets (every |col - row| <= 32767)."""
+    bit 2 when its column entries are 16-bit residuals."""
     if not expect_built(A):
         return 0
-    return 1 | (4 if max_offset(A) <= 32767 else 0)
+    return 1 | (4 if max_spread(A) <= 65535 else 0)
 
 
 def with_long_range_entry(A, value):
@@ -159,11 +170,13 @@ def test_preconditioned_solve_slices_m():
 
 @pytest.mark.parametrize("prec", [pk.PREC_FP64, pk.PREC_FP32_IR])
 def test_solve_sliced_32bit_columns(prec):
-    """One entry at offset n - 1 > 32767 keeps the sliced copy's 32-bit columns; the solve
-    must still return the same bits as on CSR (and as the oracle in FP64)."""
-    p = g.problem("cd2d_64", scale=200)                    # n = 40,000
+    """One entry at offset n - 1 (spread above 65535 at its position) keeps the sliced
+    copy's 32-bit columns; the solve must still return the same bits as on CSR (and as
+    the oracle in FP64)."""
+    p = g.problem("cd2d_64", scale=300)                    # n = 90,000
     Ah = with_long_range_entry(p.A, -1e-3 * p.A.val[0])
-    assert max_offset(Ah) == Ah.n - 1 > 32767 and expect_built(Ah)
+    assert max_spread(Ah) > 65535 and expect_built(Ah)
+    assert max_spread(p.A) <= 65535 and expect_sliced_bits(p.A) == 5
     xs = np.random.default_rng(3).uniform(-1, 1, Ah.n)
     bh = spmv(Ah, xs)
     A = pk.CSR.from_host(Ah)
