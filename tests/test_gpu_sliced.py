@@ -190,3 +190,52 @@ def test_solve_sliced_32bit_columns(prec):
         ora = ctier.pbicgstab(Ah, bh, tol=1e-10, max_iter=60)
         assert ora["iterations"] == ia["iterations"]
         assert np.array_equal(xa.cpu().numpy().view(np.uint64), ora["x"].view(np.uint64))
+
+
+def dominant(A):
+    """A with every row's diagonal entry set (inserted if absent) to 1 + sum |off-diagonal|."""
+    rp, ci, va = [0], [], []
+    for i in range(A.n):
+        a, b = int(A.row_ptr[i]), int(A.row_ptr[i + 1])
+        cols, vals = list(A.col_idx[a:b]), list(A.val[a:b])
+        off = sum(abs(v) for c, v in zip(cols, vals) if c != i)
+        if i in cols:
+            vals[cols.index(i)] = 1.0 + off
+        else:
+            k = int(np.searchsorted(cols, i))
+            cols.insert(k, i)
+            vals.insert(k, 1.0 + off)
+        ci += cols
+        va += vals
+        rp.append(len(ci))
+    return g.CSR(A.n, np.array(rp, dtype=np.int32), np.array(ci, dtype=np.int32), np.array(va))
+
+
+def wide_rows():
+    """512 rows: the first slice 95..100 entries per row (more than 64 positions, so two
+    groups of per-position bases), the second 3..5; a ragged tail of empty rows."""
+    rng = np.random.default_rng(8)
+    lens = np.concatenate([rng.integers(95, 101, 256), rng.integers(3, 6, 200), np.zeros(56, dtype=np.int64)])
+    return ragged(512, lens, 6)
+
+
+@pytest.mark.parametrize("name", ["ragged_1000", "wide_rows"])
+def test_solve_ragged_16bit_residuals(name):
+    """Ragged slices, a ragged tail, empty rows and rows longer than 64 entries through the
+    solver's own sliced copy with 16-bit residuals: the same bits as on CSR and as the
+    oracle."""
+    A0 = wide_rows() if name == "wide_rows" else dict(cases())[name]
+    Ah = dominant(A0)
+    assert expect_sliced_bits(Ah) == 5, (name, max_spread(Ah), expect_built(Ah))
+    xs = np.random.default_rng(9).uniform(-1, 1, Ah.n)
+    bh = spmv(Ah, xs)
+    A = pk.CSR.from_host(Ah)
+    b = to_dev(bh)
+    xa, ia = pk.solve(A, b, tol=1e-10, max_iter=8)
+    xc, ic = pk.solve(A, b, tol=1e-10, max_iter=8, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == 5 and ic["sliced"] == 0
+    assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+    ora = ctier.pbicgstab(Ah, bh, tol=1e-10, max_iter=8)
+    assert ora["iterations"] == ia["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), ora["x"].view(np.uint64))
