@@ -242,9 +242,11 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
             for (int u = 0; u < U; ++u)
                 if (k0 + u < w) cv[u] += row + __builtin_amdgcn_readlane(bv, (k0 + u) & 63);
         }
+        // gathers without branches (an entry past the row end reads x[0] and is not added),
+        // so that all U gathers are in flight together
         XT xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (k0 + u < len) ? x[cv[u]] : XT(0);
+        for (int u = 0; u < U; ++u) xv[u] = x[(k0 + u < len) ? cv[u] : 0];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (k0 + u < len) {
@@ -329,13 +331,20 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
 #pragma unroll
                 for (int j = 0; j < PER; ++j) {
                     const int k = w + t + j * R;
+                    pv[j] = VT(0);
+                    pc[j] = 0;
                     if (k < we) { pv[j] = val[k]; pc[j] = ci[k]; }
                 }
+                // gathers without branches (a slot past the window reads x[0], unused), so
+                // that all PER gathers are in flight together
+                XT xg[PER];
+#pragma unroll
+                for (int j = 0; j < PER; ++j) xg[j] = x[pc[j]];
 #pragma unroll
                 for (int j = 0; j < PER; ++j) {
                     const int k = w + t + j * R;
                     if (k < we) {
-                        const AT a = (AT)pv[j], xv = (AT)x[pc[j]];
+                        const AT a = (AT)pv[j], xv = (AT)xg[j];
                         AT prod = a * xv;
                         if constexpr (COMP) {
                             float2* sp2 = (float2*)sprod;
