@@ -22,6 +22,8 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "state.hpp"
 #include "xdot.hpp"
 
@@ -652,6 +654,13 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
 // Plain FP32 dots: per-thread sequential sums in grid-stride order, xor-butterfly
 // within the wave, waves in index order; the per-block partials are summed in a fixed
 // tree by a finalize role (FFin; deterministic for a given launch shape).
+// An op with SPLIT provides ld(i, in[NIN]) and st(i, in, xa, ya): the kernel then issues
+// the loads of two elements before computing either (more loads in flight per lane).
+template <class Op, class = void>
+struct fsplit : std::false_type {};
+template <class Op>
+struct fsplit<Op, std::void_t<decltype(Op::SPLIT)>> : std::bool_constant<Op::SPLIT> {};
+
 template <class T, int D, class Op>
 __global__ void __launch_bounds__(1024)
 ew_fdot_kernel(Op op, int64_t n, TSite<T> site, const int* halt, int* seen) {
@@ -665,13 +674,48 @@ ew_fdot_kernel(Op op, int64_t n, TSite<T> site, const int* halt, int* seen) {
 #pragma unroll
     for (int d = 0; d < D; ++d) a[d] = T(0);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        T xa[D], ya[D];
-        op.elem(i, xa, ya);
+    if constexpr (fsplit<Op>::value) {
+        // elements i and i + stride per trip, accumulated in that order (the same sums as
+        // one element per trip)
+        int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        for (; i + stride < n; i += 2 * stride) {
+            T ia[Op::NIN], ib[Op::NIN];
+            op.ld(i, ia);
+            op.ld(i + stride, ib);
+            T xa[D], ya[D];
+            op.st(i, ia, xa, ya);
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            T p = xa[d] * ya[d];
-            a[d] = a[d] + p;
+            for (int d = 0; d < D; ++d) {
+                T p = xa[d] * ya[d];
+                a[d] = a[d] + p;
+            }
+            op.st(i + stride, ib, xa, ya);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                T p = xa[d] * ya[d];
+                a[d] = a[d] + p;
+            }
+        }
+        if (i < n) {
+            T ia[Op::NIN];
+            op.ld(i, ia);
+            T xa[D], ya[D];
+            op.st(i, ia, xa, ya);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                T p = xa[d] * ya[d];
+                a[d] = a[d] + p;
+            }
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            T xa[D], ya[D];
+            op.elem(i, xa, ya);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                T p = xa[d] * ya[d];
+                a[d] = a[d] + p;
+            }
         }
     }
     const int wid = threadIdx.x / xd::WAVE, nw = blockDim.x / xd::WAVE;
@@ -1072,14 +1116,22 @@ struct FPhaseA {
     float* p; float* s; float* z; float* q; float* y;
     const float* scal; int first; Fin fin;
     float alpha, beta, omega;
+    static constexpr bool SPLIT = true;
+    static constexpr int NIN = 8;
     __device__ __forceinline__ void load() { alpha = scal[0]; beta = scal[1]; omega = scal[2]; }
-    __device__ __forceinline__ void elem(int64_t i, float (&xa)[4], float (&ya)[4]) {
-        const float ri = get<NT>(r, i), wi = get<NT>(w, i), ti = get<NT>(t, i);
+    __device__ __forceinline__ void ld(int64_t i, float (&in)[NIN]) const {
+        in[0] = get<NT>(r, i); in[1] = get<NT>(w, i); in[2] = get<NT>(t, i); in[3] = get<NT>(rhat, i);
+        if (!first) {
+            in[4] = get<NT, float>(p, i); in[5] = get<NT, float>(s, i);
+            in[6] = get<NT, float>(z, i); in[7] = get<NT>(v, i);
+        }
+    }
+    __device__ __forceinline__ void st(int64_t i, const float (&in)[NIN], float (&xa)[4], float (&ya)[4]) {
+        const float ri = in[0], wi = in[1], ti = in[2];
         float pi, si, zi;
         if (first) { pi = ri; si = wi; zi = ti; }
         else {
-            const float pp = get<NT, float>(p, i), sp = get<NT, float>(s, i), zp = get<NT, float>(z, i),
-                        vp = get<NT>(v, i);
+            const float pp = in[4], sp = in[5], zp = in[6], vp = in[7];
             pi = ri + beta * (pp - omega * sp);
             si = wi + beta * (sp - omega * zp);
             zi = ti + beta * (zp - omega * vp);
@@ -1087,7 +1139,7 @@ struct FPhaseA {
         const float qi = ri - alpha * si;
         const float yi = wi - alpha * zi;
         put<NT>(p, i, pi); put<NT>(s, i, si); put<false>(z, i, zi); put<NT>(q, i, qi); put<NT>(y, i, yi);
-        const float rh = get<NT>(rhat, i);
+        const float rh = in[3];
         xa[0] = qi; ya[0] = yi;
         xa[1] = yi; ya[1] = yi;
         xa[2] = rh; ya[2] = si;
@@ -1101,14 +1153,20 @@ struct FPhaseB {
     float* x; const float* p; const float* q; const float* y; const float* t; const float* v;
     const float* rhat; float* r; float* w; const float* scal; Fin fin;
     float alpha, omega;
+    static constexpr bool SPLIT = true;
+    static constexpr int NIN = 7;
     __device__ __forceinline__ void load() { alpha = scal[0]; omega = scal[2]; }
-    __device__ __forceinline__ void elem(int64_t i, float (&xa)[3], float (&ya)[3]) {
-        const float qi = get<NT>(q, i), yi = get<NT>(y, i);
-        const float xi = (get<NT, float>(x, i) + alpha * get<NT>(p, i)) + omega * qi;
+    __device__ __forceinline__ void ld(int64_t i, float (&in)[NIN]) const {
+        in[0] = get<NT>(q, i); in[1] = get<NT>(y, i); in[2] = get<NT, float>(x, i); in[3] = get<NT>(p, i);
+        in[4] = get<NT>(t, i); in[5] = get<NT>(v, i); in[6] = get<NT>(rhat, i);
+    }
+    __device__ __forceinline__ void st(int64_t i, const float (&in)[NIN], float (&xa)[3], float (&ya)[3]) {
+        const float qi = in[0], yi = in[1];
+        const float xi = (in[2] + alpha * in[3]) + omega * qi;
         const float ri = qi - omega * yi;
-        const float wi = yi - omega * (get<NT>(t, i) - alpha * get<NT>(v, i));
+        const float wi = yi - omega * (in[4] - alpha * in[5]);
         put<NT>(x, i, xi); put<NT>(r, i, ri); put<false>(w, i, wi);
-        const float rh = get<NT>(rhat, i);
+        const float rh = in[6];
         xa[0] = rh; ya[0] = ri;
         xa[1] = rh; ya[1] = wi;
         xa[2] = ri; ya[2] = ri;
