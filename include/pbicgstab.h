@@ -230,6 +230,26 @@ int exdot_config(int64_t n, const double* x, const double* y, double* out,
                  void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------
+ * Allocation-free exact dot/* ---------------------------------------------------------------------------------
+ * Allocation-free exact dot, for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same result as exdot, bit for bit, with the same kernels; the per-block
+ * records live in a static device array of exdot_noalloc_scratch_bytes() bytes (about
+ * 0.55 MB), one copy per GPU, held until the process ends.  The array's device address
+ * is looked up once per device on the first call there, which must run with the
+ * stream's device current (PBCG_ERR_INVALID otherwise).  No call allocates or frees
+ * memory.  n <= EXDOT_NOALLOC_MAX_N (2^34, beyond any vector pair that fits the GPU);
+ * a larger n returns PBCG_ERR_INVALID before anything is launched.  Every call on one
+ * GPU uses the same array: calls that overlap in time on that GPU (different streams,
+ * threads or processes sharing the device) race and may return wrong results --
+ * serialise them.  Nothing in the array needs to start at zero (each launched block
+ * rewrites its whole record before it is read).
+ */
+#define EXDOT_NOALLOC_MAX_N ((int64_t)1 << 34)
+size_t exdot_noalloc_scratch_bytes(void);
+int exdot_noalloc(int64_t n, const double* x, const double* y, double* out, void* stream);
+
+/* ---------------------------------------------------------------------------------
  * One fused pass of p-BiCGStab (paper Algorithm 2).  `scal` is a device array
  * {alpha, beta, omega}.
  * Phase A: p = r + beta (p - omega s); s = w + beta (s - omega z); z = t + beta (z - omega v)

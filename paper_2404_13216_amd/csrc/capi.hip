@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/pbicgstab.h"
 #include "kernels.hpp"
@@ -638,6 +639,70 @@ int exdot_config(int64_t n, const double* x, const double* y, double* out, int32
     op.a[0] = x; op.b[0] = y;
     op.fin = FinStore{out, 1};
     launch_ew_dot<1>(op, n, site, nullptr, s, grid, block, k);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free exact dot
+// The records of exdot_noalloc live in a file-scope device array (one copy per GPU, held
+// until the process ends).  Host code never passes `scratch` itself to a kernel: its name
+// is a host-side stand-in; the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current.
+namespace {
+constexpr int NOALLOC_GRID = 512;    // the largest grid exdot launches
+constexpr size_t NOALLOC_HDR = (size_t)NOALLOC_GRID * sizeof(xd::RecHdr);
+constexpr size_t NOALLOC_BYTES = NOALLOC_HDR + (size_t)NOALLOC_GRID * xd::NCH * sizeof(long long);
+static_assert(NOALLOC_HDR % 256 == 0, "chunk records start 256-byte aligned");
+constexpr int NOALLOC_MAX_DEV = 64;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+int scratch_address(hipStream_t s, void** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (s) {
+        int sdev = -1;
+        HIPCHK(hipStreamGetDevice(s, &sdev));
+        if (sdev != dev) return PBCG_ERR_INVALID;   // the stream's device must be current
+    }
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) return PBCG_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return PBCG_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PBCG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t exdot_noalloc_scratch_bytes(void) { return NOALLOC_BYTES; }
+
+int exdot_noalloc(int64_t n, const double* x, const double* y, double* out, void* stream) {
+    if (n < 0 || !out || (n > 0 && (!x || !y))) return PBCG_ERR_INVALID;
+    if (n > EXDOT_NOALLOC_MAX_N) return PBCG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    void* base = nullptr;
+    const int rc = scratch_address(s, &base);
+    if (rc != PBCG_OK) return rc;
+    const int64_t per = (int64_t)DOT_BLOCK * 8;
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, NOALLOC_GRID));
+    // every launched block writes its whole record before the finalize reads it, so
+    // nothing in the scratch array has to start at zero
+    xd::Site site;
+    site.hdr = (xd::RecHdr*)base;
+    site.dig = (long long*)((char*)base + NOALLOC_HDR);
+    DotsOp<1, FinStore> op{};
+    op.a[0] = x; op.b[0] = y;
+    op.fin = FinStore{out, 1};
+    launch_ew_dot<1>(op, n, site, nullptr, s, g, DOT_BLOCK, KEXP);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
