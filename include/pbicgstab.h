@@ -230,6 +230,22 @@ int exdot_config(int64_t n, const double* x, const double* y, double* out,
                  void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------
+ * Plain (not exact) dot product: the inner products of the FP32 solver inside the
+ * refinement (dtype PBCG_F32: FP32 products and sums) and of the ordinary-dot
+ * comparator (PBCG_F64).  Each product is rounded to dtype and the sum is formed in a
+ * fixed reduction tree: per-lane sums over a grid-stride loop, a butterfly within each
+ * 64-lane wavefront, the block's wavefronts in index order, then a 256-wide tree over the
+ * block partials.  The order depends on n only (not on the stream or timing), so the
+ * result is reproducible run to run; it is not the sequential order, and its error
+ * obeys the classical bound |dot - sum x_i y_i| <= gamma_n sum |x_i y_i|,
+ * gamma_n = n u / (1 - n u).  x, y: n device values of dtype; out: one device value of
+ * dtype.  Workspace: plain_dot_workspace_bytes(n).
+ */
+size_t plain_dot_workspace_bytes(int64_t n);
+int plain_dot(int64_t n, const void* x, const void* y, int32_t dtype, void* out,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
  * Allocation-free exact dot/* ---------------------------------------------------------------------------------
  * Allocation-free exact dot, for callers that cannot allocate device memory or pass a
  * workspace (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -136,7 +136,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     starting from y_0 = 0, and x = M y; ``x0`` must then be None.
     ``record`` keeps (x_i, r_i, alpha, omega) for the first ``record`` iterations.
     ``dot`` forms the inner products of the recurrences; ``exact_dot`` (default: the
-    same) forms ||b||, the true residual and the (q, q) test -- with dot = dot_f64_tree
+    same) forms ||b||, the true residual and the (q, q) test -- with dot = dot_f64_seq
     and the exact dot there, this is the ordinary-dot comparator.
     ``rr_period`` > 0: residual replacement (the p-BiCGStabRR variant the paper refers
     to) after every rr_period-th completed iteration: r = b - A x, w = A r, t = A w,
@@ -360,71 +360,23 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
 # FP32 inner p-BiCGStab inside FP64 iterative refinement
 # ---------------------------------------------------------------------------
 
-FDOT_BLOCK = 512   # lanes per group of the FP32 dot's reduction tree
-
-
-def fdot_grid(n: int) -> int:
-    """Groups in the FP32 dot's reduction tree: one per 512 x 8 elements, 1 to 256."""
-    g = -(-int(n) // (FDOT_BLOCK * 8))
-    return max(1, min(g, 256))
-
-
 def dot_f32_seq(a: np.ndarray, b: np.ndarray) -> np.float32:
-    """Plain float32 dot, sequential left-to-right accumulation (ufunc.accumulate is a
-    strictly sequential scan: s_k = s_{k-1} + p_k, each rounded to float32)."""
-    prod = (a.astype(np.float32) * b.astype(np.float32)).astype(np.float32)
+    """Plain float32 dot by its definition: every product a_i b_i rounded to float32 and
+    added left to right, s_k = fl32(s_(k-1) + p_k) from s_0 = 0 (ufunc.accumulate is a
+    strictly sequential scan) -- the inner products of the FP32 solver."""
+    prod = (np.asarray(a).astype(np.float32) * np.asarray(b).astype(np.float32)).astype(np.float32)
     if prod.size == 0:
         return np.float32(0.0)
     return np.float32(np.add.accumulate(prod, dtype=np.float32)[-1])
 
 
-def dot_f64_tree(a: np.ndarray, b: np.ndarray) -> float:
-    """Ordinary FP64 dot (products and sums rounded to double) in the same fixed
-    reduction tree as ``dot_f32_tree`` -- the non-exact comparator of the paper's
-    claim about exact inner products."""
-    return float(_tree_dot(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64), np.float64))
-
-
-def dot_f32_tree(a: np.ndarray, b: np.ndarray) -> np.float32:
-    """Plain float32 dot in a fixed reduction tree -- the dot of the FP32 inner solver.
-    Every product and every addition is rounded to float32; the order is fixed by n
-    alone.  With G = fdot_grid(n) groups of 512 lanes (8 waves of 64), S = 512 G:
-
-      1. lane g (0 <= g < S) adds, starting from 0, the products a_i b_i for
-         i = g, g + S, g + 2S, ... in that order;
-      2. in every wave of 64 lanes, six butterfly levels u_j <- u_j + u_(j xor o),
-         o = 32, 16, 8, 4, 2, 1; the wave's value is lane 0's;
-      3. a group's 8 wave values are added, starting from 0, in wave order;
-      4. the G group values v_g (zero-padded to 256) become h_j = 0 + v_j and are
-         folded h_j <- h_j + h_(j+w) for w = 128, 64, ..., 1; the dot is h_0.
-    """
-    return _tree_dot(np.asarray(a, dtype=np.float32), np.asarray(b, dtype=np.float32), np.float32)
-
-
-def _tree_dot(a, b, f):
-    """The fixed tree of ``dot_f32_tree`` in the arithmetic of type f."""
-    n = a.size
-    G = fdot_grid(n)
-    S = G * FDOT_BLOCK
-    lane = np.zeros(S, dtype=f)
-    for k0 in range(0, n, S):
-        m = min(S, n - k0)
-        lane[:m] = lane[:m] + a[k0:k0 + m] * b[k0:k0 + m]
-    u = lane.reshape(G * 8, 64)
-    j = np.arange(64)
-    for o in (32, 16, 8, 4, 2, 1):
-        u = u + u[:, j ^ o]
-    wv = u[:, 0].reshape(G, 8)
-    gs = np.zeros(G, dtype=f)
-    for w in range(8):
-        gs = gs + wv[:, w]
-    h = np.zeros(256, dtype=f)
-    h[:G] = f(0.0) + gs
-    w = 128
-    while w:
-        h[:w] = h[:w] + h[w:2 * w]
-        w //= 2
-    return f(h[0])
+def dot_f64_seq(a: np.ndarray, b: np.ndarray) -> float:
+    """Ordinary FP64 dot by its definition: products rounded to double, added left to
+    right -- the non-exact comparator of the paper's claim about exact inner products."""
+    prod = np.asarray(a, dtype=np.float64) * np.asarray(b, dtype=np.float64)
+    if prod.size == 0:
+        return 0.0
+    return float(np.add.accumulate(prod)[-1])
 
 
 # reasons that end a run of FP32 iterations (bit flags)
@@ -457,8 +409,8 @@ def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=N
     """FP64 iterative refinement around an FP32 p-BiCGStab with reliable updates.
 
     FP32 part: Algorithm 2 with FP32 matrix values, vectors and scalars, the
-    compensated row-sequential FP32 SpMV (``oracle.spmv.spmv_f32``) and the FP32 tree
-    dot (``dot_f32_tree``); it accumulates a correction d (x0 = 0) to the FP64 iterate.
+    compensated row-sequential FP32 SpMV (``oracle.spmv.spmv_f32``) and the plain
+    sequential FP32 dot (``dot_f32_seq``); it accumulates a correction d (x0 = 0) to the FP64 iterate.
     FP64 part, a "reliable update" each time the FP32 iterations stop: x = x + nu d,
     r = b - A x (row-sequential FP64 SpMV), nu' = sqrt(exdot(r, r)); converged when
     nu' / ||b|| <= tol.  Otherwise the FP32 state is rebuilt from r / nu' and the same
@@ -485,7 +437,7 @@ def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=N
     from synthgen import CSR
     f = np.float32
     spmv = spmv or _spmv
-    dot32 = dot_f32_tree
+    dot32 = dot_f32_seq
     n = A.n
     dot = dot or default_dot(n)
     b = np.asarray(b, dtype=np.float64)

@@ -71,7 +71,7 @@ class PbcgVectors(ctypes.Structure):
 EXPORTS = [
     "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "csr_jacobi", "csr_slice_workspace_bytes", "csr_slice",
     "csr_spmv_sliced", "csr_spmv_f32_sliced", "exdot_workspace_bytes", "exdot", "exdot_config",
-    "exdot_noalloc_scratch_bytes", "exdot_noalloc",
+    "exdot_noalloc_scratch_bytes", "exdot_noalloc", "plain_dot_workspace_bytes", "plain_dot",
     "pbcg_phase_workspace_bytes", "pbcg_phase_a", "pbcg_phase_b", "pbicgstab_workspace_bytes",
     "pbicgstab_solve", "pbcg_default_opts", "pbcg_status_string", "pbcg_abi_version",
     "spai_param_count", "spai_workspace_bytes", "spai_features", "spai_forward", "spai_infer_bf16",
@@ -105,6 +105,8 @@ def lib():
         "exdot_config": (ctypes.c_int, [i64, _P, _P, _P, i32, i32, i32, _P, sz, _P]),
         "exdot_noalloc_scratch_bytes": (sz, []),
         "exdot_noalloc": (ctypes.c_int, [i64, _P, _P, _P, _P]),
+        "plain_dot_workspace_bytes": (sz, [i64]),
+        "plain_dot": (ctypes.c_int, [i64, _P, _P, i32, _P, _P, sz, _P]),
         "pbcg_phase_workspace_bytes": (sz, [i32]),
         "pbcg_phase_a": (ctypes.c_int, [i32, ctypes.POINTER(PbcgVectors), _P, i32, _P, _P, sz, _P]),
         "pbcg_phase_b": (ctypes.c_int, [i32, ctypes.POINTER(PbcgVectors), _P, _P, _P, sz, _P]),
@@ -313,6 +315,19 @@ def exdot_noalloc(x, y, out):
     """exdot without a workspace: the library's static scratch array holds the records.
     `out` is a caller-owned one-element float64 device tensor (nothing is allocated)."""
     _check(lib().exdot_noalloc(x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream()), "exdot_noalloc")
+    return out
+
+
+def plain_dot(x, y, out=None, ws=None):
+    """Plain dot in the library's fixed reduction tree (float32 or float64 vectors)."""
+    torch = _torch()
+    n = x.numel()
+    if out is None:
+        out = torch.empty(1, dtype=x.dtype, device=x.device)
+    if ws is None:
+        ws = _workspace(lib().plain_dot_workspace_bytes(n), x.device)
+    dt = F64 if x.dtype == torch.float64 else F32
+    _check(lib().plain_dot(n, _ptr(x), _ptr(y), dt, _ptr(out), _ptr(ws), ws.numel(), _stream()), "plain_dot")
     return out
 
 

@@ -463,7 +463,14 @@ struct Pinned {
     FState* f = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool ready = false;
-    ~Pinned() {}
+    // Thread-storage objects of a thread are destroyed before any static object (the HIP
+    // runtime's included), so the release below runs while the runtime is still up.
+    ~Pinned() {
+        if (!ready) return;
+        for (int i = 0; i < 2; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        (void)hipHostFree(s);
+    }
 };
 thread_local Pinned g_pin;
 
@@ -714,6 +721,35 @@ int exdot(int64_t n, const double* x, const double* y, double* out, void* ws, si
     const int64_t per = (int64_t)DOT_BLOCK * 8;
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 512));
     return exdot_config(n, x, y, out, g, DOT_BLOCK, KEXP, ws, ws_bytes, stream);
+}
+
+size_t plain_dot_workspace_bytes(int64_t n) {
+    (void)n;
+    return align_up((size_t)DOT_GRID_MAX * 4 * sizeof(double), 256) + 256;
+}
+
+int plain_dot(int64_t n, const void* x, const void* y, int32_t dtype, void* out, void* ws, size_t ws_bytes,
+              void* stream) {
+    if (n < 0 || !out || (n > 0 && (!x || !y))) return PBCG_ERR_INVALID;
+    if (dtype != PBCG_F64 && dtype != PBCG_F32) return PBCG_ERR_INVALID;
+    if (!ws || ws_bytes < plain_dot_workspace_bytes(n) || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    if (dtype == PBCG_F64) {
+        TSite<double> site{c.take<double>((size_t)DOT_GRID_MAX * 4)};
+        DotsOp<1, FinStore> op{};
+        op.a[0] = (const double*)x; op.b[0] = (const double*)y;
+        op.fin = FinStore{(double*)out, 1};
+        launch_ew_fdot<1>(ElemOf<DotsOp<1, FinStore>>{op}, n, site, nullptr, s);
+    } else {
+        FSite site{c.take<float>((size_t)DOT_GRID_MAX * 4)};
+        FDotsOp<1, FinStoreF> op{};
+        op.a[0] = (const float*)x; op.b[0] = (const float*)y;
+        op.fin = FinStoreF{(float*)out};
+        launch_ew_fdot<1>(op, n, site, nullptr, s);
+    }
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
 }
 
 size_t pbcg_phase_workspace_bytes(int32_t n) {

@@ -877,6 +877,11 @@ struct FinStore {            // write the D results to out[]
     }
 };
 
+struct FinStoreF {           // one FP32 result to out[0]
+    float* out;
+    __device__ void operator()(const float* d) const { out[0] = d[0]; }
+};
+
 __device__ __forceinline__ bool fin3(double a, double b, double c) { return isfinite(a) && isfinite(b) && isfinite(c); }
 
 // ||b||^2 -> normb

@@ -1,11 +1,21 @@
-"""FP32 refinement with reliable updates on the GPU vs the oracle.
+"""FP32 refinement with reliable updates on the GPU, judged by outcome.
 
-Every piece of the GPU solve has a bit-exact counterpart in the oracle: the FP64
-row-sequential SpMV and exact dots of the reliable updates, the compensated FP32 SpMV,
-the FP32 dots in their fixed reduction tree, and the FP32 recurrences and scalars in the
-same order with separate roundings.  The solves are therefore compared bit for bit:
-same iterate, same FP32 iteration count, same number of reliable updates.  The error of
-the refined solution against the FP64 oracle's is reported per case.
+The refinement's FP32 inner products are plain FP32 sums in the library's fixed
+reduction tree, while the oracle's plain FP32 dot is the sequential sum of its
+definition, so the FP32 iterates differ by rounding and the two solves are not compared
+bit for bit.  Each GPU solve is judged instead by what it reaches (tests/outcome.py):
+
+* status OK, and the true relative residual of the returned x recomputed by the oracle
+  (row-sequential FP64 SpMV, exact dots) is <= 1e-10 and equals the one the library
+  reports bit for bit (its reliable updates use the same SpMV order and exact dots);
+* ||x - x_ref||_inf stays within the certified perturbation bound
+  ||A^-1||_inf (||r||_inf + ||r_ref||_inf) of the FP64 oracle's solution x_ref;
+* the same bound holds against the generator's exact solution x* (b = A x* rounded).
+
+The errors against x_ref and x* are printed per case.  At the full sizes of the random
+10^6 and 256^3 workloads the FP64 reference is the solve the bench compares against:
+BiCGStab from the C oracle on the random matrix (plain p-BiCGStab stagnates there at
+2.5e-10), and x* on 256^3, where the CPU oracle would need minutes.
 """
 import numpy as np
 import pytest
@@ -15,43 +25,83 @@ import paper_2404_13216_amd as pk
 import synthgen as g
 from oracle import ctier, solvers
 from oracle.spmv import spmv_f32
+from tests import outcome as oc
 from tests.gpu_util import to_dev
 
 pytestmark = pytest.mark.gpu
 
 
+def _check(p, x, info, xref, K, tag, capsys, tol=1e-10):
+    true = oc.true_relres(p.A, p.b, x)
+    gap = float(np.abs(x - xref).max())
+    bound = oc.solution_gap_bound(p.A, p.b, x, xref, K)
+    gap_star = float(np.abs(x - p.xstar).max())
+    bound_star = oc.solution_gap_bound(p.A, p.b, x, p.xstar, K)
+    with capsys.disabled():
+        print(f"\n  {tag}: updates {info['outer_iterations']} FP32 iterations {info['iterations']} fell back "
+              f"{info['fell_back']} true {true:.2e} |x - x_ref|_inf {gap:.2e} (bound {bound:.2e}) "
+              f"|x - x*|_inf {gap_star:.2e} (bound {bound_star:.2e})")
+    assert info["status"] == pk.OK, info
+    assert true <= tol
+    assert true == info["true_relres"]
+    assert gap <= bound
+    assert gap_star <= bound_star
+
+
 @pytest.mark.parametrize("name,scale", [("cd2d_64", 20), ("cd2d_64", None), ("cd3d_128", 24),
                                         ("cd3d_256_var", 20), ("rand_1m", 8000), ("spai_eval_128", 16)])
-def test_ir_bitwise(name, scale, capsys):
+def test_ir_outcome(name, scale, capsys):
     p = g.problem(name, scale=scale)
-    ora = solvers.ir_solve(p.A, p.b, tol=1e-10, max_iter=5000)
     x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), tol=1e-10, prec=pk.PREC_FP32_IR, max_iter=5000)
     torch.cuda.synchronize()
-    x = x.cpu().numpy()
     ref = ctier.pbicgstab(p.A, p.b, tol=1e-10, max_iter=20000)
-    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
-    with capsys.disabled():
-        print(f"\n  {name}/{scale}: updates {info['outer_iterations']} FP32 iterations {info['iterations']} "
-              f"(FP64 solve {ref['iterations']}) fell back {info['fell_back']} true {info['true_relres']:.2e} "
-              f"err vs FP64 oracle {err:.2e}")
-    assert ora.status == solvers.OK and info["status"] == pk.OK
-    assert info["true_relres"] <= 1e-10
-    assert info["iterations"] == ora.iterations
-    assert info["outer_iterations"] == ora.outer_iterations
-    assert info["fell_back"] == ora.fell_back
-    assert np.array_equal(x.view(np.uint64), ora.x.view(np.uint64))
+    assert ref["status"] == 0
+    _check(p, x.cpu().numpy(), info, ref["x"], oc.inv_norm_inf_bound(p.A), f"{name}/{scale}", capsys)
 
 
-def test_ir_finish_path_bitwise():
+def test_ir_reproducible():
+    """The fixed reduction tree makes the refinement reproducible run to run."""
+    p = g.problem("rand_1m", scale=8000)
+    A, b = pk.CSR.from_host(p.A), to_dev(p.b)
+    x1, i1 = pk.solve(A, b, tol=1e-10, prec=pk.PREC_FP32_IR)
+    x2, i2 = pk.solve(A, b, tol=1e-10, prec=pk.PREC_FP32_IR)
+    assert i1["iterations"] == i2["iterations"]
+    assert torch.equal(x1.view(torch.int64), x2.view(torch.int64))
+
+
+def test_ir_finish_path(capsys):
     """max_outer = 1: one reliable update, then the FP64 finish from the best iterate."""
     p = g.problem("cd3d_256_var", scale=16)
-    ora = solvers.ir_solve(p.A, p.b, tol=1e-10, max_iter=5000, max_outer=1)
     x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), tol=1e-10, prec=pk.PREC_FP32_IR, max_iter=5000,
                        max_outer=1)
-    assert ora.fell_back == 1 and info["fell_back"] == 1
-    assert info["status"] == ora.status == pk.OK
-    assert info["iterations"] == ora.iterations
-    assert np.array_equal(x.cpu().numpy().view(np.uint64), ora.x.view(np.uint64))
+    ora = solvers.ir_solve(p.A, p.b, tol=1e-10, max_iter=5000, max_outer=1)
+    assert ora.fell_back == 1 and info["fell_back"] == 1 and ora.status == solvers.OK
+    _check(p, x.cpu().numpy(), info, ora.x, oc.inv_norm_inf_bound(p.A), "256var/16 finish", capsys)
+
+
+def test_ir_full_rand_1m(capsys):
+    p = g.problem("rand_1m")
+    x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), tol=1e-10, prec=pk.PREC_FP32_IR)
+    torch.cuda.synchronize()
+    ref = ctier.bicgstab(p.A, p.b, tol=1e-10, max_iter=5000)
+    assert ref["status"] == 0
+    _check(p, x.cpu().numpy(), info, ref["x"], oc.inv_norm_inf_bound(p.A), "rand_1m full", capsys)
+
+
+@pytest.mark.parametrize("inner_tol", [None, 1e-5])
+def test_ir_full_256(inner_tol, capsys):
+    p = g.problem("cd3d_256_var")
+    A = pk.CSR.from_host(p.A)
+    kw = {} if inner_tol is None else {"inner_tol": inner_tol}
+    x, info = pk.solve(A, to_dev(p.b), tol=1e-10, prec=pk.PREC_FP32_IR, **kw)
+    # certificate candidate for ||A^-1||_inf: v ~ A^-1 1 from the library's BiCGStab (only
+    # the inequality A v >= c > 0, checked by the oracle, is trusted; plain p-BiCGStab
+    # diverges on this right-hand side)
+    v, vinfo = pk.solve(A, torch.ones(p.A.n, dtype=torch.float64, device="cuda:0"), tol=1e-10,
+                        alg=pk.ALG_BICGSTAB)
+    torch.cuda.synchronize()
+    K = oc.inv_norm_inf_bound(p.A, v.cpu().numpy())
+    _check(p, x.cpu().numpy(), info, p.xstar, K, f"256^3 full inner_tol {inner_tol}", capsys)
 
 
 def test_csr_spmv_f32_dot2_bitwise():

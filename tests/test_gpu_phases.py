@@ -68,12 +68,22 @@ def test_phase_b(n):
 
 
 def test_phase_a_full_size():
+    """2^24 rows (the 256^3 workload's vector length): updated vectors bit for bit against
+    the literal-order recurrences, dots against the oracle's exact dots of those vectors."""
     n = 1 << 24
     V = rand_vecs(n, 7)
+    alpha, beta, omega = 0.5, 0.25, -2.0
+    s = V["w"] + beta * (V["s"] - omega * V["z"])
+    z = V["t"] + beta * (V["z"] - omega * V["v"])
+    q = V["r"] - alpha * s
+    y = V["w"] - alpha * z
     TV = {k: to_dev(a) for k, a in V.items()}
-    scal = to_dev(np.array([0.5, 0.25, -2.0]))
+    scal = to_dev(np.array([alpha, beta, omega]))
     dots = pk.pbcg_phase_a(TV, scal, False).cpu().numpy()
-    q = TV["q"].cpu().numpy()
-    y = TV["y"].cpu().numpy()
-    assert same_bits(dots[0], ctier.exact_dot(q, y)) and same_bits(dots[1], ctier.exact_dot(y, y))
     torch.cuda.synchronize()
+    for name, ref in (("s", s), ("z", z), ("q", q), ("y", y)):
+        assert np.array_equal(TV[name].cpu().numpy().view(np.uint64), ref.view(np.uint64)), name
+    expect = [ctier.exact_dot(q, y), ctier.exact_dot(y, y), ctier.exact_dot(V["rhat"], s),
+              ctier.exact_dot(V["rhat"], z)]
+    for a, b in zip(dots, expect):
+        assert same_bits(a, b)

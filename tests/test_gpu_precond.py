@@ -91,3 +91,41 @@ def test_no_fallback_returns_breakdown():
     M = diag_csr(np.zeros(p.A.n))
     x, info = run(p.A, p.b, M, tol=1e-10, fallback=0)
     assert info["status"] == pk.BREAKDOWN and info["fell_back"] == 0
+
+
+def _learned_m(p, seed=3):
+    """bf16-inferred M values of a network with a non-zero last layer (so M is not Jacobi)
+    on A's pattern, from the library's own features and inference kernels."""
+    from oracle import spai as ospai
+    from paper_2404_13216_amd import spai
+    th = ospai.init_params(seed)
+    th[4992:] = np.random.default_rng(seed + 1).standard_normal(65) * 0.05
+    sm = spai.SpaiMatrix(pk.CSR.from_host(p.A))
+    m = sm.m_bf16(torch.from_numpy(th.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    return g.CSR(p.A.n, p.A.row_ptr, p.A.col_idx, m.cpu().numpy().astype(np.float64)), m
+
+
+@pytest.mark.parametrize("scale", [12, 24])
+def test_learned_m_bit_identical(scale):
+    """The GPU's own learned M values, fed to the oracle: the preconditioned solves (M
+    applied by the row-sequential SpMV, then A) agree bit for bit."""
+    p = g.problem("spai_eval_128", scale=scale)
+    Mh, m = _learned_m(p)
+    ref = solvers.pbicgstab(p.A, p.b, tol=1e-10, M=Mh)
+    Md = pk.CSR.from_host(p.A).with_values(m)
+    x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), M=Md, tol=1e-10)
+    assert info["status"] == ref.status == pk.OK
+    assert info["iterations"] == ref.iterations
+    assert np.array_equal(bits(x.cpu().numpy()), bits(ref.x))
+
+
+def test_learned_m_full_size_twenty_iterations():
+    """Held-out 128^3 matrix at full size: 20 preconditioned iterations bit for bit."""
+    p = g.problem("spai_eval_128")
+    Mh, m = _learned_m(p)
+    ref = solvers.pbicgstab(p.A, p.b, tol=1e-10, M=Mh, max_iter=20)
+    Md = pk.CSR.from_host(p.A).with_values(m)
+    x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), M=Md, tol=1e-10, max_iter=20)
+    assert info["iterations"] == ref.iterations == 20
+    assert np.array_equal(bits(x.cpu().numpy()), bits(ref.x))

@@ -35,6 +35,19 @@ def test_features(mat):
     assert np.array_equal(sm.diag.cpu().numpy(), mat.A.diag())
 
 
+def test_features_hand_worked_unsymmetric():
+    """All twelve features on the hand-worked unsymmetric 4 x 4 matrix of the oracle's
+    pins (negative diagonal, a missing transpose entry), FP32 against the exact values."""
+    from tests.test_oracle_spai import HAND_A, HAND_PHI
+    rows = np.array([i for i, _, _ in HAND_A])
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=4))]).astype(np.int32)
+    A = g.CSR(4, rp, np.array([j for _, j, _ in HAND_A], dtype=np.int32), np.array([v for _, _, v in HAND_A]))
+    sm = spai.SpaiMatrix(pk.CSR.from_host(A))
+    got = sm.feat.view(-1, 12).cpu().numpy().astype(np.float64)
+    expect = np.array([[float(v) for v in row] for row in HAND_PHI])
+    assert np.all(np.abs(got - expect) <= 2.0 ** -21 * np.abs(expect)), np.argwhere(got != expect)
+
+
 def test_untrained_net_is_jacobi(mat):
     sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
     th = torch.from_numpy(ospai.init_params(0).astype(np.float32)).cuda()

@@ -1,8 +1,9 @@
 """Pins of the comparators for the paper's central claim: p-BiCGStab with ordinary
-FP64 dots (a fixed reduction tree) and p-BiCGStab with residual replacement.
+FP64 dots and p-BiCGStab with residual replacement.
 
-* The FP64 tree dot is exact on small integers, obeys the gamma_n bound, and its
-  association order is pinned by hand-worked inputs (2^53 + 1 rounds to 2^53).
+* The ordinary FP64 dot (its definition: products rounded to double, added left to
+  right) is exact on small integers, obeys the gamma_n bound, and its association order
+  and product rounding are pinned by hand-worked inputs (2^53 + 1 rounds to 2^53).
 * Residual replacement does not change the iterates in exact arithmetic, so the FP64
   run with replacement must still track the rational Algorithm 2 (as the plain run
   does); a planted mistake in the replacement is caught by the same check.
@@ -22,27 +23,28 @@ U64 = 2.0 ** -53
 
 
 @pytest.mark.parametrize("n", [0, 1, 64, 4097, 70000, 1_500_000])
-def test_f64_tree_dot_exact_on_integers(n):
+def test_f64_seq_dot_exact_on_integers(n):
     rng = np.random.default_rng(n + 7)
     a = rng.integers(-1000, 1001, n).astype(np.float64)
     b = rng.integers(-1000, 1001, n).astype(np.float64)
-    assert solvers.dot_f64_tree(a, b) == float(np.dot(a.astype(np.int64), b.astype(np.int64)))
+    assert solvers.dot_f64_seq(a, b) == float(np.dot(a.astype(np.int64), b.astype(np.int64)))
 
 
-def test_f64_tree_dot_bound_and_order():
+def test_f64_seq_dot_bound_and_order():
     rng = np.random.default_rng(3)
     n = 200000
     a, b = rng.standard_normal(n), rng.standard_normal(n)
     exact = ctier.exact_dot(a, b)
     gam = n * U64 / (1 - n * U64)
-    assert abs(solvers.dot_f64_tree(a, b) - exact) <= gam * float(np.dot(np.abs(a), np.abs(b)))
+    assert abs(solvers.dot_f64_seq(a, b) - exact) <= gam * float(np.dot(np.abs(a), np.abs(b)))
     big = 2.0 ** 53
-    x = np.zeros(4096)
-    x[0], x[1], x[32] = big, 1.0, -big       # lanes 0 and 32 meet first in the butterfly
-    assert solvers.dot_f64_tree(x, np.ones(4096)) == 1.0
-    x = np.zeros(4096)
-    x[0], x[512], x[1024] = big, 1.0, -big   # one lane's own elements, in index order
-    assert solvers.dot_f64_tree(x, np.ones(4096)) == 0.0
+    # left to right: 2^53 + 1 ties to 2^53 (twice), then - 2^53 -> 0; a pairwise order
+    # would give 1, the reversed order 2
+    assert solvers.dot_f64_seq(np.array([big, 1.0, 1.0, -big]), np.ones(4)) == 0.0
+    assert solvers.dot_f64_seq(np.array([-big, 1.0, 1.0, big]), np.ones(4)) == 2.0
+    # products rounded to double first: (1 + 2^-27)^2 = 1 + 2^-26 + 2^-54 -> 1 + 2^-26
+    u = 1.0 + 2.0 ** -27
+    assert solvers.dot_f64_seq(np.array([u, -(1.0 + 2.0 ** -26)]), np.array([u, 1.0])) == 0.0
 
 
 def _tracks(kw, tol=1e-12, dot=None):
@@ -79,7 +81,7 @@ def test_replacement_mutation_caught():
 
 
 def test_plain_dots_track_rational():
-    assert _tracks({"exact_dot": None}, tol=1e-11, dot=solvers.dot_f64_tree)
+    assert _tracks({"exact_dot": None}, tol=1e-11, dot=solvers.dot_f64_seq)
 
 
 def test_plain_dot_plumbing():
@@ -89,6 +91,6 @@ def test_plain_dot_plumbing():
     same = solvers.pbicgstab(p.A, p.b, tol=1e-10, dot=solvers.default_dot(p.A.n),
                              exact_dot=solvers.default_dot(p.A.n))
     assert ex.iterations == same.iterations and np.array_equal(ex.x, same.x)
-    pl = solvers.pbicgstab(p.A, p.b, tol=1e-10, dot=solvers.dot_f64_tree, exact_dot=solvers.default_dot(p.A.n))
+    pl = solvers.pbicgstab(p.A, p.b, tol=1e-10, dot=solvers.dot_f64_seq, exact_dot=solvers.default_dot(p.A.n))
     assert pl.status == solvers.OK and pl.true_relres <= 1e-10
     assert np.linalg.norm(pl.x - ex.x) <= 1e-8 * np.linalg.norm(ex.x)

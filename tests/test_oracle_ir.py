@@ -5,8 +5,9 @@
   exact rational row sum, recovers rows whose plain FP32 sum cancels to garbage, and
   agrees with a loop transcription that takes the product error from exact rational
   arithmetic.
-* The FP32 tree dot is exact on small integers, obeys the worst-case gamma_n bound,
-  and its association order (butterfly pairs, wave order, group tree) is pinned by
+* The plain FP32 dot (its definition: products rounded to float32, added left to right)
+  is exact on small integers, obeys the worst-case gamma_n bound, and its association
+  order and product rounding are pinned by
   hand-worked inputs whose result depends on that order.
 * The refinement reaches the true relative residual 1e-10 with the FP64 oracle's
   solution, on every workload family; degenerate right-hand sides and the FP64
@@ -89,50 +90,48 @@ def test_dot2_spmv_matches_loops_and_empty_rows():
 
 
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 513, 4096, 4097, 70000, 2_200_000])
-def test_tree_dot_exact_on_integers(n):
+def test_seq_dot_exact_on_integers(n):
     rng = np.random.default_rng(n)
     a = rng.integers(-7, 8, n).astype(np.float32)
     b = rng.integers(-7, 8, n).astype(np.float32)
     exact = int(np.dot(a.astype(np.int64), b.astype(np.int64)))
-    assert abs(exact) < 2 ** 24
-    assert solvers.dot_f32_tree(a, b) == np.float32(exact)
+    # every partial sum stays below 2^24 in magnitude, so each addition is exact
+    assert np.abs(np.cumsum(a.astype(np.int64) * b.astype(np.int64))).max(initial=0) < 2 ** 24
+    assert solvers.dot_f32_seq(a, b) == np.float32(exact)
 
 
 @pytest.mark.parametrize("n", [1000, 50000, 300000])
-def test_tree_dot_bound(n):
+def test_seq_dot_bound(n):
     rng = np.random.default_rng(n + 1)
     a = rng.standard_normal(n).astype(np.float32)
     b = rng.standard_normal(n).astype(np.float32)
-    exact = np.dot(a.astype(np.float64), b.astype(np.float64))
-    err = abs(float(solvers.dot_f32_tree(a, b)) - exact)
+    exact = np.dot(a.astype(np.float64), b.astype(np.float64))   # products of floats are exact in double
+    err = abs(float(solvers.dot_f32_seq(a, b)) - exact)
     assert err <= gamma(n) * float(np.dot(np.abs(a).astype(np.float64), np.abs(b).astype(np.float64)))
 
 
-def lanes(n, entries):
-    """a with the given (index, value) entries, b = 1."""
-    a = np.zeros(n, dtype=np.float32)
-    for i, v in entries:
-        a[i] = v
-    return a, np.ones(n, dtype=np.float32)
-
-
-def test_tree_dot_association_order():
-    big = float(2 ** 24)
-    # butterfly: lanes 0 and 32 meet at the first level, before lane 1 joins
-    a, b = lanes(4096, [(0, big), (1, 1.0), (32, -big)])
-    assert solvers.dot_f32_tree(a, b) == 1.0
-    # a lane's own elements are summed first, in index order (n > S = 512 here: G = 1)
-    a, b = lanes(4096, [(0, big), (512, 1.0), (1024, -big)])
-    assert solvers.dot_f32_tree(a, b) == 0.0           # (2^24 + 1) rounds to 2^24, then - 2^24
-    # waves of a group are added in order: wave 0 + wave 1 absorbs 1, wave 2 cancels
-    a, b = lanes(4096, [(0, big), (64, 1.0), (128, -big)])
-    assert solvers.dot_f32_tree(a, b) == 0.0
-    # groups (n = 8193 -> G = 3): h_0 + h_2 at the w = 2 level ... tree w = 128 .. 1 pairs
-    # h_0 with h_128 first, so with G = 3 the order is (h_0 + h_2) + h_1
-    n = 8193
-    a, b = lanes(n, [(0, big), (512, 1.0), (1024, -big)])
-    assert solvers.fdot_grid(n) == 3
-    assert solvers.dot_f32_tree(a, b) == 1.0
+def test_seq_dot_association_and_rounding():
+    big = np.float32(2 ** 24)
+    one = np.float32(1.0)
+    ones = np.ones(4, dtype=np.float32)
+    # left to right: (2^24 + 1) ties to 2^24, then + 1 again, then - 2^24 -> 0
+    # (a pairwise order would give (2^24 + 1) + (1 - 2^24) = 2^24 + (-(2^24 - 1)) = 1)
+    assert solvers.dot_f32_seq(np.array([big, one, one, -big]), ones) == 0.0
+    assert solvers.dot_f32_seq(np.array([big, -big, one, one]), ones) == 2.0
+    # 16 terms: numpy's own reduction would keep 8 strided partial sums and pair them,
+    # (2^24 + 1) + (1 - 2^24) = 1; the sequential definition still gives 0
+    a16 = np.zeros(16, dtype=np.float32)
+    a16[:4] = [big, one, one, -big]
+    assert solvers.dot_f32_seq(a16, np.ones(16, dtype=np.float32)) == 0.0
+    # a reversed order would cancel first: 1 + 1 + (-2^24) + 2^24 -> (2 - 2^24) + 2^24 = 2
+    assert solvers.dot_f32_seq(np.array([big, one, one, -big])[::-1].copy(), ones) == 2.0
+    # each product is rounded to float32 before the addition: (1 + 2^-12)^2 = 1 + 2^-11 + 2^-24
+    # rounds to 1 + 2^-11 (ties to even), and the exact remainder 2^-24 is lost
+    u = np.float32(1.0 + 2.0 ** -12)
+    a = np.array([u, np.float32(-(1.0 + 2.0 ** -11))], dtype=np.float32)
+    b = np.array([u, one], dtype=np.float32)
+    assert solvers.dot_f32_seq(a, b) == 0.0
+    assert solvers.dot_f32_seq(np.zeros(0, np.float32), np.zeros(0, np.float32)) == 0.0
 
 
 @pytest.mark.parametrize("name,scale", [("cd2d_64", 20), ("cd2d_64", None), ("cd3d_128", 24),

@@ -83,14 +83,27 @@ def test_mutated_dot2_spmv_is_caught():
     assert bad(A, x)[0] != np.float32(2.0 ** -24)
 
 
-def test_mutated_tree_dot_order_is_caught():
-    big = float(2 ** 24)
-    a = np.zeros(4096, dtype=np.float32)
-    a[0], a[1], a[32] = big, 1.0, -big
-    b = np.ones(4096, dtype=np.float32)
-    assert solvers.dot_f32_tree(a, b) == 1.0
-    bad = _mutant(solvers._tree_dot, "for o in (32, 16, 8, 4, 2, 1):", "for o in (1, 2, 4, 8, 16, 32):")
-    assert bad(a, b, np.float32) != 1.0
+@pytest.mark.parametrize("old,new", [
+    ("np.add.accumulate(prod, dtype=np.float32)[-1]", "np.add.accumulate(prod[::-1], dtype=np.float32)[-1]"),
+    ("np.add.accumulate(prod, dtype=np.float32)[-1]", "np.add.reduce(prod, dtype=np.float32)"),   # pairwise
+    ("np.add.accumulate(prod, dtype=np.float32)[-1]", "np.add.accumulate(prod.astype(np.float64))[-1]"),  # double sums
+    ("prod = (np.asarray(a).astype(np.float32) * np.asarray(b).astype(np.float32)).astype(np.float32)\n",
+     "prod = np.asarray(a).astype(np.float64) * np.asarray(b).astype(np.float64)\n"
+     "    prod = prod.astype(np.float32) if prod.size < 2 else np.concatenate("
+     "[(prod[:1] + prod[1:2]).astype(np.float32), np.zeros(prod.size - 1, np.float32)])\n"),  # fused first products
+])
+def test_mutated_seq_dot_is_caught(old, new):
+    """Each planted change of the plain FP32 dot's definition fails its order / rounding pin."""
+    from tests.test_oracle_ir import test_seq_dot_association_and_rounding
+    test_seq_dot_association_and_rounding()
+    bad = _mutant(solvers.dot_f32_seq, old, new)
+    saved = solvers.dot_f32_seq
+    try:
+        solvers.dot_f32_seq = bad
+        with pytest.raises(AssertionError):
+            test_seq_dot_association_and_rounding()
+    finally:
+        solvers.dot_f32_seq = saved
 
 
 @pytest.mark.parametrize("old,new", [

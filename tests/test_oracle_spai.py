@@ -4,7 +4,8 @@ Central finite differences of the loss in float64 pin the whole analytic gradien
 chain (SDDMM, skip connection, both GELU layers, biases); the untrained net (zero
 last layer) is exactly Jacobi; the features are invariant under A -> cA and the
 m values scale as 1/c; the bf16 rounding matches its definition on hand-picked
-values; Adam matches its closed form on the first step (lr * sign(g)).
+values; Adam matches its closed form on the first step (lr * sign(g)); all twelve
+features of a hand-worked unsymmetric 4 x 4 matrix are written out and must match.
 """
 import math
 
@@ -54,6 +55,44 @@ def test_features_closed_form_entries():
     assert np.allclose(phi[:, 2], 1.0) and np.allclose(phi[:, 3], 1.0)
     assert np.allclose(phi[off, 11], 0.0)  # symmetric: zero local Peclet number
     assert np.allclose(phi[~off, 10], 1.0) and np.allclose(phi[off, 10], 0.0)
+
+
+# A hand-worked unsymmetric 4 x 4 matrix (negative diagonal in row 2, a missing transpose
+# entry at (1, 2)) and all twelve features of its eleven entries, worked out by hand:
+#   row abs sums R = (7, 7, 12, 4), column abs sums C = (7, 7, 9, 7),
+#   row lengths (3, 2, 3, 3) (max 3), max |j - i| per row (3, 1, 1, 3).
+HAND_A = [(0, 0, 4.0), (0, 1, -1.0), (0, 3, 2.0),
+          (1, 0, -2.0), (1, 1, 5.0),
+          (2, 1, 1.0), (2, 2, -8.0), (2, 3, 3.0),
+          (3, 0, 1.0), (3, 2, -1.0), (3, 3, 2.0)]
+F = __import__("fractions").Fraction
+HAND_PHI = [
+    # a_ij/|aii| a_ji/|aii| a_jj/|aii| sgn  R_i/|aii| R_j/|ajj| C_i/|aii| C_j/|ajj| len   (j-i)/mo [i=j] Pe
+    [1,        1,        1,        1,  F(7, 4), F(7, 4), F(7, 4), F(7, 4), 1,       0,       1, 0],        # (0,0)
+    [F(-1, 4), F(-1, 2), F(5, 4),  1,  F(7, 4), F(7, 5), F(7, 4), F(7, 5), 1,       F(1, 3), 0, F(1, 3)],  # (0,1)
+    [F(1, 2),  F(1, 4),  F(1, 2),  1,  F(7, 4), 2,       F(7, 4), F(7, 2), 1,       1,       0, F(1, 3)],  # (0,3)
+    [F(-2, 5), F(-1, 5), F(4, 5),  1,  F(7, 5), F(7, 4), F(7, 5), F(7, 4), F(2, 3), -1,      0, F(1, 3)],  # (1,0)
+    [1,        1,        1,        1,  F(7, 5), F(7, 5), F(7, 5), F(7, 5), F(2, 3), 0,       1, 0],        # (1,1)
+    [F(1, 8),  0,        F(5, 8),  -1, F(3, 2), F(7, 5), F(9, 8), F(7, 5), 1,       -1,      0, 1],        # (2,1)
+    [-1,       -1,       -1,       -1, F(3, 2), F(3, 2), F(9, 8), F(9, 8), 1,       0,       1, 0],        # (2,2)
+    [F(3, 8),  F(-1, 8), F(1, 4),  -1, F(3, 2), 2,       F(9, 8), F(7, 2), 1,       1,       0, 2],        # (2,3)
+    [F(1, 2),  1,        2,        1,  2,       F(7, 4), F(7, 2), F(7, 4), 1,       -1,      0, F(1, 3)],  # (3,0)
+    [F(-1, 2), F(3, 2),  -4,       1,  2,       F(3, 2), F(7, 2), F(9, 8), 1,       F(-1, 3), 0, 2],       # (3,2)
+    [1,        1,        1,        1,  2,       2,       F(7, 2), F(7, 2), 1,       0,       1, 0],        # (3,3)
+]
+
+
+def test_features_hand_worked_unsymmetric():
+    rows = [i for i, _, _ in HAND_A]
+    rp = np.zeros(5, dtype=np.int32)
+    np.add.at(rp, np.array(rows) + 1, 1)
+    A = g.CSR(4, np.cumsum(rp).astype(np.int32), np.array([j for _, j, _ in HAND_A], dtype=np.int32),
+              np.array([v for _, _, v in HAND_A]))
+    phi = spai.features(A)
+    expect = np.array([[float(v) for v in row] for row in HAND_PHI])
+    assert phi.shape == expect.shape
+    # every value is a ratio of small integers: float64 division rounds it once
+    assert np.array_equal(phi, expect), np.argwhere(phi != expect)
 
 
 def test_gradient_matches_finite_differences(small):
