@@ -1,31 +1,41 @@
 #!/usr/bin/env python3
 """Benchmark: time to true relative residual 1e-10, plus SpMV / exact-dot HBM bandwidth.
 
-Workload (the 128^3 configuration): 3D upwind convection-diffusion on a 128^3 grid,
-7-point stencil, velocity (30, 20, 10), n = 2,097,152, nnz = 14,581,760, CSR FP64 with
-int32 indices; x* ~ U[-1, 1] (seed 1), b = A x*, x0 = 0, tol 1e-10 on the true
-relative residual.  One step = one complete FP64 p-BiCGStab solve with exact dot
-products (initialisation, every iteration's phase A / SpMV / phase B / SpMV with their
-fused exact dots, and the true-residual checks), inputs already resident in HBM.
+Headline workload (the largest single-GPU configuration): 3D upwind convection-diffusion
+on a 256^3 grid, 7-point stencil, cell-wise diffusivity exp(N(0,1)) (harmonic face
+means), velocity (50, 25, 10), n = 16,777,216, nnz = 117,047,296, CSR FP64 with int32
+indices; x* ~ U[-1, 1] (seed 3), b = A x*, x0 = 0, tol 1e-10 on the true relative
+residual.  One step = one complete FP64 p-BiCGStab solve with exact dot products
+(initialisation, every iteration's phase A / SpMV / phase B / SpMV with their fused exact
+dots, and the true-residual checks), inputs already resident in HBM.  Its matrix (1.17 GB
+in the solver's sliced copy) and Krylov vectors (1.6 GB) are far larger than the 256 MB
+Infinity Cache, so every iteration streams from HBM: the roofline is HBM bandwidth.
 
 Also reported (outside the timed steps):
-  * on the same matrix: the BiCGStab comparator and FP32 / FP64 refinement with
-    reliable updates at update threshold 0.1 (the library default) and 1e-5;
-  * the paper's central comparison: exact vs ordinary FP64 dots, with and without
-    residual replacement, at tolerances 1e-10 and 1e-13;
+  * on the headline matrix: BiCGStab, p-BiCGStab with residual replacement every 50
+    iterations, FP32 refinement with reliable updates at update threshold 0.1 (the
+    library default) and 1e-5, each against the fastest FP64 form that reaches 1e-10;
+  * per-kernel durations of the solve's four kernels (phase A, v = A z, phase B, t = A w)
+    from HIP events that the kernels' own dispatches stamp inside a solve identical to
+    the timed ones, and from them the roofline of the dominant kernel (the SpMV);
+  * the 128^3 constant-coefficient workload, whose 146 MB sliced matrix stays resident in
+    the Infinity Cache (its SpMV figures are cache bandwidth, not HBM), with its own
+    kernel table, forms, and the paper's central comparison (exact vs ordinary FP64
+    dots, with and without residual replacement, at 1e-10 and 1e-13);
+  * the 64^2 workload (n = 4096): wall time only (latency-bound);
+  * the random unsymmetric n = 10^6 matrix: FP64 forms vs FP32 refinement;
   * the learned preconditioner: training on the seeded matrices 100..299 with the GPU
     kernels, then the held-out 128^3 Peclet-50 matrix solved plain, with Jacobi and with
     the learned M (setup time stated separately);
-  * plain FP64 vs FP32-IR on the random unsymmetric n = 10^6 matrix and on the 256^3
-    variable-diffusivity matrix;
-  * per-kernel durations of the solve's four kernels (phase A, v = A z, phase B, t = A w)
-    from HIP events that the kernels' own dispatches stamp inside the timed solves, and
-    from them the roofline of the dominant kernel (the SpMV);
   * micro-benchmarks (HIP events around every launch): the SpMV kernel shapes on a cold
-    cache and the standalone exact dot; and the CPU oracle timed on this host.
+    cache and the standalone exact dot;
+  * the CPU oracle (C, exact dots) on the headline workload on this host's cores, all
+    threads and one thread: a bounded sample of iterations, extrapolated per iteration to
+    the GPU's iteration count.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--solve-only]
-                       [--legs claim,learned,rand_1m,cd3d_256_var] [--epochs 30]
+                       [--legs cd3d_128,claim,cd2d_64,learned,rand_1m] [--epochs 30]
+                       [--traffic-run [--workload cd3d_256_var|cd3d_128]]
 """
 import argparse
 import hashlib
@@ -41,7 +51,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 CSRC = os.path.join(ROOT, "paper_2404_13216_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cd3d_128.md")
+HEADLINE = "cd3d_256_var"
+TRAFFIC_FILES = {"cd3d_256_var": os.path.join(ROOT, "profiles", "hbm_traffic_cd3d_256_var.md"),
+                 "cd3d_128": os.path.join(ROOT, "profiles", "hbm_traffic_cd3d_128.md")}
 KEV = 128  # iterations of each timed solve whose kernels carry timing events
 
 
@@ -101,16 +113,17 @@ def time_launches(fn, reps, torch):
 
 
 def spmv_cold(pk, torch, A, reps, kind=None, S=None):
-    """Median duration of one SpMV launch with a 512 MB write before each (no launch is
-    served from the Infinity Cache); returns (seconds, GB/s of 12 B/nnz + 20 B/row).
-    With S (a built sliced copy of A) the sliced row-sequential kernel is timed."""
-    flush = torch.empty(64 << 20, dtype=torch.float64, device=A.val.device)
+    """Median duration of one SpMV launch with a 1 GiB read before each (no launch is
+    served from the Infinity Cache, and no dirty lines are left to write back); returns
+    (seconds, GB/s of 12 B/nnz + 20 B/row).  With S (a built sliced copy of A) the sliced
+    row-sequential kernel is timed."""
+    flush = torch.ones(128 << 20, dtype=torch.float64, device=A.val.device)
     vin = torch.ones(A.n, dtype=torch.float64, device=A.val.device)
     vout = torch.empty_like(vin)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ts = []
     for it in range(reps + 1):
-        flush.zero_()
+        flush.sum()
         e0.record()
         if S is not None:
             pk.csr_spmv_sliced(S, vin, vout)
@@ -146,40 +159,100 @@ def rel(torch, a, b):
     return (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
 
 
-def precision_forms(pk, torch, A, b, xs, x64, t64, info64, reps):
-    """Plain FP64 p-BiCGStab (given) beside FP32 / FP64 refinement with reliable updates
-    at the default update threshold (0.1) and at 1e-5, each with its error against the
-    FP64 solution."""
-    forms = {"pbicgstab_fp64": {"seconds": t64, "iterations": info64["iterations"],
-                                "true_relres": info64["true_relres"], "status": info64["status"]}}
+def fp64_forms(pk, torch, A, b, xs, reps, plain=None):
+    """The FP64 solves of one workload: plain p-BiCGStab (exact dots; given, or timed
+    here), p-BiCGStab with residual replacement every 50 iterations, and BiCGStab
+    (Algorithm 1).  Returns (forms, x of the plain solve)."""
+    forms = {}
+    if plain is None:
+        plain = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000)
+    t64, i64, x64 = plain
+    forms["pbicgstab_fp64"] = {"seconds": t64, "iterations": i64["iterations"], "true_relres": i64["true_relres"],
+                               "status": i64["status"], "rel_err_vs_xstar": rel(torch, x64, xs)}
+    for key, kw in (("pbicgstab_fp64_rr50", {"rr_period": 50}), ("bicgstab_fp64", {"alg": pk.ALG_BICGSTAB})):
+        tr, ir, xr = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, **kw)
+        forms[key] = {"seconds": tr, "iterations": ir["iterations"], "true_relres": ir["true_relres"],
+                      "status": ir["status"], "rel_err_vs_xstar": rel(torch, xr, xs)}
+        log(f"  {key}: {tr:.4f} s, {ir['iterations']} iterations, status {ir['status']}")
+    return forms, x64
+
+
+def converged(f):
+    return f["status"] == 0 and f["true_relres"] <= 1e-10
+
+
+def precision_forms(pk, torch, A, b, xs, x64, forms, reps):
+    """FP32 refinement with reliable updates at the default update threshold (0.1) and at
+    1e-5, each with its error against the plain FP64 solution and x*, beside the FP64
+    forms.  speedup_vs_fp64 compares with plain FP64 p-BiCGStab and is null when that
+    solve did not reach 1e-10; speedup_vs_fastest_fp64 compares with the fastest FP64
+    form that did."""
+    ok = {k: v for k, v in forms.items() if converged(v)}
+    fastest = min(ok, key=lambda k: ok[k]["seconds"]) if ok else None
+    t64 = forms["pbicgstab_fp64"]["seconds"] if converged(forms["pbicgstab_fp64"]) else None
+    out = {}
     for key, itol in (("fp32_ir", None), ("fp32_ir_inner_1e-5", 1e-5)):
         kw = {} if itol is None else {"inner_tol": itol}
         ti, ii, xi = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, prec=pk.PREC_FP32_IR, **kw)
-        forms[key] = {"seconds": ti, "inner_tol": itol or 0.1, "inner_iterations": ii["iterations"],
-                      "outer": ii["outer_iterations"], "fell_back_to_fp64": ii["fell_back"],
-                      "true_relres": ii["true_relres"], "status": ii["status"],
-                      "rel_diff_vs_fp64_solve": rel(torch, xi, x64), "rel_err_vs_xstar": rel(torch, xi, xs),
-                      "speedup_vs_fp64": t64 / ti}
-    return forms
+        out[key] = {"seconds": ti, "inner_tol": itol or 0.1, "inner_iterations": ii["iterations"],
+                    "outer": ii["outer_iterations"], "fell_back_to_fp64": ii["fell_back"],
+                    "true_relres": ii["true_relres"], "status": ii["status"],
+                    "rel_diff_vs_fp64_solve": rel(torch, xi, x64), "rel_err_vs_xstar": rel(torch, xi, xs),
+                    "speedup_vs_fp64": (t64 / ti) if t64 else None,
+                    "fastest_fp64": fastest,
+                    "speedup_vs_fastest_fp64": (ok[fastest]["seconds"] / ti) if fastest else None}
+        log(f"  {key}: {ti:.4f} s, {ii['iterations']} FP32 iterations, fell back {ii['fell_back']}, "
+            f"status {ii['status']}")
+    return out
+
+
+def kernel_table(pk, torch, A, b, n, nnz, info, x, batch):
+    """Durations of the solve's four kernels over iterations 1..KEV of one more solve,
+    identical to the timed ones, whose kernels carry HIP events stamped by their own
+    dispatches (hipExtLaunchKernel: no markers between kernels, the launches keep their
+    spacing).  Bytes per launch: the algorithmic figures -- 12 per nonzero + 20 per row
+    for an SpMV (8-byte value, 4-byte column index; x once, y, row pointers), 104 and 80
+    per row for the phases -- and, for the SpMV, what the solve's layout moves (its
+    sliced copy stores 16-bit column residuals: 10 per nonzero + 20 per row)."""
+    tsolver = pk.Solver(A, kernel_events=KEV, tol=1e-10, max_iter=10000)
+    xk = torch.zeros(n, dtype=torch.float64, device=b.device)
+    _, kinfo = tsolver.solve(b, xk)
+    assert kinfo["iterations"] == info["iterations"] and torch.equal(xk, x)
+    ktimes = tsolver.kernel_times()
+    del tsolver, xk
+    used = max(1, min(KEV, info["iterations"] - 2 * batch))
+    col_bytes = 2 if info["sliced"] & 4 else 4
+    spmv_alg = 12 * nnz + 20 * n
+    spmv_layout = (8 + col_bytes) * nnz + 20 * n
+    roles = {"phase_a": 104 * n, "spmv_az": spmv_alg, "phase_b": 80 * n, "spmv_aw": spmv_alg}
+    kern = {}
+    for name, nb in roles.items():
+        ts = np.array(ktimes[name][:used])
+        kern[name] = {"us": float(ts.mean() * 1e6), "median_us": float(np.median(ts) * 1e6),
+                      "min_us": float(ts.min() * 1e6), "max_us": float(ts.max() * 1e6),
+                      "bytes": nb, "GBs": nb / ts.mean() / 1e9, "launches": int(ts.size)}
+    both = np.array(ktimes["spmv_az"][:used] + ktimes["spmv_aw"][:used])
+    kern["spmv_seq"] = {"us": float(both.mean() * 1e6), "median_us": float(np.median(both) * 1e6),
+                        "bytes": spmv_alg, "GBs": spmv_alg / both.mean() / 1e9, "launches": int(both.size),
+                        "layout": "sliced" if info["sliced"] & 1 else "csr",
+                        "layout_bytes": spmv_layout, "layout_GBs": spmv_layout / both.mean() / 1e9}
+    for v in kern.values():
+        v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
+    return kern, used, sum(kern[k]["us"] for k in roles)
 
 
 def config_leg(pk, torch, g, dev, name, reps):
-    """Plain FP64 vs FP32-IR on another workload (time to true relative residual 1e-10)."""
+    """FP64 forms vs FP32 refinement on another workload (time to true relative residual
+    1e-10), plus its SpMV kernel shapes on a cold cache."""
     t0 = time.time()
     prob = g.problem(name)
     A = pk.CSR.from_host(prob.A, dev)
     b = torch.from_numpy(prob.b).to(dev)
     xs = torch.from_numpy(prob.xstar).to(dev)
     gen = time.time() - t0
-    t64, i64, x64 = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000)
-    out = {"n": prob.A.n, "nnz": prob.A.nnz, "host_generation_s": gen,
-           "forms": precision_forms(pk, torch, A, b, xs, x64, t64, i64, reps)}
-    # FP64 references that do not depend on p-BiCGStab's attainable accuracy: residual
-    # replacement every 50 iterations, and BiCGStab (Algorithm 1)
-    for key, kw in (("pbicgstab_fp64_rr50", {"rr_period": 50}), ("bicgstab_fp64", {"alg": pk.ALG_BICGSTAB})):
-        tr, ir, xr = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, **kw)
-        out["forms"][key] = {"seconds": tr, "iterations": ir["iterations"], "true_relres": ir["true_relres"],
-                             "status": ir["status"], "rel_err_vs_xstar": rel(torch, xr, xs)}
+    forms, x64 = fp64_forms(pk, torch, A, b, xs, reps)
+    forms.update(precision_forms(pk, torch, A, b, xs, x64, forms, reps))
+    out = {"n": prob.A.n, "nnz": prob.A.nnz, "host_generation_s": gen, "forms": forms}
     kern = {}
     S = pk.SlicedCSR(A)
     out["sliced"] = {"built": S.built, "entries": S.entries}
@@ -191,8 +264,22 @@ def config_leg(pk, torch, g, dev, name, reps):
         kern[kname] = {"us": dt * 1e6, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
     out["kernels"] = kern
     del S
-    out["forms"]["pbicgstab_fp64"]["rel_err_vs_xstar"] = rel(torch, x64, xs)
     log(f"{name}:", json.dumps(out))
+    return out
+
+
+def small_leg(pk, torch, g, dev, reps=20):
+    """The 64^2 workload (n = 4096, 20,224 nonzeros): latency-bound, wall time only."""
+    prob = g.problem("cd2d_64")
+    A = pk.CSR.from_host(prob.A, dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    out = {}
+    for key, kw in (("pbicgstab_fp64", {}), ("bicgstab_fp64", {"alg": pk.ALG_BICGSTAB}),
+                    ("fp32_ir", {"prec": pk.PREC_FP32_IR})):
+        t, info, _ = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=2000, **kw)
+        out[key] = {"seconds": t, "iterations": info["iterations"], "status": info["status"],
+                    "true_relres": info["true_relres"], "us_per_iteration": t / max(info["iterations"], 1) * 1e6}
+    log("cd2d_64:", json.dumps(out))
     return out
 
 
@@ -293,9 +380,10 @@ def learned_leg(pk, torch, g, dev, reps, epochs):
 def traffic_run(pk, torch, A, b, n, nnz, dev):
     """Kernels whose HBM bytes rocprofv3 counters measure: a 256 MiB device copy (the
     calibration: 256 MiB read, 256 MiB written), the SpMV, phase A / phase B and the
-    standalone exact dot on the 128^3 workload, each launched 10 times with a 1 GiB read
+    standalone exact dot on the chosen workload, each launched 10 times with a 1 GiB read
     between launches so that no launch is served from the Infinity Cache; then one
     complete solve, whose kernels run as in the timed steps."""
+    log(f"source_hash {kernel_source_hash()}")
     rng = np.random.default_rng(1)
     V = {k: torch.from_numpy(rng.standard_normal(n) * 1e-3).to(dev) for k in
          ("x", "r", "rhat", "w", "t", "p", "s", "z", "q", "y", "v")}
@@ -332,22 +420,147 @@ def traffic_run(pk, torch, A, b, n, nnz, dev):
     log(f"traffic run done (solve: {info['iterations']} iterations, status {info['status']})")
 
 
+def resident_leg(pk, torch, g, dev, reps, with_claim):
+    """The 128^3 constant-coefficient workload: its 146 MB sliced matrix stays in the
+    256 MB Infinity Cache across the iteration (the phases stream the vectors past it),
+    so its SpMV figures are cache bandwidth, reported with bound "cache", not HBM."""
+    prob = g.problem("cd3d_128")
+    A = pk.CSR.from_host(prob.A, dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    xs = torch.from_numpy(prob.xstar).to(dev)
+    n, nnz = prob.A.n, prob.A.nnz
+    t, info, x = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000)
+    kern, used, itk = kernel_table(pk, torch, A, b, n, nnz, info, x, 16)
+    forms, x64 = fp64_forms(pk, torch, A, b, xs, 1, plain=(t, info, x))
+    forms.update(precision_forms(pk, torch, A, b, xs, x64, forms, 1))
+    out = {"workload": "cd3d_128: 3D upwind convection-diffusion 128^3, v=(30,20,10), seed 1; n=%d nnz=%d"
+                       % (n, nnz),
+           "regime": "Infinity-Cache-resident matrix: SpMV GB/s are cache bandwidth, not HBM",
+           "seconds": t, "iterations": info["iterations"], "true_relres": info["true_relres"],
+           "us_per_iteration": t / max(info["iterations"], 1) * 1e6,
+           "kernels_in_solve": kern, "iteration_kernel_us": itk,
+           "spmv_roofline": {"bound": "cache", "achieved": kern["spmv_seq"]["GBs"], "unit": "GB/s",
+                             "note": "above the HBM copy ceiling because the matrix is served by the "
+                                     "Infinity Cache; not an HBM fraction"},
+           "forms": forms}
+    if with_claim:
+        out["exact_vs_plain_dots"] = claim_leg(pk, torch, A, b, n)
+    log("cd3d_128:", json.dumps({k: v for k, v in out.items() if k != "exact_vs_plain_dots"}))
+    return out
+
+
+def micro_kernels(pk, torch, g, A, n, nnz, dev, reps):
+    """HIP events around every launch on the launch stream: the SpMV kernel shapes on a
+    cold cache (bytes: 12 per nonzero + 20 per row) and the standalone exact dot."""
+    kern = {}
+    S = pk.SlicedCSR(A)
+    shapes = [("spmv_seq_cold", pk.SPMV_SEQ, None), ("spmv_vector_cold", pk.SPMV_VECTOR, None),
+              ("spmv_wave_cold", pk.SPMV_WAVE, None)]
+    if S.built:
+        shapes.insert(0, ("spmv_seq_sliced_cold", pk.SPMV_SEQ, S))
+    for name, kind, sl in shapes:
+        dt, gbs = spmv_cold(pk, torch, A, min(reps, 10), kind, sl)
+        kern[name] = {"us": dt * 1e6, "bytes": 12 * nnz + 20 * n, "GBs": gbs}   # 32-bit columns
+    del S
+    # standalone exact dot, rotating over buffers larger than the cache: uniform
+    # U[-1, 1] at 2^20, 2^24, 2^26; wide exponents (+-1000) and exactly cancelling
+    # (ill-conditioned) inputs at 2^24
+    cases = [("uniform", 1 << 20), ("uniform", 1 << 24), ("uniform", 1 << 26),
+             ("wide_exponent", 1 << 24), ("ill_conditioned", 1 << 24)]
+    for fam, ne in cases:
+        nbuf = max(2, int((768 << 20) // (16 * ne)))
+
+        def vecs(i):
+            if fam == "uniform":
+                return (np.random.default_rng(10 + i).uniform(-1, 1, ne),
+                        np.random.default_rng(20 + i).uniform(-1, 1, ne))
+            if fam == "wide_exponent":
+                return g.wide_exponent_vec(ne, 10 + i), g.wide_exponent_vec(ne, 20 + i, -20, 20)
+            return g.cancelling_vec(ne, 10 + i), np.ones(ne)
+        bufs = [tuple(torch.from_numpy(v).to(dev) for v in vecs(i)) for i in range(nbuf)]
+        o1 = torch.empty(1, dtype=torch.float64, device=dev)
+        wse = torch.empty(pk.lib().exdot_workspace_bytes(ne), dtype=torch.uint8, device=dev)
+        cnt = [0]
+
+        def f():
+            xa, ya = bufs[cnt[0] % nbuf]
+            cnt[0] += 1
+            pk.exdot(xa, ya, o1, wse)
+        dt = time_launches(f, reps, torch)
+        key = f"exdot_2^{ne.bit_length() - 1}" + ("" if fam == "uniform" else f"_{fam}")
+        kern[key] = {"us": dt * 1e6, "bytes": 16 * ne, "GBs": 16 * ne / dt / 1e9}
+        del bufs
+    for k, v in kern.items():
+        v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
+    log("micro kernels:", json.dumps(kern))
+    return kern
+
+
+def cpu_baseline(prob, gi):
+    """The C oracle (exact dots, OpenMP) on the headline workload: a bounded sample of
+    iterations (about 20 s of CPU work) with all threads and with one, each extrapolated
+    per iteration to the GPU's iteration count gi."""
+    from oracle import ctier
+    host_cpus = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    res = {}
+    all_threads = ctier.num_threads()
+    for label, nt, budget in (("all", all_threads, 20.0), ("one", 1, 15.0)):
+        ctier.set_threads(nt)
+        t = time.perf_counter()
+        ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=0)
+        t_init = time.perf_counter() - t
+        t = time.perf_counter()
+        ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=2)
+        per_it = max(time.perf_counter() - t - t_init, 1e-9) / 2
+        k = int(max(2, min(gi, 200, budget / per_it)))
+        t = time.perf_counter()
+        rk = ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=k)
+        tk = time.perf_counter() - t
+        per_it = max(tk - t_init, 1e-9) / max(rk["iterations"], 1)
+        est = t_init + gi * per_it
+        res[label] = {"threads": nt, "iterations_timed": rk["iterations"], "seconds_timed": tk,
+                      "seconds_per_iteration": per_it, "init_s": t_init, "extrapolated_solve_s": est,
+                      "complete": rk["iterations"] == gi and rk["status"] == 0}
+        log(f"cpu oracle ({nt} threads): {rk['iterations']} iterations in {tk:.2f}s, {per_it * 1e3:.1f} ms each")
+    ctier.set_threads(all_threads)
+    a = res["all"]
+    return {"value": a["extrapolated_solve_s"], "unit": "s", "cores": a["threads"], "kind": "oracle",
+            "sample": (f"C oracle p-BiCGStab (exact dots, OpenMP) on the headline workload: "
+                       f"{a['iterations_timed']} of the GPU's {gi} iterations timed ({a['seconds_timed']:.1f} s, "
+                       f"{a['threads']} threads), extrapolated per iteration to {gi} iterations"
+                       + ("" if not a["complete"] else "; complete solve")),
+            "extrapolated": not a["complete"],
+            "one_thread": {"value": res["one"]["extrapolated_solve_s"], "cores": 1,
+                           "iterations_timed": res["one"]["iterations_timed"],
+                           "seconds_per_iteration": res["one"]["seconds_per_iteration"]},
+            "host_cpus": host_cpus, "cpu_model": model, "runs": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-only", action="store_true")
-    ap.add_argument("--reps", type=int, default=50)
-    ap.add_argument("--legs", default="claim,learned,rand_1m,cd3d_256_var",
-                    help="comma list of extra legs: claim, learned, rand_1m, cd3d_256_var (empty: none)")
+    ap.add_argument("--reps", type=int, default=30)
+    ap.add_argument("--legs", default="cd3d_128,claim,cd2d_64,learned,rand_1m",
+                    help="comma list of extra legs: cd3d_128, claim (needs cd3d_128), cd2d_64, learned, "
+                         "rand_1m (empty: none)")
     ap.add_argument("--epochs", type=int, default=30, help="learned-preconditioner training epochs")
     ap.add_argument("--traffic-run", action="store_true",
                     help="launch each measured kernel 10 times (for rocprofv3 --pmc runs) and exit")
+    ap.add_argument("--workload", default=HEADLINE, help="workload of --traffic-run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU: bench.py measures one GPU's throughput; "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -357,11 +570,12 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     t0 = time.time()
-    prob = g.problem("cd3d_128")
+    wl = args.workload if args.traffic_run else HEADLINE
+    prob = g.problem(wl)
     A = pk.CSR.from_host(prob.A, dev)
     b = torch.from_numpy(prob.b).to(dev)
     n, nnz = prob.A.n, prob.A.nnz
-    log(f"workload cd3d_128 n={n} nnz={nnz} built in {time.time() - t0:.1f}s")
+    log(f"workload {wl} n={n} nnz={nnz} built in {time.time() - t0:.1f}s")
 
     if args.traffic_run:
         traffic_run(pk, torch, A, b, n, nnz, dev)
@@ -376,53 +590,28 @@ def main():
 
     for _ in range(args.warmup):
         _, info = step()
+        log(f"warmup solve: {info['iterations']} iterations, status {info['status']}")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     infos = []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         _, info = step()
         infos.append(info)
+        log(f"step {k + 1}/{args.steps}: {info['iterations']} iterations")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     sec = elapsed / args.steps
     info = infos[-1]
     assert all(i["status"] == pk.OK and i["iterations"] == info["iterations"] for i in infos), infos
     xs = torch.from_numpy(prob.xstar).to(dev)
-    err_xstar = (torch.linalg.norm(x - xs) / torch.linalg.norm(xs)).item()
+    err_xstar = rel(torch, x, xs)
     log(f"p-BiCGStab: {sec * 1e3:.2f} ms/solve, {info['iterations']} iterations, "
         f"true relres {info['true_relres']:.3e}")
-    # kernel durations: one more solve, identical to the timed ones, whose kernels of
-    # iterations 1..KEV carry HIP events stamped by the kernels' own dispatches
-    # (hipExtLaunchKernel; no markers between kernels, so the launches keep their spacing)
-    tsolver = pk.Solver(A, kernel_events=KEV, tol=1e-10, max_iter=10000)
-    xk = torch.zeros(n, dtype=torch.float64, device=dev)
-    _, kinfo = tsolver.solve(b, xk)
-    assert kinfo["iterations"] == info["iterations"] and torch.equal(xk, x)
-    ktimes = tsolver.kernel_times()
-    del tsolver, xk
-    used = max(1, min(KEV, info["iterations"] - 2 * solver.opts.batch))
-    # the SpMV's bytes: 8-byte value + column entry per nonzero (4 bytes, or 2 when the
-    # sliced copy stores 16-bit column residuals), x once, y, row pointers: 20 bytes per row
-    col_bytes = 2 if info["sliced"] & 4 else 4
-    spmv_bytes = (8 + col_bytes) * nnz + 20 * n
-    roles = {"phase_a": 104 * n, "spmv_az": spmv_bytes, "phase_b": 80 * n, "spmv_aw": spmv_bytes}
-    kern = {}
-    for name, nb in roles.items():
-        ts = np.array(ktimes[name][:used])
-        kern[name] = {"us": float(ts.mean() * 1e6), "median_us": float(np.median(ts) * 1e6),
-                      "min_us": float(ts.min() * 1e6), "max_us": float(ts.max() * 1e6),
-                      "bytes": nb, "GBs": nb / ts.mean() / 1e9, "launches": int(ts.size)}
-    both = np.array(ktimes["spmv_az"][:used] + ktimes["spmv_aw"][:used])
-    kern["spmv_seq"] = {"us": float(both.mean() * 1e6), "median_us": float(np.median(both) * 1e6),
-                        "bytes": spmv_bytes, "GBs": spmv_bytes / both.mean() / 1e9, "launches": int(both.size),
-                        "layout": "sliced" if info["sliced"] & 1 else "csr"}
-    for v in kern.values():
-        v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
-    iter_kernels_us = sum(kern[k]["us"] for k in roles)
+    kern, used, iter_kernels_us = kernel_table(pk, torch, A, b, n, nnz, info, x, solver.opts.batch)
     log("kernels in the solve:", json.dumps(kern))
 
     out = {
-        "metric": "time to true rel. residual 1e-10 (plain FP64 p-BiCGStab, exact dots)",
+        "metric": "time to true rel. residual 1e-10 (plain FP64 p-BiCGStab, exact dots) + SpMV HBM GB/s",
         "value": sec,
         "unit": "s",
         "n_gpus": 1,
@@ -434,7 +623,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cd3d_128: 3D upwind convection-diffusion 128^3, v=(30,20,10), seed 1",
+        "config": {"workload": "cd3d_256_var: 3D upwind convection-diffusion 256^3, kappa=exp(N(0,1)) cell-wise "
+                               "(harmonic faces), v=(50,25,10), seed 3",
                    "n": n, "nnz": nnz, "tol": 1e-10, "x0": "0", "alg": "p-BiCGStab",
                    "dots": "exact (rounded once)",
                    "spmv": "row-sequential, " + ("sliced copy (256-row slices%s)" % (
@@ -448,108 +638,43 @@ def main():
     }
     # dominant kernel of the iteration: the SpMV (two launches per iteration)
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        txt = open(TRAFFIC_FILE).read()
+    tf = TRAFFIC_FILES[HEADLINE]
+    if os.path.exists(tf):
+        txt = open(tf).read()
         blob = txt[txt.index("```json") + 7: txt.index("```", txt.index("```json") + 7)]
         tr = json.loads(blob)
         if tr.get("source_hash") == kernel_source_hash() and "spmv_seq" in tr.get("kernels", {}):
-            traffic = tr["kernels"]["spmv_seq"]["bytes_per_launch"]
-    out["roofline"] = {"kernel": "spmv_seq", "bound": "hbm", "achieved": kern["spmv_seq"]["GBs"],
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["spmv_seq"]["GBs"] / HBM_PEAK_GBS,
-                       "traffic": traffic, "algorithmic_bytes_per_launch": spmv_bytes,
-                       "algorithmic_bytes": "%d per nonzero + 20 per row" % (8 + col_bytes),
-                       "avg_launch_us": kern["spmv_seq"]["us"], "launches": kern["spmv_seq"]["launches"],
-                       "timing": "HIP events stamped by the kernel dispatches of iterations 1..%d of a solve identical to the timed ones" % used}
+            ks = tr["kernels"]
+            traffic = (ks["spmv_seq"]["bytes_per_launch"] + ks.get("spmv_aw", ks["spmv_seq"])["bytes_per_launch"]) / 2
+    sp = kern["spmv_seq"]
+    out["roofline"] = {"kernel": "spmv_seq", "bound": "hbm", "achieved": sp["GBs"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sp["GBs"] / HBM_PEAK_GBS,
+                       "traffic": traffic, "algorithmic_bytes_per_launch": sp["bytes"],
+                       "algorithmic_bytes": "12 per nonzero + 20 per row",
+                       "layout_bytes_per_launch": sp["layout_bytes"], "layout_GBs": sp["layout_GBs"],
+                       "avg_launch_us": sp["us"], "launches": sp["launches"],
+                       "timing": "HIP events stamped by the kernel dispatches of iterations 1..%d of a solve "
+                                 "identical to the timed ones" % used}
 
     if not args.solve_only:
-        forms = {}
-        # BiCGStab comparator (Algorithm 1)
-        tb, ib, xb = timed_solve(pk, torch, A, b, 1, tol=1e-10, max_iter=10000, alg=pk.ALG_BICGSTAB)
-        forms["bicgstab_fp64"] = {"seconds": tb, "iterations": ib["iterations"], "true_relres": ib["true_relres"],
-                                  "status": ib["status"]}
-        forms.update(precision_forms(pk, torch, A, b, xs, x, sec, info, 1))
+        forms, x64 = fp64_forms(pk, torch, A, b, xs, 1, plain=(sec, info, x))
+        forms.update(precision_forms(pk, torch, A, b, xs, x64, forms, 1))
         out["forms"] = forms
         log("forms:", json.dumps(forms))
-
-        # micro-benchmarks outside the solve (HIP events around every launch on the
-        # launch stream): the SpMV kernel shapes on a cold cache and the standalone exact dot
-        kern = {}
-        reps = args.reps
-        S = pk.SlicedCSR(A)
-        # SpMV kernel shapes, each launch preceded by a 512 MB write that evicts the cache
-        shapes = [("spmv_seq_cold", pk.SPMV_SEQ, None), ("spmv_vector_cold", pk.SPMV_VECTOR, None),
-                  ("spmv_wave_cold", pk.SPMV_WAVE, None)]
-        if S.built:
-            shapes.insert(0, ("spmv_seq_sliced_cold", pk.SPMV_SEQ, S))
-        for name, kind, sl in shapes:
-            dt, gbs = spmv_cold(pk, torch, A, min(reps, 20), kind, sl)
-            kern[name] = {"us": dt * 1e6, "bytes": 12 * nnz + 20 * n, "GBs": gbs}   # 32-bit columns
-        # standalone exact dot, rotating over buffers larger than the cache: uniform
-        # U[-1, 1] at 2^20, 2^24, 2^26; wide exponents (+-1000) and exactly cancelling
-        # (ill-conditioned) inputs at 2^24
-        cases = [("uniform", 1 << 20), ("uniform", 1 << 24), ("uniform", 1 << 26),
-                 ("wide_exponent", 1 << 24), ("ill_conditioned", 1 << 24)]
-        for fam, ne in cases:
-            nbuf = max(2, int((768 << 20) // (16 * ne)))
-
-            def vecs(i):
-                if fam == "uniform":
-                    return (np.random.default_rng(10 + i).uniform(-1, 1, ne),
-                            np.random.default_rng(20 + i).uniform(-1, 1, ne))
-                if fam == "wide_exponent":
-                    return g.wide_exponent_vec(ne, 10 + i), g.wide_exponent_vec(ne, 20 + i, -20, 20)
-                return g.cancelling_vec(ne, 10 + i), np.ones(ne)
-            bufs = [tuple(torch.from_numpy(v).to(dev) for v in vecs(i)) for i in range(nbuf)]
-            o1 = torch.empty(1, dtype=torch.float64, device=dev)
-            wse = torch.empty(pk.lib().exdot_workspace_bytes(ne), dtype=torch.uint8, device=dev)
-            cnt = [0]
-
-            def f():
-                xa, ya = bufs[cnt[0] % nbuf]
-                cnt[0] += 1
-                pk.exdot(xa, ya, o1, wse)
-            dt = time_launches(f, reps, torch)
-            key = f"exdot_2^{ne.bit_length() - 1}" + ("" if fam == "uniform" else f"_{fam}")
-            kern[key] = {"us": dt * 1e6, "bytes": 16 * ne, "GBs": 16 * ne / dt / 1e9}
-            del bufs
-        for k, v in kern.items():
-            v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
-        out["micro_kernels"] = kern
-        log("micro kernels:", json.dumps(kern))
-        del S
-        # further legs run after the kernel table, so that they do not disturb its timings
+        out["micro_kernels"] = micro_kernels(pk, torch, g, A, n, nnz, dev, args.reps)
+        # further legs run after the headline tables, so that they do not disturb them
         legs = [l for l in args.legs.split(",") if l]
-        if "claim" in legs:
-            out["exact_vs_plain_dots"] = claim_leg(pk, torch, A, b, n)
+        if "cd3d_128" in legs:
+            out["cd3d_128"] = resident_leg(pk, torch, g, dev, 3, "claim" in legs)
+        if "cd2d_64" in legs:
+            out["cd2d_64"] = small_leg(pk, torch, g, dev)
         if "learned" in legs:
             out["learned_m"] = learned_leg(pk, torch, g, dev, 1, args.epochs)
-        for name in ("rand_1m", "cd3d_256_var"):
-            if name in legs:
-                out.setdefault("other_workloads", {})[name] = config_leg(pk, torch, g, dev, name, 1)
+        if "rand_1m" in legs:
+            out.setdefault("other_workloads", {})["rand_1m"] = config_leg(pk, torch, g, dev, "rand_1m", 1)
 
     if not args.no_cpu:
-        from oracle import ctier
-        cores = ctier.num_threads()
-        gi = info["iterations"]
-        t = time.perf_counter()
-        ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=0)
-        t_init = time.perf_counter() - t
-        t = time.perf_counter()
-        ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=4)
-        per_it = max(time.perf_counter() - t - t_init, 1e-9) / 4
-        k = int(max(4, min(gi, 20.0 / per_it)))  # bounded sample: about 20 s of CPU work
-        t = time.perf_counter()
-        rk = ctier.pbicgstab(prob.A, prob.b, tol=1e-10, max_iter=k)
-        tk = time.perf_counter() - t
-        per_it = max(tk - t_init, 1e-9) / max(rk["iterations"], 1)
-        est = tk + max(gi - rk["iterations"], 0) * per_it
-        full = rk["iterations"] == gi and rk["status"] == 0
-        out["cpu_baseline"] = {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
-                               "sample": (f"C oracle p-BiCGStab (exact dots, OpenMP, {cores} threads) on the same "
-                                          f"workload: {rk['iterations']} of the GPU's {gi} iterations timed "
-                                          f"({tk:.2f}s)" + ("; complete solve, same iterates" if full else
-                                                            ", remainder extrapolated per iteration")),
-                               "seconds_per_iteration": per_it}
+        out["cpu_baseline"] = cpu_baseline(prob, info["iterations"])
         log("cpu baseline:", json.dumps(out["cpu_baseline"]))
     print(json.dumps(out), flush=True)
 
