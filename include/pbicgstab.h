@@ -68,11 +68,15 @@ typedef enum { PBCG_DOTS_EXACT = 0, PBCG_DOTS_PLAIN = 1 } pbcg_dots;
 
 /* Matrix layout of the solver's row-sequential SpMVs.  AUTO: the solver copies A (and
  * M) into the sliced layout of csr_slice when its padding stays within nnz/8 + 256
- * entries, else it keeps CSR; the copy stores each column entry as a 16-bit residual
- * col - row - base, with one 32-bit base per slice and entry position (the smallest
- * col - row there), when every residual fits (2 bytes per entry less).  CSR: never
- * copied.  All give bit-identical results. */
-typedef enum { PBCG_LAYOUT_AUTO = 0, PBCG_LAYOUT_CSR = 1 } pbcg_layout;
+ * entries; the copy stores each column entry as a 16-bit residual col - row - base, with
+ * one 32-bit base per slice and entry position (the smallest col - row there), when every
+ * residual fits (2 bytes per entry less); otherwise it keeps CSR.  SORTED: a row-sorted
+ * copy instead (when its padding fits the same bound): slices of 64 rows (one
+ * wavefront), the rows of every window of 4096 consecutive rows ordered by decreasing
+ * length so that each slice holds rows of nearly equal length, with a permutation back
+ * to the row order (4 bytes per row).  CSR: never copied.  All give bit-identical
+ * results: every row is still summed left to right in storage order by one lane. */
+typedef enum { PBCG_LAYOUT_AUTO = 0, PBCG_LAYOUT_CSR = 1, PBCG_LAYOUT_SORTED = 2 } pbcg_layout;
 
 /* Square CSR matrix.  `val` points to nnz values of type `val_type`. */
 typedef struct {
@@ -129,6 +133,14 @@ typedef struct {
                                   events [8(j-1) + 2k] and [8(j-1) + 2k + 1] with kernel k's
                                   start and end; events of iterations that do not run keep
                                   their previous state.  Results are unaffected.            */
+    int32_t exact_rows;        /* exactly rounded SpMV rows (the reproducible-reduction idea
+                                  of the paper's Section 2 applied to A x; FP64 p-BiCGStab
+                                  without M): 0 off; 1 every b - A x (r0, the true residual,
+                                  residual replacement, true-residual history) has each row
+                                  b_i - sum_k a_ik x_k formed exactly and rounded once;
+                                  2 as 1, and every A v of the iteration has exactly rounded
+                                  rows too (csr_spmv_exact), so no result depends on a
+                                  summation order.  Slower per SpMV (csr_spmv_exact).       */
 } pbcg_opts;
 
 /* Result summary (host struct). */
@@ -139,7 +151,8 @@ typedef struct {
     int32_t true_checks;       /* true-residual evaluations                                  */
     int32_t fell_back;         /* 1 if the preconditioned solve fell back                    */
     int32_t sliced;            /* bit 0: A, bit 1: M ran on a sliced copy (layout AUTO);
-                                  bit 2: A's, bit 3: M's copy holds 16-bit column residuals */
+                                  bit 2: A's, bit 3: M's copy holds 16-bit column residuals;
+                                  bit 4: A's, bit 5: M's copy is the row-sorted one        */
     double true_relres;        /* ||b - A x|| / ||b|| of the returned x (exact dots)         */
     double rec_relres;         /* last recursive ||r|| / ||b||                               */
     double seconds;            /* host wall time of the call                                 */
@@ -157,6 +170,13 @@ typedef struct {
  * alias x.
  */
 int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream);
+
+/* y = A x with every row summed exactly and rounded once to nearest even (the exact
+ * dot's definition applied to each row: exact zero gives +0, NaN / inf as in exdot), so
+ * the result depends on no summation order (paper, Section 2, the ExBLAS paragraph).
+ * A: FP64 or FP32 values; x, y: FP64, y != x.  16 lanes per row deposit the exact
+ * products into the row's LDS long accumulator; about 3x the time of csr_spmv. */
+int csr_spmv_exact(const pbcg_csr* A, const double* x, double* y, void* stream);
 
 /* Same with an explicit kernel shape (pbcg_spmv_kind). */
 int csr_spmv_config(const pbcg_csr* A, const double* x, double* y, int32_t kind, void* stream);
@@ -336,6 +356,15 @@ int spai_forward(int64_t nnz, const float* feat, const float* params, const int3
  * FP32 accumulation and GELU, M values stored FP32. */
 int spai_infer_bf16(int64_t nnz, const float* feat, const float* params, const int32_t* rowidx,
                     const double* diag, float* m_out, void* stream);
+
+/* One residual column of a probe block (the training objective's V holds residuals
+ * r_i / ||r_i|| of a plain p-BiCGStab run on the training matrix):
+ * out[i] = fp32(r_i / ||r||_2), ||r||_2 the square root of the exact dot (r, r) (rounded
+ * once, as every inner product here); r = 0 gives a zero column.  r: n device doubles,
+ * out: n device floats (e.g. a column of a column-major V).  Workspace:
+ * spai_probe_column_workspace_bytes(n). */
+size_t spai_probe_column_workspace_bytes(int32_t n);
+int spai_probe_column(int32_t n, const double* r, float* out, void* ws, size_t ws_bytes, void* stream);
 
 /* U = A V for a probe block V (n x k, column-major FP32); FP64 row sums stored FP32. */
 int spai_probe_product(const pbcg_csr* A, const float* V, int32_t k, float* U, void* stream);

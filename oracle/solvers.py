@@ -123,13 +123,17 @@ class _TrueTest:
         return self.stag >= self.PATIENCE
 
 
-def _true_relres(A, b, x, normb, dot, spmv):
-    res = b - spmv(A, x)
+def _resid_seq(spmv):
+    return lambda A, b, x: b - spmv(A, x)
+
+
+def _true_relres(A, b, x, normb, dot, resid):
+    res = resid(A, b, x)
     return math.sqrt(dot(res, res)) / normb
 
 
 def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=None,
-              record=0, stall_window=0, exact_dot=None, rr_period=0, true_every=0) -> Result:
+              record=0, stall_window=0, exact_dot=None, rr_period=0, true_every=0, resid=None) -> Result:
     """p-BiCGStab, Algorithm 2, with the readings in the module docstring.
 
     With ``M`` (a CSR right preconditioner) the recurrences run on A.M and y,
@@ -143,8 +147,12 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     s = A p, z = A s, v = A z, with the scalars kept (unpreconditioned only).
     ``true_every`` > 0: after every true_every-th completed iteration the solve
     continues from, the true relative residual is appended to ``true_history``.
+    ``resid(A, b, x)`` forms b - A x wherever the solve needs it (r_0, the true residual,
+    replacement); default b - spmv(A, x) (two roundings per row); ``oracle.spmv.resid_exact``
+    rounds each row of it once.
     """
     spmv = spmv or _spmv
+    resid = resid or _resid_seq(spmv)
     n = A.n
     dot = dot or default_dot(n)
     xdot = exact_dot or dot
@@ -161,7 +169,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     def finish(status, iters, rec, hist, its, checks, true=None):
         x = op.to_x(y)
         if true is None:
-            true = _true_relres(A, b, x, normb, xdot, spmv) if normb > 0 else 0.0
+            true = _true_relres(A, b, x, normb, xdot, resid) if normb > 0 else 0.0
         return Result(x, status, iters, true, rec, checks, hist, its, true_history=true_hist)
 
     nb2 = xdot(b, b)
@@ -171,7 +179,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     if normb == 0.0:
         return Result(np.zeros(n), OK, 0, 0.0, 0.0)
     # initialisation (Algorithm 2, before the loop)
-    r = b - spmv(A, op.to_x(y)) if x0 is not None else b.copy()
+    r = resid(A, b, op.to_x(y)) if x0 is not None else b.copy()
     rhat = r.copy()
     w = op.apply(r)
     t = op.apply(w)
@@ -182,7 +190,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
     test = _TrueTest(tol)
     if test.due(rec, 0):
         checks += 1
-        tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
+        tr = _true_relres(A, b, op.to_x(y), normb, xdot, resid)
         if tr <= tol:
             return finish(OK, 0, rec, hist, its, checks, tr)
         if test.failed(rec, tr, 0, y):
@@ -215,7 +223,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
             if xdot(q, q) == 0.0:  # lucky breakdown: r_{i+1} = q_i = 0
                 y = y + alpha * p
                 checks += 1
-                tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
+                tr = _true_relres(A, b, op.to_x(y), normb, xdot, resid)
                 return finish(OK if tr <= tol else BREAKDOWN, i + 1, 0.0, hist, its, checks, tr)
             return finish(BREAKDOWN, i, rec, hist, its, checks)
         omega = qy / yy
@@ -237,7 +245,7 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         alpha_new = rho_new / den if den != 0.0 else math.nan
         if test.due(rec, i + 1):
             checks += 1
-            tr = _true_relres(A, b, op.to_x(y), normb, xdot, spmv)
+            tr = _true_relres(A, b, op.to_x(y), normb, xdot, resid)
             if tr <= tol:
                 return finish(OK, i + 1, rec, hist, its, checks, tr)
             if test.failed(rec, tr, i + 1, y):
@@ -254,9 +262,9 @@ def pbicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, M=None, dot=None, spmv=N
         if i + 1 == max_iter:          # the solve does not continue from the last iteration
             break
         if true_every and (i + 1) % true_every == 0:
-            true_hist.append(_true_relres(A, b, op.to_x(y), normb, xdot, spmv))
+            true_hist.append(_true_relres(A, b, op.to_x(y), normb, xdot, resid))
         if rr_period and (i + 1) % rr_period == 0:
-            r = b - spmv(A, y)
+            r = resid(A, b, y)
             w = op.apply(r)
             t = op.apply(w)
             s = op.apply(p)
@@ -286,7 +294,7 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
 
     def finish(status, iters, rec, true=None):
         if true is None:
-            true = _true_relres(A, b, x, normb, dot, spmv)
+            true = _true_relres(A, b, x, normb, dot, _resid_seq(spmv))
         return Result(x, status, iters, true, rec, checks, hist, its)
 
     r = b - spmv(A, x) if x0 is not None else b.copy()
@@ -298,7 +306,7 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
     test = _TrueTest(tol)
     if test.due(rec, 0):
         checks += 1
-        tr = _true_relres(A, b, x, normb, dot, spmv)
+        tr = _true_relres(A, b, x, normb, dot, _resid_seq(spmv))
         if tr <= tol:
             return finish(OK, 0, rec, tr)
         if test.failed(rec, tr, 0, x):
@@ -324,7 +332,7 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
             if dot(q, q) == 0.0:
                 x = x + alpha * p
                 checks += 1
-                tr = _true_relres(A, b, x, normb, dot, spmv)
+                tr = _true_relres(A, b, x, normb, dot, _resid_seq(spmv))
                 return finish(OK if tr <= tol else BREAKDOWN, i + 1, 0.0, tr)
             return finish(BREAKDOWN, i, rec)
         omega = qy / yy
@@ -341,7 +349,7 @@ def bicgstab(A, b, x0=None, tol=1e-10, max_iter=10000, dot=None, spmv=None, reco
         beta = ((alpha / omega) * rho_new) / rho
         if test.due(rec, i + 1):
             checks += 1
-            tr = _true_relres(A, b, x, normb, dot, spmv)
+            tr = _true_relres(A, b, x, normb, dot, _resid_seq(spmv))
             if tr <= tol:
                 return finish(OK, i + 1, rec, tr)
             if test.failed(rec, tr, i + 1, x):

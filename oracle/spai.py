@@ -213,9 +213,19 @@ def infer_bf16_values(theta, phi, a_ii):
 
 
 # ------------------------------------------------------------------ probe blocks
+def _exact_dot(a, b):
+    from . import exact
+    if a.size <= 20000:
+        return exact.exact_dot(a.tolist(), b.tolist())
+    from . import ctier
+    return ctier.exact_dot(a, b)
+
+
 def probe_block(A, b, seed, dot=None, k_rad=4, steps=(1, 4, 16, 64)):
     """V = [k_rad Rademacher columns | normalised residuals r_i / ||r_i|| of a plain
-    p-BiCGStab run on (A, b) at the iterations in `steps` (or the last available)]."""
+    p-BiCGStab run on (A, b) at the iterations in `steps` (or the last available)].
+    ||r|| is the square root of the exact (r, r), rounded once -- the norm every inner
+    product of the method uses; a zero residual gives a zero column."""
     from synthgen import rademacher
     from . import solvers
     n = A.n
@@ -224,5 +234,6 @@ def probe_block(A, b, seed, dot=None, k_rad=4, steps=(1, 4, 16, 64)):
     for s in steps:
         it = res.iterates[min(s, len(res.iterates)) - 1] if res.iterates else None
         r = it[1] if it is not None else b
-        cols.append((r / np.linalg.norm(r))[:, None])
+        nrm = math.sqrt(_exact_dot(r, r))
+        cols.append((r / nrm if nrm > 0 else np.zeros(n))[:, None])
     return np.asfortranarray(np.concatenate(cols, axis=1))

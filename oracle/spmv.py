@@ -108,3 +108,45 @@ def spmv_f32_loops(A32, x32) -> list:
             c = c + (err + e)
         out.append(s + c)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Exactly rounded rows (the ExBLAS idea of the paper's Section 2 applied to the rows of
+# A x): every row's sum is formed exactly and rounded once to nearest-even, so the result
+# depends on no summation order at all.
+# ---------------------------------------------------------------------------
+def _row_dot(a, b):
+    from . import exact
+    if len(a) <= 64:
+        return exact.exact_dot(list(a), list(b))
+    from . import ctier
+    return ctier.exact_dot(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64))
+
+
+def spmv_exact(A, x, rows=None) -> np.ndarray:
+    """y_i = RN(sum_k a_ik x_k), each row one exact dot product rounded once (rows: an
+    optional subset; the returned vector then holds those rows only)."""
+    x = np.asarray(x, dtype=np.float64)
+    rp = A.row_ptr
+    idx = range(A.n) if rows is None else rows
+    out = []
+    for i in idx:
+        a, e = int(rp[i]), int(rp[i + 1])
+        out.append(_row_dot(np.asarray(A.val[a:e], dtype=np.float64).tolist(), x[A.col_idx[a:e]].tolist()))
+    return np.array(out, dtype=np.float64)
+
+
+def resid_exact(A, b, x, rows=None) -> np.ndarray:
+    """r_i = RN(b_i - sum_k a_ik x_k): the residual row as one exact sum, rounded once
+    (b_i enters as the term b_i * 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    rp = A.row_ptr
+    idx = range(A.n) if rows is None else rows
+    out = []
+    for i in idx:
+        a, e = int(rp[i]), int(rp[i + 1])
+        vals = [float(b[i])] + (-np.asarray(A.val[a:e], dtype=np.float64)).tolist()
+        xs = [1.0] + x[A.col_idx[a:e]].tolist()
+        out.append(_row_dot(vals, xs))
+    return np.array(out, dtype=np.float64)

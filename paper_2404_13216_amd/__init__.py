@@ -26,7 +26,7 @@ ALG_PBICGSTAB, ALG_BICGSTAB = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 SPMV_SEQ, SPMV_VECTOR, SPMV_WAVE = 0, 1, 2
 DOTS_EXACT, DOTS_PLAIN = 0, 1
-LAYOUT_AUTO, LAYOUT_CSR = 0, 1
+LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SORTED = 0, 1, 2
 
 _P = ctypes.c_void_p
 
@@ -46,7 +46,8 @@ class PbcgOpts(ctypes.Structure):
                 ("dots", ctypes.c_int32), ("rr_period", ctypes.c_int32),
                 ("true_every", ctypes.c_int32), ("true_history_len", ctypes.c_int32),
                 ("true_history", ctypes.c_void_p), ("layout", ctypes.c_int32),
-                ("kernel_events_len", ctypes.c_int32), ("kernel_events", ctypes.POINTER(ctypes.c_void_p))]
+                ("kernel_events_len", ctypes.c_int32), ("kernel_events", ctypes.POINTER(ctypes.c_void_p)),
+                ("exact_rows", ctypes.c_int32)]
 
 
 class PbcgInfo(ctypes.Structure):
@@ -69,13 +70,14 @@ class PbcgVectors(ctypes.Structure):
 
 
 EXPORTS = [
-    "csr_spmv", "csr_spmv_config", "csr_spmv_f32", "csr_jacobi", "csr_slice_workspace_bytes", "csr_slice",
+    "csr_spmv", "csr_spmv_exact", "csr_spmv_config", "csr_spmv_f32", "csr_jacobi", "csr_slice_workspace_bytes", "csr_slice",
     "csr_spmv_sliced", "csr_spmv_f32_sliced", "exdot_workspace_bytes", "exdot", "exdot_config",
     "exdot_noalloc_scratch_bytes", "exdot_noalloc", "plain_dot_workspace_bytes", "plain_dot",
     "pbcg_phase_workspace_bytes", "pbcg_phase_a", "pbcg_phase_b", "pbicgstab_workspace_bytes",
     "pbicgstab_solve", "pbcg_default_opts", "pbcg_status_string", "pbcg_abi_version",
     "spai_param_count", "spai_workspace_bytes", "spai_features", "spai_forward", "spai_infer_bf16",
-    "spai_probe_product", "spai_loss_grad", "spai_adam", "spai_train_step",
+    "spai_probe_product", "spai_loss_grad", "spai_adam", "spai_train_step", "spai_probe_column_workspace_bytes",
+    "spai_probe_column",
 ]
 
 _lib = None
@@ -93,6 +95,7 @@ def lib():
     CP = ctypes.POINTER(PbcgCsr)
     sig = {
         "csr_spmv": (ctypes.c_int, [CP, _P, _P, _P]),
+        "csr_spmv_exact": (ctypes.c_int, [CP, _P, _P, _P]),
         "csr_spmv_config": (ctypes.c_int, [CP, _P, _P, i32, _P]),
         "csr_spmv_f32": (ctypes.c_int, [CP, _P, _P, _P]),
         "csr_jacobi": (ctypes.c_int, [CP, _P, i32, _P]),
@@ -122,6 +125,8 @@ def lib():
         "spai_forward": (ctypes.c_int, [i64, _P, _P, _P, _P, _P, _P, _P, _P]),
         "spai_infer_bf16": (ctypes.c_int, [i64, _P, _P, _P, _P, _P, _P]),
         "spai_probe_product": (ctypes.c_int, [CP, _P, i32, _P, _P]),
+        "spai_probe_column_workspace_bytes": (sz, [i32]),
+        "spai_probe_column": (ctypes.c_int, [i32, _P, _P, _P, sz, _P]),
         "spai_loss_grad": (ctypes.c_int, [CP, _P, _P, _P, _P, _P, _P, i32, _P, _P, _P, _P, sz, _P]),
         "spai_adam": (ctypes.c_int, [_P, _P, _P, _P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, _P]),
@@ -251,6 +256,15 @@ def csr_spmv(A: CSR, x, y=None, kind: int | None = None):
         _check(lib().csr_spmv(A.c, _ptr(x), _ptr(y), _stream()), "csr_spmv")
     else:
         _check(lib().csr_spmv_config(A.c, _ptr(x), _ptr(y), int(kind), _stream()), "csr_spmv_config")
+    return y
+
+
+def csr_spmv_exact(A: CSR, x, y=None):
+    """y = A x with every row summed exactly and rounded once."""
+    torch = _torch()
+    if y is None:
+        y = torch.empty(A.n, dtype=torch.float64, device=x.device)
+    _check(lib().csr_spmv_exact(A.c, _ptr(x), _ptr(y), _stream()), "csr_spmv_exact")
     return y
 
 
@@ -455,3 +469,9 @@ def solve(A: CSR, b, x0=None, M: CSR | None = None, history: int = 0, **opts):
         th = s.true_history.cpu().numpy()
         info["true_history"] = th[~np.isnan(th)]
     return x, info
+
+
+def read_matrix_market(src):
+    """Square coordinate Matrix Market file -> host CSR (see paper_2404_13216_amd.mtx)."""
+    from .mtx import read_matrix_market as _r
+    return _r(src)

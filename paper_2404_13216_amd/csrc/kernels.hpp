@@ -184,6 +184,7 @@ struct Sliced {
     const int32_t* col = nullptr;   // 32-bit columns, or (SL_D16) 16-bit residuals
     const VT* val = nullptr;
     const int32_t* base = nullptr;  // SL_D16: per slice and position, at off[c] / 256 + k
+    const int32_t* perm = nullptr;  // SL_PERM: the row held by each slot (slice height 64)
 };
 
 constexpr int SLICE_UNROLL = 8;   // entries of a row loaded ahead of their additions
@@ -198,6 +199,14 @@ static_assert(64 % SLICE_UNROLL == 0, "the base broadcast covers whole unrolled 
 // slice's rows (every residual of the matrix fits in 16 bits): two bytes per entry less
 // than 32-bit columns.  On a stencil each position holds one or two neighbour offsets.
 constexpr int SL_NT = 1, SL_D16 = 2;
+// SL_PERM: the row-sorted copy for matrices of irregular row lengths (random sparsity):
+// slices of 64 rows (one wavefront), the rows of each window of WSORT consecutive rows
+// ordered by decreasing length (ties: ascending row) so that a slice holds rows of nearly
+// equal length; slot j of the order holds row perm[j], and entry k of slot 64c + t sits at
+// off[c] + 64 k + t.  Each lane still sums its own row left to right in storage order.
+constexpr int SL_PERM = 4;
+constexpr int WS_ROWS = 64;
+constexpr int WSORT = 4096;
 
 template <class VT, class XT, class AT, bool COMP, int SLF = 0>
 __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, int len, const XT* __restrict__ x,
@@ -269,6 +278,59 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
     }
 }
 
+// One lane's row (len entries) in wave slice ws of a row-sorted copy.  Loads are masked by
+// the row's own length, so a slice's padding is never fetched; the x gathers are issued
+// without branches (a slot past the row end reads x[0] and is not added).
+template <class VT, class XT, class AT, bool COMP, int SLF>
+__device__ __forceinline__ void wslice_row(const Sliced<VT>& sl, int ws, int lane, int len,
+                                           const XT* __restrict__ x, AT& s, AT& cmp) {
+    constexpr int U = SLICE_UNROLL, R = WS_ROWS;
+    constexpr bool MNT = (SLF & SL_NT) != 0;
+    const int64_t base = sl.off[ws];
+    const int w = (int)((sl.off[ws + 1] - base) / R);
+    const VT* __restrict__ vp = sl.val + base + lane;
+    const int32_t* __restrict__ cp = sl.col + base + lane;
+    for (int k0 = 0; k0 < w; k0 += U) {
+        VT av[U];
+        int32_t cv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            av[u] = VT(0);
+            cv[u] = 0;
+            if (k0 + u < len) {
+                const int64_t o = (int64_t)(k0 + u) * R;
+                if constexpr (MNT) {
+                    av[u] = __builtin_nontemporal_load(vp + o);
+                    cv[u] = __builtin_nontemporal_load(cp + o);
+                } else {
+                    av[u] = vp[o];
+                    cv[u] = cp[o];
+                }
+            }
+        }
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[cv[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u < len) {
+                const AT a = (AT)av[u], xx = (AT)xv[u];
+                const AT prod = a * xx;
+                if constexpr (COMP) {
+                    const float pe = fmaf(a, xx, -prod);
+                    const float sn = s + prod;
+                    const float bb = sn - s;
+                    const float err = (s - (sn - bb)) + (prod - bb);
+                    s = sn;
+                    cmp = cmp + (err + pe);
+                } else {
+                    s = s + prod;
+                }
+            }
+        }
+    }
+}
+
 // Row-sequential SpMV engine (persistent, product-staged).
 //
 // Rows are taken in chunks of R = blockDim.x rows, one row per lane, and every row is
@@ -318,6 +380,19 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
     }
     const int t = threadIdx.x;
     for (int c = cbeg + bi; c < cend; c += gper) {
+        if constexpr (SL && (SLF & SL_PERM) != 0) {
+            // row-sorted copy: chunk c is wave slices 4c .. 4c + 3 (slots 256c ..)
+            const int slot = c * R + t;
+            if (slot < n) {
+                const int prow = sl.perm[slot];
+                const int pa = rp[prow], pb = rp[prow + 1];
+                AT s = AT(0), cmp = AT(0);
+                wslice_row<VT, XT, AT, COMP, SLF>(sl, slot / WS_ROWS, t % WS_ROWS, pb - pa, x, s, cmp);
+                if constexpr (COMP) s = s + cmp;
+                body(prow, s);
+            }
+            continue;
+        }
         const int r0 = c * R, r1 = min(r0 + R, n), row = r0 + t;
         int RA = 0, RB = 0;
         if (row < r1) { RA = rp[row]; RB = rp[row + 1]; }
@@ -513,6 +588,84 @@ __global__ void __launch_bounds__(256) slice_fill_kernel(int n, const int32_t* _
     }
 }
 
+// Row-sorted copy, step 1: perm over each window of WSORT rows, by decreasing row length
+// (ties: ascending row), one block of 1024 threads per window (bitonic sort in LDS of the
+// keys (INT_MAX - len) << 32 | local row, which are distinct).
+__global__ void __launch_bounds__(1024) wslice_sort_kernel(int n, const int32_t* __restrict__ rp,
+                                                           int32_t* __restrict__ perm) {
+    __shared__ unsigned long long key[WSORT];
+    const int r0 = blockIdx.x * WSORT;
+    for (int j = threadIdx.x; j < WSORT; j += blockDim.x) {
+        const int r = r0 + j;
+        key[j] = r < n ? ((unsigned long long)(uint32_t)(0x7fffffff - (rp[r + 1] - rp[r])) << 32) | (uint32_t)j
+                       : ~0ull;
+    }
+    __syncthreads();
+    for (int k = 2; k <= WSORT; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < WSORT; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = threadIdx.x; j < WSORT; j += blockDim.x) {
+        const int r = r0 + j;
+        if (r < n) perm[r] = r0 + (int)(uint32_t)(key[j] & 0xffffffffull);
+    }
+}
+
+// Step 2: off[c + 1] = 64 * (longest row of wave slice c), off[0] = 0 (blocks of 256 = 4
+// slices; nws slices in all).
+__global__ void __launch_bounds__(256) wslice_width_kernel(int n, int nws, const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ perm,
+                                                           int64_t* __restrict__ off) {
+    const int slot = blockIdx.x * 256 + threadIdx.x;
+    const int ws = slot / WS_ROWS;
+    int len = 0;
+    if (slot < n) {
+        const int r = perm[slot];
+        len = rp[r + 1] - rp[r];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o));
+    if ((threadIdx.x & 63) == 0 && ws < nws) off[ws + 1] = (int64_t)WS_ROWS * len;
+    if (slot == 0) off[0] = 0;
+}
+
+// Step 3 (after the scan): copy every row into its slot, column-major per wave slice.
+template <class VT>
+__global__ void __launch_bounds__(256) wslice_fill_kernel(int n, int nws, const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci,
+                                                          const VT* __restrict__ val,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int64_t* __restrict__ off,
+                                                          int32_t* __restrict__ scol, VT* __restrict__ sval) {
+    const int slot = blockIdx.x * 256 + threadIdx.x;
+    const int ws = slot / WS_ROWS, lane = slot % WS_ROWS;
+    if (ws >= nws) return;
+    const int64_t base = off[ws];
+    const int w = (int)((off[ws + 1] - base) / WS_ROWS);
+    int a = 0, len = 0;
+    if (slot < n) {
+        const int r = perm[slot];
+        a = rp[r];
+        len = rp[r + 1] - a;
+    }
+    for (int k = 0; k < w; ++k) {
+        const int64_t i = base + (int64_t)k * WS_ROWS + lane;
+        scol[i] = k < len ? ci[a + k] : 0;
+        sval[i] = k < len ? val[a + k] : VT(0);
+    }
+}
+
 // ----------------------------------------------------------------------------- dot sites
 #define XD_SHARED(D)                                   \
     __shared__ unsigned long long sh_acc[(D) * xd::NCH]; \
@@ -648,6 +801,189 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
 }
+
+// ----------------------------------------------------------------------------- exact rows
+// Exactly rounded SpMV rows: every row's sum is formed exactly and rounded once to nearest
+// even -- the reproducible-reduction idea (exact accumulation, one rounding) applied to the
+// rows of A x, so y no longer depends on any summation order.  16 lanes (one DPP row of
+// the wave) take one matrix row: each lane deposits its products as exact integers
+// (TwoProd is not needed: the 106-bit product goes straight into the row's long
+// accumulator of 32-bit chunks in LDS, integer additions commute), the group finds the
+// chunk range it touched, and its leader rounds the range once (the exact dot's
+// rounding).  RESID: the row value is b_i - (A x)_i as one exact sum (b_i enters as a
+// term), rounded once.
+constexpr int XR_GROUP = 16;                   // lanes per matrix row
+constexpr int XR_ROWS = 256 / XR_GROUP;        // rows in flight per 256-thread block
+constexpr int XR_SMEM = XR_ROWS * xd::NCH * 8 + XR_ROWS * 4;
+
+__device__ __forceinline__ int xr_row_max(int v) { return -xd::row_min_i(-v); }
+
+__device__ __forceinline__ void xr_flag_nonfinite(uint32_t* flag, double a, double x) {
+    uint32_t f;
+    if (isnan(a) || isnan(x) || a == 0.0 || x == 0.0) f = xd::F_NAN;
+    else f = ((a > 0.0) == (x > 0.0)) ? xd::F_PINF : xd::F_NINF;
+    atomicOr(flag, f);
+}
+
+// One row per 16-lane group (row < 0: the group idles).  acc: the group's NCH chunks, zero
+// on entry and zero again on return; flag: the group's non-finite flags (likewise).  All
+// 64 lanes of the wave call it together; the group leader (gl == 0) gets the value.
+template <class VT, bool RESID>
+__device__ __forceinline__ double exact_row(int row, const int32_t* __restrict__ rp,
+                                            const int32_t* __restrict__ ci, const VT* __restrict__ val,
+                                            const double* __restrict__ x, const double* __restrict__ b,
+                                            unsigned long long* acc, uint32_t* flag, int gl) {
+    int lo = INT_MAX, hi = -1;
+    if (row >= 0) {
+        const int a = rp[row], e = rp[row + 1];
+        for (int k = a + gl; k < e; k += XR_GROUP) {
+            const double av = (double)val[k], xv = x[ci[k]];
+            if (!(isfinite(av) && isfinite(xv))) {
+                xr_flag_nonfinite(flag, RESID ? -av : av, xv);
+            } else if (av != 0.0 && xv != 0.0) {
+                uint64_t m;
+                int Pa, Px;
+                bool ng;
+                xd::decompose(av, m, Pa, ng);
+                xd::decompose(xv, m, Px, ng);
+                const int c = (Pa + Px - xd::BIAS) >> 5;     // lowest chunk of the product
+                lo = min(lo, c);
+                hi = max(hi, c + 4);
+                xd::deposit_product(acc, RESID ? -av : av, xv);
+            }
+        }
+        if constexpr (RESID) {
+            if (gl == 0) {
+                const double bv = b[row];
+                if (!isfinite(bv)) {
+                    xr_flag_nonfinite(flag, bv, 1.0);
+                } else if (bv != 0.0) {
+                    uint64_t m;
+                    int P;
+                    bool ng;
+                    xd::decompose(bv, m, P, ng);
+                    lo = min(lo, P >> 5);
+                    hi = max(hi, (P >> 5) + 2);
+                    xd::deposit_double(acc, bv);
+                }
+            }
+        }
+    }
+    lo = xd::row_min_i(lo);
+    hi = xr_row_max(hi);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    double v = 0.0;
+    if (gl == 0 && row >= 0) v = xd::round_chunks((long long*)acc, *flag, lo, min(hi, xd::NCH - 1));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    // clear what the row touched (the rounding's carries stop at most one chunk above hi)
+    if (lo <= hi)
+        for (int c = lo + gl; c <= min(hi + 2, xd::NCH - 1); c += XR_GROUP) acc[c] = 0ull;
+    if (gl == 0) *flag = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    return v;
+}
+
+// y = A x with exactly rounded rows (RESID: r = b - A x, each row rounded once), epilogue
+// epi(row, value) on the group leader; block 0 may carry a finalize role.
+template <class VT, class Epi, class Fin, bool RESID>
+__global__ void __launch_bounds__(256)
+spmv_exact_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                  const VT* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
+                  Epi epi, Fin fin, const int* halt) {
+    if (halt && *halt) return;
+    constexpr int SMEM = Fin::SMEM > XR_SMEM ? Fin::SMEM : XR_SMEM;
+    __shared__ __align__(16) unsigned char smem[SMEM];
+    int bfirst = 0;
+    if constexpr (Fin::D > 0) {
+        if (blockIdx.x == 0) {
+            fin.run(smem);
+            return;
+        }
+        bfirst = 1;
+    }
+    unsigned long long* accs = (unsigned long long*)smem;
+    uint32_t* flags = (uint32_t*)(smem + XR_ROWS * xd::NCH * 8);
+    for (int i = threadIdx.x; i < XR_ROWS * xd::NCH; i += blockDim.x) accs[i] = 0ull;
+    if (threadIdx.x < XR_ROWS) flags[threadIdx.x] = 0u;
+    __syncthreads();
+    const int g = threadIdx.x / XR_GROUP, gl = threadIdx.x % XR_GROUP;
+    const int G = (int)gridDim.x - bfirst;
+    const int steps = (n + XR_ROWS - 1) / XR_ROWS;
+    for (int st = (int)blockIdx.x - bfirst; st < steps; st += G) {   // uniform over the block
+        const int row = st * XR_ROWS + g;
+        const double v = exact_row<VT, RESID>(row < n ? row : -1, rp, ci, val, x, b, accs + g * xd::NCH,
+                                               flags + g, gl);
+        if (gl == 0 && row < n) epi(row, v);
+    }
+}
+
+// The same with D exact dots of the rows' values in the epilogue (the true residual and
+// its norm): epi.row(row, value, xa, ya) as in the row-sequential dot kernels.
+template <int D, int K, class VT, class Epi, bool RESID>
+__global__ void __launch_bounds__(256)
+spmv_exact_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                      const VT* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
+                      Epi epi, xd::Site site, const int* halt) {
+    if (halt && *halt) return;
+    XD_SHARED(D)
+    __shared__ __align__(16) unsigned char smem[XR_SMEM];
+    xd::block_init<D>(sh_acc, sh_flags);
+    epi.load();
+    unsigned long long* accs = (unsigned long long*)smem;
+    uint32_t* flags = (uint32_t*)(smem + XR_ROWS * xd::NCH * 8);
+    for (int i = threadIdx.x; i < XR_ROWS * xd::NCH; i += blockDim.x) accs[i] = 0ull;
+    if (threadIdx.x < XR_ROWS) flags[threadIdx.x] = 0u;
+    __syncthreads();
+    double e[D][K];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int k = 0; k < K; ++k) e[d][k] = 0.0;
+    const int g = threadIdx.x / XR_GROUP, gl = threadIdx.x % XR_GROUP;
+    const int steps = (n + XR_ROWS - 1) / XR_ROWS;
+    for (int st = blockIdx.x; st < steps; st += gridDim.x) {
+        const int row = st * XR_ROWS + g;
+        const double v = exact_row<VT, RESID>(row < n ? row : -1, rp, ci, val, x, b, accs + g * xd::NCH,
+                                               flags + g, gl);
+        if (gl == 0 && row < n) {
+            double xa[D], ya[D];
+            epi.row(row, v, xa, ya);
+#pragma unroll
+            for (int d = 0; d < D; ++d) xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+        }
+    }
+    __syncthreads();
+    xd::block_flush<D, K>(e, sh_acc);
+    xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
+}
+
+// epilogues taking the exactly rounded residual row r (not A x)
+template <class T>
+struct EpiResidX {          // r (and copies c1, c2 at initialisation)
+    T* r;
+    T* c1;
+    T* c2;
+    __device__ __forceinline__ void operator()(int row, T v) const {
+        r[row] = v;
+        if (c1) c1[row] = v;
+        if (c2) c2[row] = v;
+    }
+};
+template <class Fin>
+struct EpiResidXDot {       // r and the dot (r, r)
+    double* res;
+    Fin fin;
+    __device__ __forceinline__ void load() {}
+    __device__ __forceinline__ void row(int i, double v, double (&xa)[1], double (&ya)[1]) {
+        res[i] = v;
+        xa[0] = v;
+        ya[0] = v;
+    }
+    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
+};
 
 // ----------------------------------------------------------------------------- FP32 plain dots
 

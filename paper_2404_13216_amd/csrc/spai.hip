@@ -365,6 +365,15 @@ __global__ void __launch_bounds__(BLOCK) k_adam(float* __restrict__ p, float* __
     p[e] = p[e] - lr * mh / (sqrtf(vh) + eps);
 }
 
+// ------------------------------------------------------------------ probe columns
+// out[i] = fp32(r_i / sqrt(rr)) with rr the exact (r, r) rounded once; zero column if rr = 0
+__global__ void __launch_bounds__(BLOCK) k_probe_column(int n, const double* __restrict__ r,
+                                                        const double* __restrict__ rr, float* __restrict__ out) {
+    const double nrm = sqrt(*rr);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[i] = nrm > 0.0 ? (float)(r[i] / nrm) : 0.0f;
+}
+
 // ------------------------------------------------------------------ bf16 MFMA inference
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -551,6 +560,22 @@ int spai_infer_bf16(int64_t nnz, const float* feat, const float* params, const i
     const int64_t tiles = (nnz + 15) / 16;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
     k_infer_bf16<<<grid, 256, 0, s>>>(nnz, feat, params, rowidx, diag, m_out);
+    HIPCHK(hipGetLastError());
+    return PBCG_OK;
+}
+
+size_t spai_probe_column_workspace_bytes(int32_t n) {
+    return n < 0 ? 0 : 256 + exdot_workspace_bytes((int64_t)n) + 256;
+}
+
+int spai_probe_column(int32_t n, const double* r, float* out, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 1 || !r || !out) return PBCG_ERR_INVALID;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < spai_probe_column_workspace_bytes(n)) return PBCG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    double* nrm2 = (double*)ws;
+    const int rc = exdot((int64_t)n, r, r, nrm2, (char*)ws + 256, ws_bytes - 256, stream);
+    if (rc != PBCG_OK) return rc;
+    k_probe_column<<<grid_for(n), BLOCK, 0, s>>>(n, r, nrm2, out);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }

@@ -62,13 +62,12 @@ class SpaiMatrix:
         m = self.m_bf16(params) if bf16 else self.m_fp32(params)
         return self.A.with_values(m)
 
-    def probe_product(self, V):
+    def probe_product(self, Vc, k):
+        """U = A V for a column-major probe block Vc (k x n float32, row j = column j)."""
         torch = _torch()
-        k = V.shape[1]
-        Vc = V.t().contiguous()  # column-major n x k
         U = torch.empty_like(Vc)
-        _check(lib().spai_probe_product(self.A.c, _ptr(Vc), k, _ptr(U), _stream()), "spai_probe_product")
-        return Vc, U
+        _check(lib().spai_probe_product(self.A.c, _ptr(Vc), int(k), _ptr(U), _stream()), "spai_probe_product")
+        return U
 
     def train_step(self, params, m, v, Vc, U, k, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, loss=None):
         """One fused training step (loss/gradient then Adam) via spai_train_step;
@@ -146,17 +145,23 @@ def load_params(path: str, device="cuda"):
 
 def probe_block(A: CSR, b, seed: int, k_rad=4, steps=(1, 4, 16, 64)):
     """V = [Rademacher columns | r_i / ||r_i|| of plain p-BiCGStab at the given iterations]
-    as an n x k torch tensor (float32).  Residuals come from the GPU solver (r_out)."""
+    as a column-major k x n float32 tensor (row j = column j of V).  The Rademacher
+    columns are seeded input draws; the residuals come from the GPU solver (r_out) and are
+    normalised and rounded by spai_probe_column."""
     torch = _torch()
     from synthgen import rademacher
     dev = A.val.device
-    cols = [torch.from_numpy(rademacher(A.n, k_rad, seed)).to(dev)]
+    k = k_rad + len(steps)
+    Vc = torch.empty((k, A.n), dtype=torch.float32, device=dev)
+    Vc[:k_rad] = torch.from_numpy(np.ascontiguousarray(rademacher(A.n, k_rad, seed).T.astype(np.float32))).to(dev)
     r = torch.empty(A.n, dtype=torch.float64, device=dev)
-    for s in steps:
+    ws = _workspace(lib().spai_probe_column_workspace_bytes(A.n), dev)
+    for j, s in enumerate(steps):
         sv = Solver(A, tol=0.0, max_iter=int(s))
         sv.solve(b, None, r_out=r)
-        cols.append((r / torch.linalg.vector_norm(r)).unsqueeze(1).clone())
-    return torch.cat(cols, dim=1).to(torch.float32)
+        _check(lib().spai_probe_column(A.n, _ptr(r), _ptr(Vc[k_rad + j]), _ptr(ws), ws.numel(), _stream()),
+               "spai_probe_column")
+    return Vc
 
 
 def train(problems, epochs=30, lr=1e-3, seed=0, device="cuda", log=None):
@@ -173,19 +178,17 @@ def train(problems, epochs=30, lr=1e-3, seed=0, device="cuda", log=None):
         A = CSR.from_host(p.A, device)
         sm = SpaiMatrix(A, ws=ws)
         b = torch.from_numpy(p.b).to(device)
-        V = probe_block(A, b, seed=1000 + int(p.meta.get("seed", 0)))
-        Vc, U = sm.probe_product(V)
-        data.append((sm, Vc, U, V.shape[1]))
+        Vc = probe_block(A, b, seed=1000 + int(p.meta.get("seed", 0)))
+        U = sm.probe_product(Vc, Vc.shape[0])
+        data.append((sm, Vc, U, Vc.shape[0]))
     hist = []
     t = 0
     for ep in range(epochs):
-        tot = 0.0
         losses = torch.empty(len(data), dtype=torch.float32, device=device)
         for j, (sm, Vc, U, k) in enumerate(data):
             t += 1
             sm.train_step(params, m, v, Vc, U, k, t, lr=lr, loss=losses[j:j + 1])
-        tot = float(losses.sum().item())
-        hist.append(tot / len(data))
+        hist.append(float(np.mean(losses.cpu().numpy().astype(np.float64))))   # host-side reporting
         if log:
             log(f"epoch {ep}: mean loss {hist[-1]:.5e}")
     return params, hist

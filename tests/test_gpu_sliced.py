@@ -48,12 +48,26 @@ def max_spread(A):
     return int((np.maximum.reduceat(dv, starts) - np.minimum.reduceat(dv, starts)).max())
 
 
-def expect_sliced_bits(A):
-    """info['sliced'] of a solve with layout AUTO: bit 0 when A's sliced copy is built,
-    bit 2 when its column entries are 16-bit residuals."""
-    if not expect_built(A):
-        return 0
-    return 1 | (4 if max_spread(A) <= 65535 else 0)
+def sorted_entries(A):
+    """Host count of the row-sorted copy's size: rows ordered by decreasing length within
+    windows of 4096, then 64 x the longest row of every group of 64 consecutive slots."""
+    lens = np.diff(A.row_ptr.astype(np.int64))
+    order = np.concatenate([np.sort(lens[a:a + 4096])[::-1] for a in range(0, A.n, 4096)] +
+                           [np.zeros(0, dtype=np.int64)])
+    nws = (A.n + 63) // 64
+    lp = np.zeros(nws * 64, dtype=np.int64)
+    lp[:A.n] = order
+    return int(64 * lp.reshape(nws, 64).max(axis=1).sum()) if nws else 0
+
+
+def expect_sliced_bits(A, layout=None):
+    """info['sliced'] of a solve with layout AUTO (or SORTED): bit 0 when a copy of A is
+    built, bit 2 when its column entries are 16-bit residuals, bit 4 when it is the
+    row-sorted copy (AUTO: when the 256-row copy's padding is too large)."""
+    cap = A.nnz + A.nnz // 8 + 256
+    if layout != pk.LAYOUT_SORTED:
+        return (1 | (4 if max_spread(A) <= 65535 else 0)) if expect_built(A) else 0
+    return (1 | 16) if sorted_entries(A) <= cap else 0
 
 
 def with_long_range_entry(A, value):
@@ -239,3 +253,63 @@ def test_solve_ragged_16bit_residuals(name):
     ora = ctier.pbicgstab(Ah, bh, tol=1e-10, max_iter=8)
     assert ora["iterations"] == ia["iterations"]
     assert np.array_equal(xa.cpu().numpy().view(np.uint64), ora["x"].view(np.uint64))
+
+
+def sorted_cases():
+    rng = np.random.default_rng(12)
+    out = [(n, a) for n, a in cases() if n in ("ragged_1000", "tiny_37", "ragged_unbuilt", "one_long_row")]
+    lens = rng.integers(0, 300, 2 * 4096 + 37)              # two sort windows and a ragged third
+    lens[::13] = 0
+    out.append(("windows_8229", ragged(2 * 4096 + 37, lens, 13)))
+    out.append(("rand_50000", g.problem("rand_1m", scale=50000).A))
+    out.append(("cd2d_64", g.problem("cd2d_64").A))
+    return out
+
+
+@pytest.mark.parametrize("name,A0", sorted_cases(), ids=[c[0] for c in sorted_cases()])
+def test_solve_row_sorted_bitwise(name, A0):
+    """The row-sorted copy (64-row slices of rows ordered by length within windows of 4096
+    rows, a permutation back to the row order): ragged windows, empty rows, one very long
+    row; the same bits as on CSR and as the oracle, FP64 and FP32 refinement."""
+    Ah = dominant(A0)
+    want = expect_sliced_bits(Ah, pk.LAYOUT_SORTED)
+    # one row of 1500 entries pads its 64-row slice past nnz + nnz/8 + 256: CSR is kept
+    assert want == (0 if name == "one_long_row" else 17), (name, sorted_entries(Ah), Ah.nnz)
+    xs = np.random.default_rng(9).uniform(-1, 1, Ah.n)
+    bh = spmv(Ah, xs)
+    A = pk.CSR.from_host(Ah)
+    b = to_dev(bh)
+    xa, ia = pk.solve(A, b, tol=1e-10, max_iter=8, layout=pk.LAYOUT_SORTED)
+    xc, ic = pk.solve(A, b, tol=1e-10, max_iter=8, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == want and ic["sliced"] == 0
+    assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+    ora = ctier.pbicgstab(Ah, bh, tol=1e-10, max_iter=8)
+    assert ora["iterations"] == ia["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), ora["x"].view(np.uint64))
+    # to convergence, and the FP32 refinement (Dot2 FP32 SpMV on the sorted copy)
+    for prec in (pk.PREC_FP64, pk.PREC_FP32_IR):
+        xa, ia = pk.solve(A, b, tol=1e-10, prec=prec, layout=pk.LAYOUT_SORTED)
+        xc, ic = pk.solve(A, b, tol=1e-10, prec=prec, layout=pk.LAYOUT_CSR)
+        for k in ("status", "iterations", "outer_iterations", "true_checks"):
+            assert ia[k] == ic[k], (prec, k)
+        assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64)), prec
+
+
+def test_row_sorted_preconditioner():
+    """SORTED on the random family (the 256-row copy would need 4.5x padding), for A and
+    for an M on A's pattern; same bits as on CSR (which AUTO keeps there)."""
+    p = g.problem("rand_1m", scale=30000)
+    assert not expect_built(p.A) and expect_sliced_bits(p.A) == 0
+    assert expect_sliced_bits(p.A, pk.LAYOUT_SORTED) == 17
+    A = pk.CSR.from_host(p.A)
+    b = to_dev(p.b)
+    d = 1.0 / p.A.diag()
+    rows = np.repeat(np.arange(p.A.n), np.diff(p.A.row_ptr))
+    mv = np.where(rows == p.A.col_idx, d[rows], 1e-3 * d[rows])
+    M = A.with_values(to_dev(mv))
+    xa, ia = pk.solve(A, b, M=M, tol=1e-10, max_iter=40, layout=pk.LAYOUT_SORTED)
+    xc, ic = pk.solve(A, b, M=M, tol=1e-10, max_iter=40, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == 1 | 2 | 16 | 32 and ic["sliced"] == 0
+    assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))

@@ -84,8 +84,8 @@ def test_loss_grad_and_adam_step(mat):
     rng = np.random.default_rng(5)
     V = np.concatenate([g.rademacher(A.n, 4, 9), rng.standard_normal((A.n, 4))], axis=1).astype(np.float32)
     th = rand_params(6).astype(np.float32)
-    Vd = torch.from_numpy(V).cuda()
-    Vc, U = sm.probe_product(Vd)
+    Vc = torch.from_numpy(np.ascontiguousarray(V.T)).cuda()    # column-major n x k
+    U = sm.probe_product(Vc, 8)
     p = torch.from_numpy(th).cuda()
     loss, grad = sm.loss_grad(p, Vc, U, 8)
     L, gref = ospai.loss_and_grad(A, th.astype(np.float64), V.astype(np.float64))
@@ -102,8 +102,8 @@ def test_loss_grad_and_adam_step(mat):
 
 def test_gradient_deterministic(mat):
     sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
-    V = torch.from_numpy(g.rademacher(mat.A.n, 8, 1).astype(np.float32)).cuda()
-    Vc, U = sm.probe_product(V)
+    Vc = torch.from_numpy(np.ascontiguousarray(g.rademacher(mat.A.n, 8, 1).T.astype(np.float32))).cuda()
+    U = sm.probe_product(Vc, 8)
     p = torch.from_numpy(rand_params(7).astype(np.float32)).cuda()
     g1 = sm.loss_grad(p, Vc, U, 8)[1].cpu().numpy()
     g2 = sm.loss_grad(p, Vc, U, 8)[1].cpu().numpy()
@@ -133,8 +133,8 @@ def test_trained_preconditioner_gains(capsys):
 def test_train_step_equals_loss_grad_then_adam(mat):
     """spai_train_step = spai_loss_grad followed by spai_adam, bit for bit."""
     sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
-    V = torch.from_numpy(g.rademacher(mat.A.n, 8, 2).astype(np.float32)).cuda()
-    Vc, U = sm.probe_product(V)
+    Vc = torch.from_numpy(np.ascontiguousarray(g.rademacher(mat.A.n, 8, 2).T.astype(np.float32))).cuda()
+    U = sm.probe_product(Vc, 8)
     p0 = torch.from_numpy(rand_params(9).astype(np.float32)).cuda()
     pa, pb = p0.clone(), p0.clone()
     ma, va = torch.zeros_like(p0), torch.zeros_like(p0)
@@ -146,3 +146,24 @@ def test_train_step_equals_loss_grad_then_adam(mat):
         assert loss_a.item() == loss_b.item()
     assert torch.equal(pa.view(torch.int32), pb.view(torch.int32))
     assert torch.equal(ma.view(torch.int32), mb.view(torch.int32))
+
+
+def test_probe_block_vs_oracle():
+    """The training probe block: Rademacher columns as drawn, residual columns
+    r_i / ||r_i|| (norm from the exact dot, rounded to FP32 once) bit for bit against the
+    oracle's probe block (the GPU residuals are bit-identical to the oracle's)."""
+    p = g.problem("spai_eval_128", scale=12)
+    A = pk.CSR.from_host(p.A)
+    Vc = spai.probe_block(A, to_dev(p.b), seed=77).cpu().numpy()
+    ref = ospai.probe_block(p.A, p.b, seed=77).astype(np.float32)
+    assert Vc.shape == (8, p.A.n)
+    assert np.array_equal(Vc.view(np.uint32), np.ascontiguousarray(ref.T).view(np.uint32))
+    # a zero residual gives a zero column
+    z = torch.zeros(5, dtype=torch.float64, device="cuda:0")
+    out = torch.full((5,), 7.0, dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(pk.lib().spai_probe_column_workspace_bytes(5), dtype=torch.uint8, device="cuda:0")
+    import ctypes
+    rc = pk.lib().spai_probe_column(5, ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0 and not out.any()

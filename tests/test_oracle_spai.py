@@ -142,3 +142,16 @@ def test_training_reduces_loss(small):
         L, gr = spai.loss_and_grad(A, th, V)
         th, m, v = spai.adam_step(th, gr, m, v, t, lr=3e-3)
     assert spai.loss_and_grad(A, th, V)[0] < 0.9 * L0
+
+
+def test_probe_block_hand_worked():
+    """A = diag(1, 2), b = (1, 1): the first p-BiCGStab iteration gives alpha = 2/3,
+    q = (1/3, -1/3), y = A q, omega = (q, y)/(y, y) = 3/5 and r_1 = q - omega y =
+    (2/15, 1/15), so the residual probe column is (2, 1)/sqrt(5); the Rademacher
+    columns hold +-1 only."""
+    A = g.CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 2.0]))
+    V = spai.probe_block(A, np.array([1.0, 1.0]), seed=3, k_rad=2, steps=(1,))
+    assert V.shape == (2, 3)
+    assert set(np.unique(V[:, :2]).tolist()) <= {-1.0, 1.0}
+    expect = np.array([2.0, 1.0]) / math.sqrt(5.0)
+    assert np.allclose(V[:, 2], expect, rtol=8 * 2.0 ** -53, atol=0)   # a few roundings
