@@ -183,18 +183,21 @@ def converged(f):
 
 def precision_forms(pk, torch, A, b, xs, x64, forms, reps):
     """FP32 refinement with reliable updates at the default update threshold (0.1) and at
-    1e-5, each with its error against the plain FP64 solution and x*, beside the FP64
-    forms.  speedup_vs_fp64 compares with plain FP64 p-BiCGStab and is null when that
+    1e-5, and the FP32-matrix form (FP32 values, FP64 vectors, replacement against the
+    FP64 A every 50 iterations), each with its error against the plain FP64 solution and
+    x*, beside the FP64 forms.  speedup_vs_fp64 compares with plain FP64 p-BiCGStab and is null when that
     solve did not reach 1e-10; speedup_vs_fastest_fp64 compares with the fastest FP64
     form that did."""
     ok = {k: v for k, v in forms.items() if converged(v)}
     fastest = min(ok, key=lambda k: ok[k]["seconds"]) if ok else None
     t64 = forms["pbicgstab_fp64"]["seconds"] if converged(forms["pbicgstab_fp64"]) else None
     out = {}
-    for key, itol in (("fp32_ir", None), ("fp32_ir_inner_1e-5", 1e-5)):
+    for key, itol in (("fp32_ir", None), ("fp32_ir_inner_1e-5", 1e-5), ("fp32_matrix", None)):
         kw = {} if itol is None else {"inner_tol": itol}
-        ti, ii, xi = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, prec=pk.PREC_FP32_IR, **kw)
-        out[key] = {"seconds": ti, "inner_tol": itol or 0.1, "inner_iterations": ii["iterations"],
+        prec = pk.PREC_FP32_MATRIX if key == "fp32_matrix" else pk.PREC_FP32_IR
+        ti, ii, xi = timed_solve(pk, torch, A, b, reps, tol=1e-10, max_iter=10000, prec=prec, **kw)
+        out[key] = {"seconds": ti, "inner_tol": (itol or 0.1) if prec == pk.PREC_FP32_IR else None,
+                    "inner_iterations": ii["iterations"],
                     "outer": ii["outer_iterations"], "fell_back_to_fp64": ii["fell_back"],
                     "true_relres": ii["true_relres"], "status": ii["status"],
                     "rel_diff_vs_fp64_solve": rel(torch, xi, x64), "rel_err_vs_xstar": rel(torch, xi, xs),
@@ -288,13 +291,17 @@ def claim_leg(pk, torch, A, b, n):
     dots, without and with residual replacement (period 50), at the benchmark tolerance
     1e-10 and at 1e-13 (below what the recurrences sustain); iteration cap 1500.  For
     the 1e-13 runs the true residual is recorded every 10 iterations (bit-identical to
-    the oracle's) and its minimum is reported: the attainable accuracy."""
+    the oracle's) and its minimum is reported: the attainable accuracy.  "exact_rows" runs
+    round every SpMV row and every residual row once as well (no summation order left
+    anywhere in the solve): whether the floor comes from the SpMV's rounding."""
     out = {}
     for tol in (1e-10, 1e-13):
-        for label, dots, rr in (("exact", pk.DOTS_EXACT, 0), ("plain", pk.DOTS_PLAIN, 0),
-                                ("exact_rr50", pk.DOTS_EXACT, 50), ("plain_rr50", pk.DOTS_PLAIN, 50)):
+        for label, dots, rr, xr in (("exact", pk.DOTS_EXACT, 0, 0), ("plain", pk.DOTS_PLAIN, 0, 0),
+                                    ("exact_rr50", pk.DOTS_EXACT, 50, 0), ("plain_rr50", pk.DOTS_PLAIN, 50, 0),
+                                    ("exact_rows", pk.DOTS_EXACT, 0, 2)):
             every = 10 if tol < 1e-12 else 0
-            solver = pk.Solver(A, tol=tol, max_iter=1500, dots=dots, rr_period=rr, true_every=every)
+            solver = pk.Solver(A, tol=tol, max_iter=1500, dots=dots, rr_period=rr, true_every=every,
+                               exact_rows=xr)
             x = torch.zeros(n, dtype=torch.float64, device=b.device)
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -549,6 +556,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-only", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the headline workload's other forms and the micro-benchmarks (legs still run)")
     ap.add_argument("--reps", type=int, default=30)
     ap.add_argument("--legs", default="cd3d_128,claim,cd2d_64,learned,rand_1m",
                     help="comma list of extra legs: cd3d_128, claim (needs cd3d_128), cd2d_64, learned, "
@@ -657,11 +666,12 @@ def main():
                                  "identical to the timed ones" % used}
 
     if not args.solve_only:
-        forms, x64 = fp64_forms(pk, torch, A, b, xs, 1, plain=(sec, info, x))
-        forms.update(precision_forms(pk, torch, A, b, xs, x64, forms, 1))
-        out["forms"] = forms
-        log("forms:", json.dumps(forms))
-        out["micro_kernels"] = micro_kernels(pk, torch, g, A, n, nnz, dev, args.reps)
+        if not args.no_forms:
+            forms, x64 = fp64_forms(pk, torch, A, b, xs, 1, plain=(sec, info, x))
+            forms.update(precision_forms(pk, torch, A, b, xs, x64, forms, 1))
+            out["forms"] = forms
+            log("forms:", json.dumps(forms))
+            out["micro_kernels"] = micro_kernels(pk, torch, g, A, n, nnz, dev, args.reps)
         # further legs run after the headline tables, so that they do not disturb them
         legs = [l for l in args.legs.split(",") if l]
         if "cd3d_128" in legs:

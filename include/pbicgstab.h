@@ -51,7 +51,13 @@ typedef enum {
 
 typedef enum { PBCG_F64 = 0, PBCG_F32 = 1 } pbcg_dtype;
 typedef enum { PBCG_ALG_PBICGSTAB = 0, PBCG_ALG_BICGSTAB = 1 } pbcg_alg;
-typedef enum { PBCG_PREC_FP64 = 0, PBCG_PREC_FP32_IR = 1 } pbcg_prec;
+/* FP64: everything FP64 (exact dots).  FP32_IR: FP64 refinement around an FP32
+ * p-BiCGStab (FP32 values, vectors and scalars; see pbicgstab_solve).  FP32_MATRIX: FP64
+ * p-BiCGStab (FP64 vectors, FP64 accumulation, exact dots) whose iterations apply A's values
+ * rounded to FP32 -- half the value bytes of every SpMV -- with residual replacement
+ * against the FP64 A every rr_period iterations (default 50): r = b - A x, and w, t, s, z,
+ * v recomputed with the FP32 values; the true residual (FP64 A) decides convergence. */
+typedef enum { PBCG_PREC_FP64 = 0, PBCG_PREC_FP32_IR = 1, PBCG_PREC_FP32_MATRIX = 2 } pbcg_prec;
 
 /* SpMV kernel shape.  SEQ sums every row left to right in storage order (the order of
  * the plain definition of A.x, so results are reproducible bit for bit by a sequential

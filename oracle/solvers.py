@@ -586,3 +586,17 @@ def ir_solve(A, b, tol=1e-10, inner_tol=0.1, max_iter=20000, max_outer=60, dot=N
         nu = nu_new
 
 
+
+
+def pbicgstab_fp32_matrix(A, b, tol=1e-10, max_iter=10000, rr_period=50, dot=None, history=False) -> Result:
+    """FP64 p-BiCGStab whose iterations apply A's values rounded to FP32 (vectors, the
+    accumulation of every row and all scalars stay FP64; inner products exact), with
+    residual replacement against the FP64 A every rr_period iterations: r = b - A x with
+    the FP64 values, then w, t, s, z, v recomputed with the FP32 ones.  ||b||, r_0 and the
+    true residual that decides convergence use the FP64 A.  (The build's precision form:
+    half the value bytes per SpMV, FP64 Krylov vectors.)"""
+    from synthgen import CSR
+    A32 = CSR(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32).astype(np.float64))
+    dot = dot or default_dot(A.n)
+    return pbicgstab(A32, b, tol=tol, max_iter=max_iter, dot=dot, rr_period=rr_period,
+                     resid=lambda _A, b_, x_: b_ - _spmv(A, x_), record=0)

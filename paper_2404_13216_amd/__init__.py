@@ -23,7 +23,7 @@ OK, NOT_CONVERGED, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 ERR_INVALID, ERR_HIP, ERR_NONFINITE, ERR_WORKSPACE = -1, -2, -3, -4
 F64, F32 = 0, 1
 ALG_PBICGSTAB, ALG_BICGSTAB = 0, 1
-PREC_FP64, PREC_FP32_IR = 0, 1
+PREC_FP64, PREC_FP32_IR, PREC_FP32_MATRIX = 0, 1, 2
 SPMV_SEQ, SPMV_VECTOR, SPMV_WAVE = 0, 1, 2
 DOTS_EXACT, DOTS_PLAIN = 0, 1
 LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SORTED = 0, 1, 2

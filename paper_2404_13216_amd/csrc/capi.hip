@@ -30,6 +30,8 @@ constexpr int IR_FP64_FINISH = 10000; // iteration limit of the FP64 finish afte
 constexpr int IR_FINISH_RR = 50;      // residual replacement period of that finish
 constexpr int IR_BATCH = 4;           // FP32 iterations enqueued between status polls (at most)
 constexpr int KEXP = 3;              // expansion terms per lane in the solver kernels
+constexpr double INFINITY_CACHE_BYTES_D = 256.0 * 1024 * 1024;   // MI355X Infinity Cache
+constexpr int FP32M_RR = 50;          // default replacement period of the FP32-matrix form
 
 #define HIPCHK(expr)                              \
     do {                                          \
@@ -698,6 +700,29 @@ int csr_jacobi(const pbcg_csr* A, void* m_out, int32_t m_type, void* stream) {
     return PBCG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The standalone exact dot: vectors together larger than the Infinity Cache stream past it
+// (non-temporal loads); smaller ones keep plain loads (a caller may reuse them).
+void exdot_launch(int64_t n, const double* x, const double* y, double* out, xd::Site site, hipStream_t s,
+                  int grid, int block, int k) {
+    if (16.0 * (double)n > INFINITY_CACHE_BYTES_D) {
+        DotsOp<1, FinStore, true> op{};
+        op.a[0] = x; op.b[0] = y;
+        op.fin = FinStore{out, 1};
+        launch_ew_dot<1>(op, n, site, nullptr, s, grid, block, k);
+    } else {
+        DotsOp<1, FinStore> op{};
+        op.a[0] = x; op.b[0] = y;
+        op.fin = FinStore{out, 1};
+        launch_ew_dot<1>(op, n, site, nullptr, s, grid, block, k);
+    }
+}
+}  // namespace
+
+extern "C" {
+
 size_t exdot_workspace_bytes(int64_t n) {
     (void)n;
     return site_bytes(DOT_GRID_MAX);
@@ -714,10 +739,7 @@ int exdot_config(int64_t n, const double* x, const double* y, double* out, int32
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws, ws_bytes);
     xd::Site site = carve_site(c, DOT_GRID_MAX);
-    DotsOp<1, FinStore> op{};
-    op.a[0] = x; op.b[0] = y;
-    op.fin = FinStore{out, 1};
-    launch_ew_dot<1>(op, n, site, nullptr, s, grid, block, k);
+    exdot_launch(n, x, y, out, site, s, grid, block, k);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
@@ -778,10 +800,7 @@ int exdot_noalloc(int64_t n, const double* x, const double* y, double* out, void
     xd::Site site;
     site.hdr = (xd::RecHdr*)base;
     site.dig = (long long*)((char*)base + NOALLOC_HDR);
-    DotsOp<1, FinStore> op{};
-    op.a[0] = x; op.b[0] = y;
-    op.fin = FinStore{out, 1};
-    launch_ew_dot<1>(op, n, site, nullptr, s, g, DOT_BLOCK, KEXP);
+    exdot_launch(n, x, y, out, site, s, g, DOT_BLOCK, KEXP);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
@@ -909,6 +928,8 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
         float** v32[] = {&W.r32, &W.rh32, &W.w32, &W.t32, &W.p32, &W.s32,
                          &W.z32, &W.q32, &W.y32, &W.v32, &W.d32};
         for (float** pp : v32) *pp = c.take<float>(N);
+    }
+    if (o && (o->prec == PBCG_PREC_FP32_IR || o->prec == PBCG_PREC_FP32_MATRIX)) {
         // FP32 values in CSR order, or in the sliced order when A has a sliced copy
         W.val32 = c.take<float>((size_t)std::max<int64_t>(slicing_on(o) ? slice_cap(nnz) : nnz, 1));
     }
@@ -963,6 +984,7 @@ struct Driver {
     int kind;              // SpMV kernel shape
     pbcg_csr A32c;         // FP32 copy of A (refinement) ...
     Mat A32;               // ... with the FP32 sliced values when A is sliced
+    Mat Aop;               // the matrix op() applies: A, or A32 (FP32 matrix values)
     int64_t a_entries = 0; // entries of A's sliced copy
     bool nt64 = false;     // stream the FP64 phase outputs past the caches ...
     bool nt32 = false;     // ... and the FP32 ones (working set above the Infinity Cache)
@@ -982,7 +1004,7 @@ struct Driver {
             launch_spmv64(M, in, EpiStore<double>{W.tmp2}, skip, s, kind, fin);
             launch_spmv64(A, W.tmp2, EpiStore<double>{out}, skip, s, kind);
         } else {
-            launch_spmv64(A, in, EpiStore<double>{out}, skip, s, kind, fin);
+            launch_spmv64(Aop, in, EpiStore<double>{out}, skip, s, kind, fin);
         }
     }
 
@@ -1310,10 +1332,8 @@ struct Driver {
     // after a breakdown or stall, restarted.  An update that does not improve on the
     // best iterate means FP32 has reached its accuracy floor (about u32 cond(A)): the
     // solve then finishes in FP64 p-BiCGStab from the best iterate.
-    int run_ir(State& h, int& outer, int& inner_total) {
-        const int n = A->n;
-        FState* fs = W.fst;
-        launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0, 0, nullptr}, s);
+    // A32: A with its values rounded to FP32 (in the sliced order when A is sliced)
+    void make_a32() {
         A32c = *A.csr;
         A32c.val = W.val32;
         A32c.val_type = PBCG_F32;
@@ -1324,6 +1344,13 @@ struct Driver {
             launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
             A32 = Mat(&A32c);
         }
+    }
+
+    int run_ir(State& h, int& outer, int& inner_total) {
+        const int n = A->n;
+        FState* fs = W.fst;
+        launch_single(FnInitState{W.st, o->tol, o->max_iter, nullptr, 0, 0, nullptr}, s);
+        make_a32();
         {
             DotsOp<1, FinNormB> nb{};
             nb.a[0] = b; nb.b[0] = b; nb.fin = FinNormB{W.st};
@@ -1459,7 +1486,11 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         (opts->kernel_events_len > 0 && !opts->kernel_events))
         return PBCG_ERR_INVALID;
     if (opts->alg != PBCG_ALG_PBICGSTAB && opts->alg != PBCG_ALG_BICGSTAB) return PBCG_ERR_INVALID;
-    if (opts->prec != PBCG_PREC_FP64 && opts->prec != PBCG_PREC_FP32_IR) return PBCG_ERR_INVALID;
+    if (opts->prec != PBCG_PREC_FP64 && opts->prec != PBCG_PREC_FP32_IR && opts->prec != PBCG_PREC_FP32_MATRIX)
+        return PBCG_ERR_INVALID;
+    if (opts->prec == PBCG_PREC_FP32_MATRIX &&
+        (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || A->val_type != PBCG_F64 || opts->exact_rows != 0))
+        return PBCG_ERR_INVALID;
     if (opts->M && (!csr_ok(opts->M) || opts->M->n != A->n)) return PBCG_ERR_INVALID;
     if (opts->M && opts->alg != PBCG_ALG_PBICGSTAB) return PBCG_ERR_INVALID;
     if (opts->prec == PBCG_PREC_FP32_IR && (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || A->val_type != PBCG_F64))
@@ -1477,7 +1508,8 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || opts->prec != PBCG_PREC_FP64))
         return PBCG_ERR_INVALID;
     if ((opts->dots == PBCG_DOTS_PLAIN || opts->rr_period > 0) &&
-        (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || opts->prec != PBCG_PREC_FP64))
+        (opts->M || opts->alg != PBCG_ALG_PBICGSTAB ||
+         (opts->prec != PBCG_PREC_FP64 && opts->prec != PBCG_PREC_FP32_MATRIX)))
         return PBCG_ERR_INVALID;
     if (!ws || ((uintptr_t)ws & 255)) return PBCG_ERR_WORKSPACE;
     Work W = carve_work(ws, ws_bytes, A->n, A->nnz, opts);
@@ -1543,7 +1575,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     }
     {
         const int64_t ma = (sliced & 1) ? D.a_entries : 0;
-        const int vb = A->val_type == PBCG_F64 ? 8 : 4;
+        const int vb = (A->val_type == PBCG_F64 && opts->prec != PBCG_PREC_FP32_MATRIX) ? 8 : 4;
         const bool a16 = D.A.sl.d16, m16 = D.M.sl.d16;
         double ws64 = matrix_bytes(A, ma, vb, a16) + 12.0 * 8.0 * A->n;
         if (opts->M) {
@@ -1561,6 +1593,14 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
                         INFINITY_CACHE_BYTES;
         if (a16) sliced |= 4;
         if (m16) sliced |= 8;
+    }
+    D.Aop = D.A;
+    if (opts->prec == PBCG_PREC_FP32_MATRIX) {
+        // the iterations apply A's values rounded to FP32 (4 bytes per entry instead of 8);
+        // the residual replacement against the FP64 A keeps the iterate on A x = b
+        D.make_a32();
+        D.Aop = D.A32;
+        if (D.rr_period <= 0) D.rr_period = FP32M_RR;
     }
     State h{};
     int status;

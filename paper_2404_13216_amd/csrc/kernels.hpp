@@ -1184,8 +1184,9 @@ struct PhaseB {
     __device__ __forceinline__ void finalize(const double* d) { fin(d); }
 };
 
-// Plain dots of given vectors (D <= 4); no updates.
-template <int D, class Fin>
+// Plain dots of given vectors (D <= 4); no updates.  NT: the vectors are read with
+// non-temporal loads (a standalone dot over vectors larger than the Infinity Cache).
+template <int D, class Fin, bool NT = false>
 struct DotsOp {
     const double* a[4];
     const double* b[4];
@@ -1195,7 +1196,7 @@ struct DotsOp {
     __device__ __forceinline__ void load() {}
     __device__ __forceinline__ void ld(int64_t i, double (&in)[NIN]) const {
 #pragma unroll
-        for (int d = 0; d < D; ++d) { in[2 * d] = a[d][i]; in[2 * d + 1] = b[d][i]; }
+        for (int d = 0; d < D; ++d) { in[2 * d] = get<NT>(a[d], i); in[2 * d + 1] = get<NT>(b[d], i); }
     }
     __device__ __forceinline__ void st(int64_t, const double (&in)[NIN], double (&xa)[D], double (&ya)[D]) const {
 #pragma unroll

@@ -375,98 +375,109 @@ __global__ void __launch_bounds__(BLOCK) k_probe_column(int n, const double* __r
 }
 
 // ------------------------------------------------------------------ bf16 MFMA inference
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ unsigned short f2bf(float x) {   // round to nearest even
-    unsigned int u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (unsigned short)((u >> 16) | 0x40);
-    u = u + 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+__device__ __forceinline__ float bf_round(float x) { return (float)(__bf16)x; }   // RNE (v_cvt_pk_bf16_f32)
+
+// GELU for inference: z Phi(z), with Phi(-|z|) = erfc(|z| / sqrt 2) / 2 from Abramowitz &
+// Stegun 7.1.26 (Hastings' rational approximation, |error| <= 1.5e-7 on erf: about one
+// FP32 ulp near 1, far below the bf16 rounding the result gets next):
+// erfc(u) = t (a1 + t (a2 + ... + t a5)) e^{-u^2}, t = 1 / (1 + p u).  With u = |z| / sqrt 2
+// folded into p, the 1/2 into the a_k and the exponential taken as 2^(-z^2 log2(e) / 2):
+// one reciprocal, one exponential and nine other operations per GELU.
+__device__ __forceinline__ float gelu_infer(float z) {
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(z), 1.0f));
+    float q = fmaf(t, 1.061405429f * 0.5f, -1.453152027f * 0.5f);
+    q = fmaf(t, q, 1.421413741f * 0.5f);
+    q = fmaf(t, q, -0.284496736f * 0.5f);
+    q = fmaf(t, q, 0.254829592f * 0.5f);
+    const float e = __builtin_amdgcn_exp2f((z * z) * -0.72134752044448170f);
+    const float h = (t * q) * e;                 // Phi(-|z|)
+    return z * (z >= 0.0f ? 1.0f - h : h);
 }
-__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-// One wave handles tiles of 16 nonzeros.  v_mfma_f32_16x16x16bf16: lane l holds
-// A[l%16][4(l/16)+j], B[4(l/16)+j][l%16] (j = 0..3) and C[4(l/16)+j][l%16].
-__global__ void __launch_bounds__(256) k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
+// One wave handles tiles of 16 nonzeros with v_mfma_f32_16x16x32_bf16 (lane l = 16 g + c
+// holds A[c][8 g + j] and B[8 g + j][c], j = 0..7, and C[4 g + j][c], j = 0..3).  The
+// nonzeros are the N dimension: layer 1 computes H1 (64 hidden x 16 nonzeros) = W1 Phi as
+// four 16-row tiles (K = 12 features padded to 32); lane (g, c) then holds hidden units
+// 16 mt + 4 g + j of nonzero c, which are exactly the B operand of layer 2 once the 64
+// hidden units are ordered (per 32-unit k-step ks) as 16 (2 ks) + 4 g + j, then
+// 16 (2 ks + 1) + 4 g + j -- so W2's columns are taken in that order and no value
+// crosses lanes.  Layer 3 (64 -> 1) sums each lane's 16 units and the four lane groups.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
                                                     const float* __restrict__ params, const int* __restrict__ rowidx,
                                                     const double* __restrict__ diag, float* __restrict__ mout) {
-    __shared__ unsigned short sh[4][16][HID + 4];      // per wave: h1 tile (bf16), row padded
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    // B operands in registers: W1 (4 n-tiles, K = 16 with 12 used) and W2 (4 n-tiles x 4 k-steps)
-    bf16x4 bw1[4], bw2[4][4];
-    for (int nt = 0; nt < 4; ++nt) {
-        for (int j = 0; j < 4; ++j) {
-            const int kk = 4 * lk + j, col = nt * 16 + lr;
-            bw1[nt][j] = (short)(kk < NF ? f2bf(params[OFF_W1 + col * NF + kk]) : 0);
+    const int c = lane & 15, grp = lane >> 4;
+    // A operands: W1 (4 m-tiles, K padded to 32) and the column-permuted W2 (4 m-tiles x 2
+    // k-steps), rounded to bf16; biases and w3 in the C layout (unit 16 mt + 4 grp + j)
+    bf16x8 aw1[4], aw2[4][2];
+    for (int mt = 0; mt < 4; ++mt) {
+        const int row = 16 * mt + c;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * grp + j;
+            aw1[mt][j] = (__bf16)(k < NF ? params[OFF_W1 + row * NF + k] : 0.0f);
         }
-        for (int ks = 0; ks < 4; ++ks)
-            for (int j = 0; j < 4; ++j) {
-                const int kk = 16 * ks + 4 * lk + j, col = nt * 16 + lr;
-                bw2[nt][ks][j] = (short)f2bf(params[OFF_W2 + col * HID + kk]);
+        for (int ks = 0; ks < 2; ++ks)
+            for (int j = 0; j < 8; ++j) {
+                const int unit = 16 * (2 * ks + (j >> 2)) + 4 * grp + (j & 3);
+                aw2[mt][ks][j] = (__bf16)params[OFF_W2 + row * HID + unit];
             }
     }
-    float b1v[4], b2v[4], w3v[4];
-    for (int nt = 0; nt < 4; ++nt) {
-        b1v[nt] = params[OFF_B1 + nt * 16 + lr];
-        b2v[nt] = params[OFF_B2 + nt * 16 + lr];
-        w3v[nt] = bf2f(f2bf(params[OFF_W3 + nt * 16 + lr]));
-    }
+    float b1v[4][4], b2v[4][4], w3v[4][4];
+    for (int mt = 0; mt < 4; ++mt)
+        for (int j = 0; j < 4; ++j) {
+            const int u = 16 * mt + 4 * grp + j;
+            b1v[mt][j] = params[OFF_B1 + u];
+            b2v[mt][j] = params[OFF_B2 + u];
+            w3v[mt][j] = bf_round(params[OFF_W3 + u]);
+        }
     const float b3 = params[OFF_B3];
     const int64_t ntiles = (nnz + 15) / 16;
     const int64_t wstride = (int64_t)gridDim.x * 4;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wid; tile < ntiles; tile += wstride) {
-        const int64_t base = tile * 16;
-        // layer 1: A = features of rows base..base+15 (bf16), K padded to 16
-        bf16x4 ax;
-        {
-            const int64_t q = base + lr;
-            for (int j = 0; j < 4; ++j) {
-                const int kk = 4 * lk + j;
-                float v = (q < nnz && kk < NF) ? feat[q * NF + kk] : 0.0f;
-                ax[j] = (short)f2bf(v);
+        const int64_t q = tile * 16 + c;          // this lane's nonzero
+        // layer 1: B = features of the tile's nonzeros, rows 8 grp .. 8 grp + 7 of K
+        bf16x8 bx;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * grp + j;
+            bx[j] = (__bf16)((q < nnz && k < NF) ? feat[q * NF + k] : 0.0f);
+        }
+        bf16x8 h1[2];
+        for (int mt = 0; mt < 4; ++mt) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw1[mt], bx, acc, 0, 0, 0);
+            for (int j = 0; j < 4; j += 2) {   // two values per conversion instruction
+                const f32x2 g2 = {gelu_infer(acc[j] + b1v[mt][j]), gelu_infer(acc[j + 1] + b1v[mt][j + 1])};
+                const bf16x2 h2 = __builtin_convertvector(g2, bf16x2);
+                h1[mt >> 1][4 * (mt & 1) + j] = h2[0];
+                h1[mt >> 1][4 * (mt & 1) + j + 1] = h2[1];
             }
         }
-        for (int nt = 0; nt < 4; ++nt) {
-            floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax, bw1[nt], c, 0, 0, 0);
-            for (int j = 0; j < 4; ++j) {
-                float z = c[j] + b1v[nt];
-                sh[wid][4 * lk + j][nt * 16 + lr] = f2bf(gelu(z));   // h1[row][col]
+        // layer 2: B = H1 in the permuted unit order (k-step ks = m-tiles 2 ks, 2 ks + 1)
+        float part = 0.0f;
+        for (int mt = 0; mt < 4; ++mt) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[mt][0], h1[0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[mt][1], h1[1], acc, 0, 0, 0);
+            // layer 3: f = sum_u bf16(gelu(z2_u)) w3_u + b3
+            for (int j = 0; j < 4; j += 2) {
+                const f32x2 g2 = {gelu_infer(acc[j] + b2v[mt][j]), gelu_infer(acc[j + 1] + b2v[mt][j + 1])};
+                const bf16x2 r2 = __builtin_convertvector(g2, bf16x2);
+                part = part + (float)r2[0] * w3v[mt][j];
+                part = part + (float)r2[1] * w3v[mt][j + 1];
             }
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        // layer 2: A = h1 (16 x 64) in 4 k-steps
-        floatx4 acc2[4];
-        for (int nt = 0; nt < 4; ++nt) acc2[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int ks = 0; ks < 4; ++ks) {
-            bf16x4 ah;
-            for (int j = 0; j < 4; ++j) ah[j] = (short)sh[wid][lr][16 * ks + 4 * lk + j];
-            for (int nt = 0; nt < 4; ++nt)
-                acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bw2[nt][ks], acc2[nt], 0, 0, 0);
-        }
-        __builtin_amdgcn_wave_barrier();
-        // layer 3: f[row] = sum_col bf16(gelu(z2[row][col])) * w3[col] + b3
-        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int nt = 0; nt < 4; ++nt)
-            for (int j = 0; j < 4; ++j) {
-                float h2 = bf2f(f2bf(gelu(acc2[nt][j] + b2v[nt])));
-                float prod = h2 * w3v[nt];
-                part[j] = part[j] + prod;
-            }
-        for (int o = 1; o < 16; o <<= 1)
-            for (int j = 0; j < 4; ++j) part[j] = part[j] + __shfl_xor(part[j], o);
-        if (lr == 0) {
-            for (int j = 0; j < 4; ++j) {
-                const int64_t q = base + 4 * lk + j;
-                if (q < nnz) {
-                    const float f = part[j] + b3;
-                    const float isd = feat[q * NF + 10];
-                    mout[q] = (isd + f) / (float)diag[rowidx[q]];
-                }
-            }
+        part = part + __shfl_xor(part, 16);
+        part = part + __shfl_xor(part, 32);
+        if (grp == 0 && q < nnz) {
+            const float f = part + b3;
+            const float isd = feat[q * NF + 10];
+            mout[q] = (isd + f) / (float)diag[rowidx[q]];
         }
     }
 }
@@ -558,7 +569,8 @@ int spai_infer_bf16(int64_t nnz, const float* feat, const float* params, const i
     if (nnz <= 0 || !feat || !params || !rowidx || !diag || !m_out) return PBCG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     const int64_t tiles = (nnz + 15) / 16;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
+    // up to 4 waves per SIMD resident (the kernel is held to 128 VGPRs): 1024 blocks
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 1024));
     k_infer_bf16<<<grid, 256, 0, s>>>(nnz, feat, params, rowidx, diag, m_out);
     HIPCHK(hipGetLastError());
     return PBCG_OK;

@@ -119,3 +119,30 @@ def test_ir_zero_rhs_and_invalid():
     assert info["status"] == pk.OK and not x.any()
     with pytest.raises(pk.LibError):
         pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), prec=pk.PREC_FP32_IR, alg=pk.ALG_BICGSTAB)
+
+
+@pytest.mark.parametrize("name,scale", [("cd2d_64", None), ("cd3d_256_var", 20), ("rand_1m", 8000),
+                                        ("cd3d_128", 24)])
+def test_fp32_matrix_form_bitwise(name, scale):
+    """FP32 matrix values with FP64 vectors, replacement against the FP64 A every 50
+    iterations: every operation is defined identically on both sides (row-sequential
+    SpMVs, exact dots), so the solve matches the oracle bit for bit."""
+    p = g.problem(name, scale=scale)
+    ref = solvers.pbicgstab_fp32_matrix(p.A, p.b, tol=1e-10, max_iter=5000)
+    x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), tol=1e-10, max_iter=5000, prec=pk.PREC_FP32_MATRIX)
+    assert info["status"] == ref.status == pk.OK
+    assert info["iterations"] == ref.iterations
+    assert np.array_equal(x.cpu().numpy().view(np.uint64), ref.x.view(np.uint64))
+    assert info["true_relres"] == ref.true_relres
+
+
+def test_fp32_matrix_form_full_256(capsys):
+    p = g.problem("cd3d_256_var")
+    x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), tol=1e-10, prec=pk.PREC_FP32_MATRIX)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    true = oc.true_relres(p.A, p.b, xh)
+    with capsys.disabled():
+        print(f"\n  256^3 FP32-matrix form: {info['iterations']} iterations, true {true:.2e}, "
+              f"|x - x*|_inf {np.abs(xh - p.xstar).max():.2e}")
+    assert info["status"] == pk.OK and true <= 1e-10 and true == info["true_relres"]

@@ -94,3 +94,31 @@ def test_plain_dot_plumbing():
     pl = solvers.pbicgstab(p.A, p.b, tol=1e-10, dot=solvers.dot_f64_seq, exact_dot=solvers.default_dot(p.A.n))
     assert pl.status == solvers.OK and pl.true_relres <= 1e-10
     assert np.linalg.norm(pl.x - ex.x) <= 1e-8 * np.linalg.norm(ex.x)
+
+
+def test_fp32_matrix_form_pins():
+    """The FP32-matrix form: on a matrix whose values are exact in FP32 (integers) it is
+    p-BiCGStab with residual replacement, bit for bit; on the families it reaches the true
+    residual 1e-10 and the FP64 solution; a planted mistake (replacement with the FP32
+    values) is caught on a matrix whose values are not exact in FP32."""
+    from synthgen import CSR
+    p = g.problem("cd2d_64", scale=20)
+    Ai = CSR(p.A.n, p.A.row_ptr, p.A.col_idx, np.rint(p.A.val * 4000.0))
+    bi = p.b * 4000.0
+    r1 = solvers.pbicgstab_fp32_matrix(Ai, bi, rr_period=7)
+    r2 = solvers.pbicgstab(Ai, bi, rr_period=7, dot=solvers.default_dot(Ai.n))
+    assert r1.iterations == r2.iterations and np.array_equal(r1.x.view(np.uint64), r2.x.view(np.uint64))
+    for name, scale in (("cd3d_256_var", 20), ("rand_1m", 4000), ("cd3d_128", 24)):
+        q = g.problem(name, scale=scale)
+        r = solvers.pbicgstab_fp32_matrix(q.A, q.b)
+        ref = ctier.bicgstab(q.A, q.b, tol=1e-10)
+        assert r.status == solvers.OK and r.true_relres <= 1e-10
+        assert np.linalg.norm(r.x - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+    q = g.problem("cd3d_256_var", scale=20)
+    bad = _mutant(solvers.pbicgstab_fp32_matrix, "resid=lambda _A, b_, x_: b_ - _spmv(A, x_)",
+                  "resid=lambda _A, b_, x_: b_ - _spmv(A32, x_)")(q.A, q.b)
+    # replacing with the FP32 matrix solves fp32(A) x = b: measured against the FP64 A its
+    # residual stays far above the tolerance
+    from oracle.spmv import spmv
+    res = q.b - spmv(q.A, bad.x)
+    assert np.sqrt(ctier.exact_dot(res, res) / ctier.exact_dot(q.b, q.b)) > 1e-9
