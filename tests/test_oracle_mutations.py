@@ -117,3 +117,38 @@ def test_mutated_refinement_is_caught(old, new):
     assert ok.status == solvers.OK and ok.fell_back == 0
     bad = _mutant(solvers.ir_solve, old, new)(p.A, p.b, tol=1e-10)
     assert bad.fell_back == 1 or bad.status != solvers.OK
+
+
+@pytest.mark.parametrize("old,new", [
+    ("vals = [float(b[i])] + (-np.asarray(A.val[a:e], dtype=np.float64)).tolist()",
+     "vals = [float(b[i])] + (np.asarray(A.val[a:e], dtype=np.float64)).tolist()"),        # wrong sign
+    ("xs = [1.0] + x[A.col_idx[a:e]].tolist()", "xs = [0.0] + x[A.col_idx[a:e]].tolist()"),  # b dropped
+])
+def test_mutated_exact_residual_is_caught(old, new):
+    from oracle import spmv as ospmv
+    from tests.test_oracle_exact_rows import test_brute_force_rational
+    test_brute_force_rational(0)
+    bad = _mutant(ospmv.resid_exact, old, new)
+    saved = ospmv.resid_exact
+    try:
+        import tests.test_oracle_exact_rows as t
+        t.resid_exact = bad
+        with pytest.raises(AssertionError):
+            t.test_brute_force_rational(0)
+    finally:
+        import tests.test_oracle_exact_rows as t
+        t.resid_exact = saved
+
+
+def test_mutated_exact_rows_is_caught():
+    """Summing a row in floating point instead of exactly fails the cancellation pin."""
+    from oracle import spmv as ospmv
+    import tests.test_oracle_exact_rows as t
+    t.test_cancellation_and_order_independence()
+    saved = t.spmv_exact
+    try:
+        t.spmv_exact = lambda A, x, rows=None: ospmv.spmv(A, x)
+        with pytest.raises(AssertionError):
+            t.test_cancellation_and_order_independence()
+    finally:
+        t.spmv_exact = saved
