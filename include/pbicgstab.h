@@ -180,8 +180,9 @@ int csr_spmv(const pbcg_csr* A, const double* x, double* y, void* stream);
 /* y = A x with every row summed exactly and rounded once to nearest even (the exact
  * dot's definition applied to each row: exact zero gives +0, NaN / inf as in exdot), so
  * the result depends on no summation order (paper, Section 2, the ExBLAS paragraph).
- * A: FP64 or FP32 values; x, y: FP64, y != x.  16 lanes per row deposit the exact
- * products into the row's LDS long accumulator; about 3x the time of csr_spmv. */
+ * A: FP64 or FP32 values; x, y: FP64, y != x.  Short rows (mean length <= 12) are summed
+ * by one lane each in a register window when their terms span a few 32-bit chunks; other
+ * rows by 16 lanes into an LDS long accumulator.  About 3-4x the time of csr_spmv. */
 int csr_spmv_exact(const pbcg_csr* A, const double* x, double* y, void* stream);
 
 /* Same with an explicit kernel shape (pbcg_spmv_kind). */

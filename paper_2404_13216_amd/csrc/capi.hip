@@ -13,6 +13,7 @@
 
 #include "../../include/pbicgstab.h"
 #include "kernels.hpp"
+#include "exact_rows.hpp"
 
 using namespace pbcg;
 
@@ -323,34 +324,54 @@ void launch_spmv_dot(const Mat& A, const double* x, Epi epi, xd::Site site, cons
     else launch_spmv_dot_t<D, float>(A, x, epi, site, halt, s, kind);
 }
 
+// Whether the exact-row kernels try the one-lane-per-row register path first: rows of
+// mean length up to 12 (stencils).  Longer rows leave most lanes of a wave waiting for its
+// longest row, and the 16-lane LDS path is faster there.
+inline bool exact_rows_fast(const pbcg_csr* A) { return (int64_t)A->nnz <= (int64_t)12 * A->n; }
+
 // Exactly rounded rows (RESID: r = b - A x rounded once per row); persistent blocks of
-// 256 threads (16 rows in flight), block 0 extra when it carries a finalize role.
+// 256 threads, block 0 extra when it carries a finalize role.
 template <bool RESID, class Epi, class Fin = NoFin>
 void launch_spmv_exact(const Mat& A, const double* x, const double* b, Epi epi, const int* halt, hipStream_t s,
                        Fin fin = Fin{}) {
     const int n = A->n;
-    const int steps = (n + XR_ROWS - 1) / XR_ROWS;
-    const int grid = std::min(steps, EXACT_ROW_WORKERS) + (Fin::D > 0 ? 1 : 0);
+    const bool fast = exact_rows_fast(A.csr);
+    const int rows = fast ? BLOCK : XR_ROWS;
+    const int grid = std::min((n + rows - 1) / rows, EXACT_ROW_WORKERS) + (Fin::D > 0 ? 1 : 0);
     if (grid <= 0) return;
-    if (A->val_type == PBCG_F64)
-        klaunch(spmv_exact_kernel<double, Epi, Fin, RESID>, grid, BLOCK, 0, s, n, A->row_ptr, A->col_idx,
-                (const double*)A->val, x, b, epi, fin, halt);
-    else
-        klaunch(spmv_exact_kernel<float, Epi, Fin, RESID>, grid, BLOCK, 0, s, n, A->row_ptr, A->col_idx,
-                (const float*)A->val, x, b, epi, fin, halt);
+    auto go = [&](auto vt, auto f) {
+        using VT = decltype(vt);
+        klaunch(spmv_exact_kernel<VT, Epi, Fin, RESID, decltype(f)::value>, grid, BLOCK, 0, s, n, A->row_ptr,
+                A->col_idx, (const VT*)A->val, x, b, epi, fin, halt);
+    };
+    if (A->val_type == PBCG_F64) {
+        if (fast) go(double{}, std::true_type{});
+        else go(double{}, std::false_type{});
+    } else {
+        if (fast) go(float{}, std::true_type{});
+        else go(float{}, std::false_type{});
+    }
 }
 
 template <int D, bool RESID, class Epi>
 void launch_spmv_exact_dot(const Mat& A, const double* x, const double* b, Epi epi, xd::Site site,
                            const int* halt, hipStream_t s) {
     const int n = A->n;
-    const int grid = std::max(1, std::min(DOT_GRID_MAX, (n + XR_ROWS - 1) / XR_ROWS));
-    if (A->val_type == PBCG_F64)
-        spmv_exact_dot_kernel<D, KEXP, double, Epi, RESID><<<grid, BLOCK, 0, s>>>(
-            n, A->row_ptr, A->col_idx, (const double*)A->val, x, b, epi, site, halt);
-    else
-        spmv_exact_dot_kernel<D, KEXP, float, Epi, RESID><<<grid, BLOCK, 0, s>>>(
-            n, A->row_ptr, A->col_idx, (const float*)A->val, x, b, epi, site, halt);
+    const bool fast = exact_rows_fast(A.csr);
+    const int rows = fast ? BLOCK : XR_ROWS;
+    const int grid = std::max(1, std::min(DOT_GRID_MAX, (n + rows - 1) / rows));
+    auto go = [&](auto vt, auto f) {
+        using VT = decltype(vt);
+        spmv_exact_dot_kernel<D, KEXP, VT, Epi, RESID, decltype(f)::value><<<grid, BLOCK, 0, s>>>(
+            n, A->row_ptr, A->col_idx, (const VT*)A->val, x, b, epi, site, halt);
+    };
+    if (A->val_type == PBCG_F64) {
+        if (fast) go(double{}, std::true_type{});
+        else go(double{}, std::false_type{});
+    } else {
+        if (fast) go(float{}, std::true_type{});
+        else go(float{}, std::false_type{});
+    }
     fin_kernel<XFin<D, Epi>><<<1, XFin<D, Epi>::BLOCK, 0, s>>>(XFin<D, Epi>{epi, site, grid, halt});
 }
 

@@ -802,189 +802,6 @@ spmv_seq_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __rest
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
 }
 
-// ----------------------------------------------------------------------------- exact rows
-// Exactly rounded SpMV rows: every row's sum is formed exactly and rounded once to nearest
-// even -- the reproducible-reduction idea (exact accumulation, one rounding) applied to the
-// rows of A x, so y no longer depends on any summation order.  16 lanes (one DPP row of
-// the wave) take one matrix row: each lane deposits its products as exact integers
-// (TwoProd is not needed: the 106-bit product goes straight into the row's long
-// accumulator of 32-bit chunks in LDS, integer additions commute), the group finds the
-// chunk range it touched, and its leader rounds the range once (the exact dot's
-// rounding).  RESID: the row value is b_i - (A x)_i as one exact sum (b_i enters as a
-// term), rounded once.
-constexpr int XR_GROUP = 16;                   // lanes per matrix row
-constexpr int XR_ROWS = 256 / XR_GROUP;        // rows in flight per 256-thread block
-constexpr int XR_SMEM = XR_ROWS * xd::NCH * 8 + XR_ROWS * 4;
-
-__device__ __forceinline__ int xr_row_max(int v) { return -xd::row_min_i(-v); }
-
-__device__ __forceinline__ void xr_flag_nonfinite(uint32_t* flag, double a, double x) {
-    uint32_t f;
-    if (isnan(a) || isnan(x) || a == 0.0 || x == 0.0) f = xd::F_NAN;
-    else f = ((a > 0.0) == (x > 0.0)) ? xd::F_PINF : xd::F_NINF;
-    atomicOr(flag, f);
-}
-
-// One row per 16-lane group (row < 0: the group idles).  acc: the group's NCH chunks, zero
-// on entry and zero again on return; flag: the group's non-finite flags (likewise).  All
-// 64 lanes of the wave call it together; the group leader (gl == 0) gets the value.
-template <class VT, bool RESID>
-__device__ __forceinline__ double exact_row(int row, const int32_t* __restrict__ rp,
-                                            const int32_t* __restrict__ ci, const VT* __restrict__ val,
-                                            const double* __restrict__ x, const double* __restrict__ b,
-                                            unsigned long long* acc, uint32_t* flag, int gl) {
-    int lo = INT_MAX, hi = -1;
-    if (row >= 0) {
-        const int a = rp[row], e = rp[row + 1];
-        for (int k = a + gl; k < e; k += XR_GROUP) {
-            const double av = (double)val[k], xv = x[ci[k]];
-            if (!(isfinite(av) && isfinite(xv))) {
-                xr_flag_nonfinite(flag, RESID ? -av : av, xv);
-            } else if (av != 0.0 && xv != 0.0) {
-                uint64_t m;
-                int Pa, Px;
-                bool ng;
-                xd::decompose(av, m, Pa, ng);
-                xd::decompose(xv, m, Px, ng);
-                const int c = (Pa + Px - xd::BIAS) >> 5;     // lowest chunk of the product
-                lo = min(lo, c);
-                hi = max(hi, c + 4);
-                xd::deposit_product(acc, RESID ? -av : av, xv);
-            }
-        }
-        if constexpr (RESID) {
-            if (gl == 0) {
-                const double bv = b[row];
-                if (!isfinite(bv)) {
-                    xr_flag_nonfinite(flag, bv, 1.0);
-                } else if (bv != 0.0) {
-                    uint64_t m;
-                    int P;
-                    bool ng;
-                    xd::decompose(bv, m, P, ng);
-                    lo = min(lo, P >> 5);
-                    hi = max(hi, (P >> 5) + 2);
-                    xd::deposit_double(acc, bv);
-                }
-            }
-        }
-    }
-    lo = xd::row_min_i(lo);
-    hi = xr_row_max(hi);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    double v = 0.0;
-    if (gl == 0 && row >= 0) v = xd::round_chunks((long long*)acc, *flag, lo, min(hi, xd::NCH - 1));
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    // clear what the row touched (the rounding's carries stop at most one chunk above hi)
-    if (lo <= hi)
-        for (int c = lo + gl; c <= min(hi + 2, xd::NCH - 1); c += XR_GROUP) acc[c] = 0ull;
-    if (gl == 0) *flag = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    return v;
-}
-
-// y = A x with exactly rounded rows (RESID: r = b - A x, each row rounded once), epilogue
-// epi(row, value) on the group leader; block 0 may carry a finalize role.
-template <class VT, class Epi, class Fin, bool RESID>
-__global__ void __launch_bounds__(256)
-spmv_exact_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                  const VT* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
-                  Epi epi, Fin fin, const int* halt) {
-    if (halt && *halt) return;
-    constexpr int SMEM = Fin::SMEM > XR_SMEM ? Fin::SMEM : XR_SMEM;
-    __shared__ __align__(16) unsigned char smem[SMEM];
-    int bfirst = 0;
-    if constexpr (Fin::D > 0) {
-        if (blockIdx.x == 0) {
-            fin.run(smem);
-            return;
-        }
-        bfirst = 1;
-    }
-    unsigned long long* accs = (unsigned long long*)smem;
-    uint32_t* flags = (uint32_t*)(smem + XR_ROWS * xd::NCH * 8);
-    for (int i = threadIdx.x; i < XR_ROWS * xd::NCH; i += blockDim.x) accs[i] = 0ull;
-    if (threadIdx.x < XR_ROWS) flags[threadIdx.x] = 0u;
-    __syncthreads();
-    const int g = threadIdx.x / XR_GROUP, gl = threadIdx.x % XR_GROUP;
-    const int G = (int)gridDim.x - bfirst;
-    const int steps = (n + XR_ROWS - 1) / XR_ROWS;
-    for (int st = (int)blockIdx.x - bfirst; st < steps; st += G) {   // uniform over the block
-        const int row = st * XR_ROWS + g;
-        const double v = exact_row<VT, RESID>(row < n ? row : -1, rp, ci, val, x, b, accs + g * xd::NCH,
-                                               flags + g, gl);
-        if (gl == 0 && row < n) epi(row, v);
-    }
-}
-
-// The same with D exact dots of the rows' values in the epilogue (the true residual and
-// its norm): epi.row(row, value, xa, ya) as in the row-sequential dot kernels.
-template <int D, int K, class VT, class Epi, bool RESID>
-__global__ void __launch_bounds__(256)
-spmv_exact_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                      const VT* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
-                      Epi epi, xd::Site site, const int* halt) {
-    if (halt && *halt) return;
-    XD_SHARED(D)
-    __shared__ __align__(16) unsigned char smem[XR_SMEM];
-    xd::block_init<D>(sh_acc, sh_flags);
-    epi.load();
-    unsigned long long* accs = (unsigned long long*)smem;
-    uint32_t* flags = (uint32_t*)(smem + XR_ROWS * xd::NCH * 8);
-    for (int i = threadIdx.x; i < XR_ROWS * xd::NCH; i += blockDim.x) accs[i] = 0ull;
-    if (threadIdx.x < XR_ROWS) flags[threadIdx.x] = 0u;
-    __syncthreads();
-    double e[D][K];
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-#pragma unroll
-        for (int k = 0; k < K; ++k) e[d][k] = 0.0;
-    const int g = threadIdx.x / XR_GROUP, gl = threadIdx.x % XR_GROUP;
-    const int steps = (n + XR_ROWS - 1) / XR_ROWS;
-    for (int st = blockIdx.x; st < steps; st += gridDim.x) {
-        const int row = st * XR_ROWS + g;
-        const double v = exact_row<VT, RESID>(row < n ? row : -1, rp, ci, val, x, b, accs + g * xd::NCH,
-                                               flags + g, gl);
-        if (gl == 0 && row < n) {
-            double xa[D], ya[D];
-            epi.row(row, v, xa, ya);
-#pragma unroll
-            for (int d = 0; d < D; ++d) xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
-        }
-    }
-    __syncthreads();
-    xd::block_flush<D, K>(e, sh_acc);
-    xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
-}
-
-// epilogues taking the exactly rounded residual row r (not A x)
-template <class T>
-struct EpiResidX {          // r (and copies c1, c2 at initialisation)
-    T* r;
-    T* c1;
-    T* c2;
-    __device__ __forceinline__ void operator()(int row, T v) const {
-        r[row] = v;
-        if (c1) c1[row] = v;
-        if (c2) c2[row] = v;
-    }
-};
-template <class Fin>
-struct EpiResidXDot {       // r and the dot (r, r)
-    double* res;
-    Fin fin;
-    __device__ __forceinline__ void load() {}
-    __device__ __forceinline__ void row(int i, double v, double (&xa)[1], double (&ya)[1]) {
-        res[i] = v;
-        xa[0] = v;
-        ya[0] = v;
-    }
-    __device__ __forceinline__ void finalize(const double* d) { fin(d); }
-};
-
 // ----------------------------------------------------------------------------- FP32 plain dots
 
 // Plain FP32 dots: per-thread sequential sums in grid-stride order, xor-butterfly

@@ -56,7 +56,51 @@ def cases():
     rows = [[(c, float(c % 7) - 3.0) for c in range(1500)]] + [[] for _ in range(1499)]
     out.append(("long_row", csr_rows(rows, 1500), rng.uniform(-1, 1, 1500)))
     out.append(("rand_3000", g.problem("rand_1m", scale=3000).A, rng.uniform(-1, 1, 3000)))
+    A, x, _ = paths_case()
+    out.append(("paths_1400", A, x))
+    # long rows: 8 and 16 lanes per row on the register path (mean length 40 and 80)
+    for n, lo, hi in ((500, 20, 61), (400, 40, 121)):
+        rows = []
+        for i in range(n):
+            k = int(rng.integers(lo, hi))
+            cols = np.sort(rng.choice(n, size=k, replace=False))
+            e = rng.integers(-20, 20, k) if i % 5 else rng.integers(-200, 200, k)
+            rows.append(list(zip(cols.tolist(), (rng.standard_normal(k) * np.exp2(e)).tolist())))
+        out.append((f"long_rows_{n}", csr_rows(rows, n), rng.uniform(-1, 1, n)))
     return out
+
+
+def paths_case():
+    """Rows in blocks of 256 that exercise both row paths of the kernel: rows whose terms
+    span a few 32-bit chunks (summed by one lane in registers) and rows spanning more
+    (summed by 16 lanes in LDS): a block of narrow rows, a block of only wide rows, blocks
+    mixing the two with exact ties, cancellations and subnormal products, and a ragged
+    tail.  Returns (A, x, b), all finite."""
+    rng = np.random.default_rng(11)
+    n = 1400
+    x = rng.uniform(-1, 1, n) * np.exp2(rng.integers(-20, 20, n))
+    x[900:1000] = rng.choice([1.0, -1.0, 0.5, 2.0 ** -53, 3.0], 100)
+    x[1000:1100] = rng.uniform(-1, 1, 100) * 2.0 ** -540
+    rows = []
+    for i in range(n):
+        k = int(rng.integers(0, 24))
+        cols = np.sort(rng.choice(n, size=k, replace=False))
+        blk = i // 256
+        if blk == 1 or (blk in (2, 4) and i % 3 == 0):              # wide: 2^-90 .. 2^90
+            vals = rng.standard_normal(k) * np.exp2(rng.integers(-90, 90, k))
+        elif blk == 3:                                               # ties and cancellation
+            cols = np.sort(rng.choice(np.arange(900, 1000), size=min(k, 100), replace=False))
+            vals = rng.choice([1.0, -1.0, 2.0 ** 52, -(2.0 ** 52), 0.5], len(cols))
+        elif blk == 4 and i % 3 == 1:                                # subnormal products
+            cols = np.sort(rng.choice(np.arange(1000, 1100), size=min(k, 100), replace=False))
+            vals = rng.standard_normal(len(cols)) * 2.0 ** -540
+        else:
+            vals = rng.standard_normal(k)
+        rows.append(list(zip(cols.tolist(), vals.tolist())))
+    A = csr_rows(rows, n)
+    b = rng.uniform(-1, 1, n) * np.exp2(rng.integers(-40, 40, n))
+    b[768:1024] = rng.choice([0.0, 1.0, -2.0 ** -53, 2.0 ** 53], 256)
+    return A, x, b
 
 
 @pytest.mark.parametrize("name,A,x", cases(), ids=[c[0] for c in cases()])
@@ -106,6 +150,23 @@ def test_solve_exact_rows_bitwise(name, scale, mode):
     x, info = pk.solve(pk.CSR.from_host(p.A), to_dev(p.b), tol=1e-10, max_iter=2000, exact_rows=mode,
                        history=2000)
     assert info["status"] == ref.status == pk.OK
+    assert info["iterations"] == ref.iterations
+    assert np.array_equal(bits(info["history"]), bits(ref.history))
+    assert np.array_equal(bits(x.cpu().numpy()), bits(ref.x))
+    assert info["true_relres"] == ref.true_relres
+
+
+def test_solve_exact_rows_hard_rows():
+    """A few iterations from x0 on the mixed-path matrix: r0 = b - A x0 and every A v
+    with exactly rounded rows, both row paths and the residual form on ties, wide
+    exponents and subnormal products, bit for bit against the oracle."""
+    A, x0, b = paths_case()
+    ex = solvers.default_dot(A.n)
+    ref = solvers.pbicgstab(A, b, x0=x0, tol=1e-300, max_iter=4, dot=ex, spmv=spmv_exact,
+                            resid=lambda A_, b_, x_: resid_exact(A_, b_, x_))
+    x, info = pk.solve(pk.CSR.from_host(A), to_dev(b), x0=to_dev(x0), tol=1e-300, max_iter=4, exact_rows=2,
+                       history=4)
+    assert info["status"] == ref.status
     assert info["iterations"] == ref.iterations
     assert np.array_equal(bits(info["history"]), bits(ref.history))
     assert np.array_equal(bits(x.cpu().numpy()), bits(ref.x))
