@@ -215,8 +215,8 @@ def kernel_table(pk, torch, A, b, n, nnz, info, x, batch):
     dispatches (hipExtLaunchKernel: no markers between kernels, the launches keep their
     spacing).  Bytes per launch: the algorithmic figures -- 12 per nonzero + 20 per row
     for an SpMV (8-byte value, 4-byte column index; x once, y, row pointers), 104 and 80
-    per row for the phases -- and, for the SpMV, what the solve's layout moves (its
-    sliced copy stores 16-bit column residuals: 10 per nonzero + 20 per row)."""
+    per row for the phases -- and, for the SpMV, what the solve's layout moves
+    (layout_bytes)."""
     tsolver = pk.Solver(A, kernel_events=KEV, tol=1e-10, max_iter=10000)
     xk = torch.zeros(n, dtype=torch.float64, device=b.device)
     _, kinfo = tsolver.solve(b, xk)
@@ -224,9 +224,8 @@ def kernel_table(pk, torch, A, b, n, nnz, info, x, batch):
     ktimes = tsolver.kernel_times()
     del tsolver, xk
     used = max(1, min(KEV, info["iterations"] - 2 * batch))
-    col_bytes = 2 if info["sliced"] & 4 else 4
     spmv_alg = 12 * nnz + 20 * n
-    spmv_layout = (8 + col_bytes) * nnz + 20 * n
+    spmv_layout = layout_bytes(info, nnz, n)
     roles = {"phase_a": 104 * n, "spmv_az": spmv_alg, "phase_b": 80 * n, "spmv_aw": spmv_alg}
     kern = {}
     for name, nb in roles.items():
@@ -237,11 +236,35 @@ def kernel_table(pk, torch, A, b, n, nnz, info, x, batch):
     both = np.array(ktimes["spmv_az"][:used] + ktimes["spmv_aw"][:used])
     kern["spmv_seq"] = {"us": float(both.mean() * 1e6), "median_us": float(np.median(both) * 1e6),
                         "bytes": spmv_alg, "GBs": spmv_alg / both.mean() / 1e9, "launches": int(both.size),
-                        "layout": "sliced" if info["sliced"] & 1 else "csr",
+                        "layout": layout_name(info),
                         "layout_bytes": spmv_layout, "layout_GBs": spmv_layout / both.mean() / 1e9}
     for v in kern.values():
         v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
     return kern, used, sum(kern[k]["us"] for k in roles)
+
+
+def layout_name(info):
+    sl = info["sliced"]
+    if not sl & 1:
+        return "csr"
+    if sl & 64:
+        return "offset form (256-row slices, per-row slot mask)"
+    if sl & 16:
+        return "row-sorted sliced copy"
+    return "sliced copy (256-row slices%s)" % (", 16-bit column residuals" if sl & 4 else "")
+
+
+def layout_bytes(info, nnz, n):
+    """Bytes one SpMV of the solve moves with its layout: values (8 per stored slot), column
+    entries (4, or 2 as 16-bit residuals; none in the offset form, which reads a mask byte
+    per row and no row pointers), x once and y (8 + 8 per row), row pointers (4 per row)."""
+    sl, ent = info["sliced"], info.get("sliced_entries", 0)
+    if not sl & 1:
+        return 12 * nnz + 20 * n
+    if sl & 64:
+        return 8 * ent + 17 * n
+    col_bytes = 2 if sl & 4 else 4
+    return (8 + col_bytes) * ent + 20 * n
 
 
 def config_leg(pk, torch, g, dev, name, reps):
@@ -424,7 +447,8 @@ def traffic_run(pk, torch, A, b, n, nnz, dev):
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     _, info = solver.solve(b, x)
     torch.cuda.synchronize()
-    log(f"traffic run done (solve: {info['iterations']} iterations, status {info['status']})")
+    log(f"traffic run done (solve: {info['iterations']} iterations, status {info['status']}, "
+        f"layout {layout_name(info)}, layout_bytes {layout_bytes(info, nnz, n)})")
 
 
 def resident_leg(pk, torch, g, dev, reps, with_claim):
@@ -636,8 +660,7 @@ def main():
                                "(harmonic faces), v=(50,25,10), seed 3",
                    "n": n, "nnz": nnz, "tol": 1e-10, "x0": "0", "alg": "p-BiCGStab",
                    "dots": "exact (rounded once)",
-                   "spmv": "row-sequential, " + ("sliced copy (256-row slices%s)" % (
-                       ", 16-bit column residuals" if info["sliced"] & 4 else "") if info["sliced"] & 1 else "CSR")},
+                   "spmv": "row-sequential, " + layout_name(info)},
         "iterations": info["iterations"],
         "true_relres": info["true_relres"],
         "rel_err_vs_xstar": err_xstar,

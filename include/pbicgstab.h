@@ -72,17 +72,27 @@ typedef enum { PBCG_SPMV_SEQ = 0, PBCG_SPMV_VECTOR = 1, PBCG_SPMV_WAVE = 2 } pbc
  * test of a lucky breakdown stay exact in both. */
 typedef enum { PBCG_DOTS_EXACT = 0, PBCG_DOTS_PLAIN = 1 } pbcg_dots;
 
-/* Matrix layout of the solver's row-sequential SpMVs.  AUTO: the solver copies A (and
- * M) into the sliced layout of csr_slice when its padding stays within nnz/8 + 256
- * entries; the copy stores each column entry as a 16-bit residual col - row - base, with
- * one 32-bit base per slice and entry position (the smallest col - row there), when every
- * residual fits (2 bytes per entry less); otherwise it keeps CSR.  SORTED: a row-sorted
- * copy instead (when its padding fits the same bound): slices of 64 rows (one
- * wavefront), the rows of every window of 4096 consecutive rows ordered by decreasing
- * length so that each slice holds rows of nearly equal length, with a permutation back
- * to the row order (4 bytes per row).  CSR: never copied.  All give bit-identical
- * results: every row is still summed left to right in storage order by one lane. */
-typedef enum { PBCG_LAYOUT_AUTO = 0, PBCG_LAYOUT_CSR = 1, PBCG_LAYOUT_SORTED = 2 } pbcg_layout;
+/* Matrix layout of the solver's row-sequential SpMVs.  AUTO: the offset form when the
+ * rows of every 256-row slice draw their columns from at most 8 offsets col - row
+ * (banded and stencil matrices): per slice the offsets, per row a mask byte of the
+ * offsets it has and one value slot per offset (0 where it has none), no column entries
+ * and no row pointers read; its slots may exceed nnz by at most nnz/8 + 256.  Otherwise
+ * as SLICED.  SLICED: the sliced layout of csr_slice when its padding stays within
+ * nnz/8 + 256 entries; the copy stores each column entry as a 16-bit residual
+ * col - row - base, with one 32-bit base per slice and entry position (the smallest
+ * col - row there), when every residual fits (2 bytes per entry less); otherwise it
+ * keeps CSR.  SORTED: a row-sorted copy instead (when its padding fits the same bound):
+ * slices of 64 rows (one wavefront), the rows of every window of 4096 consecutive rows
+ * ordered by decreasing length so that each slice holds rows of nearly equal length,
+ * with a permutation back to the row order (4 bytes per row).  CSR: never copied.  All
+ * give bit-identical results: every row is still summed left to right in storage order
+ * by one lane. */
+typedef enum {
+    PBCG_LAYOUT_AUTO = 0,
+    PBCG_LAYOUT_CSR = 1,
+    PBCG_LAYOUT_SORTED = 2,
+    PBCG_LAYOUT_SLICED = 3
+} pbcg_layout;
 
 /* Square CSR matrix.  `val` points to nnz values of type `val_type`. */
 typedef struct {
@@ -158,10 +168,12 @@ typedef struct {
     int32_t fell_back;         /* 1 if the preconditioned solve fell back                    */
     int32_t sliced;            /* bit 0: A, bit 1: M ran on a sliced copy (layout AUTO);
                                   bit 2: A's, bit 3: M's copy holds 16-bit column residuals;
-                                  bit 4: A's, bit 5: M's copy is the row-sorted one        */
+                                  bit 4: A's, bit 5: M's copy is the row-sorted one;
+                                  bit 6: A's, bit 7: M's copy is the offset form           */
     double true_relres;        /* ||b - A x|| / ||b|| of the returned x (exact dots)         */
     double rec_relres;         /* last recursive ||r|| / ||b||                               */
     double seconds;            /* host wall time of the call                                 */
+    int64_t sliced_entries;    /* entries (value slots) of A's sliced copy; 0: A ran on CSR  */
 } pbcg_info;
 
 /* Device vectors of one p-BiCGStab iteration (for the phase entry points). */

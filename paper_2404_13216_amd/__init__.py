@@ -26,7 +26,7 @@ ALG_PBICGSTAB, ALG_BICGSTAB = 0, 1
 PREC_FP64, PREC_FP32_IR, PREC_FP32_MATRIX = 0, 1, 2
 SPMV_SEQ, SPMV_VECTOR, SPMV_WAVE = 0, 1, 2
 DOTS_EXACT, DOTS_PLAIN = 0, 1
-LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SORTED = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_CSR, LAYOUT_SORTED, LAYOUT_SLICED = 0, 1, 2, 3
 
 _P = ctypes.c_void_p
 
@@ -55,7 +55,7 @@ class PbcgInfo(ctypes.Structure):
                 ("outer_iterations", ctypes.c_int32), ("true_checks", ctypes.c_int32),
                 ("fell_back", ctypes.c_int32), ("sliced", ctypes.c_int32),
                 ("true_relres", ctypes.c_double), ("rec_relres", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("sliced_entries", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

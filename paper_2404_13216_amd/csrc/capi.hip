@@ -101,11 +101,18 @@ struct SliceView {
     bool d16 = false;   // column entries are 16-bit residuals from a per-position base
     const int32_t* base = nullptr;  // per slice and position (d16)
     const int32_t* perm = nullptr;  // row-sorted copy (64-row slices): the row of each slot
+    const uint8_t* mask = nullptr;  // offset form: per row, the slots it has
+    const int32_t* ofs = nullptr;   // offset form: per slice, OFS_MAX offsets col - row
 };
 
 // the runtime layout of a sliced copy -> the kernels' compile-time layout flags
 template <class F>
 void with_slf(const SliceView& v, F&& f) {
+    if (v.mask) {   // offset form: no column entries
+        if (v.nt) f(std::integral_constant<int, SL_OFS | SL_NT>{});
+        else f(std::integral_constant<int, SL_OFS>{});
+        return;
+    }
     if (v.perm) {   // row-sorted copies keep 32-bit columns
         if (v.nt) f(std::integral_constant<int, SL_PERM | SL_NT>{});
         else f(std::integral_constant<int, SL_PERM>{});
@@ -131,7 +138,7 @@ struct Mat {
 
 template <class VT>
 Sliced<VT> typed(const SliceView& v) {
-    return Sliced<VT>{v.off, v.col, (const VT*)v.val, v.base, v.perm};
+    return Sliced<VT>{v.off, v.col, (const VT*)v.val, v.base, v.perm, v.mask, v.ofs};
 }
 
 // A sliced copy is kept when its padding is at most nnz/8 + 256 entries.
@@ -200,6 +207,32 @@ int64_t build_wslices(const pbcg_csr* A, int32_t* perm, int64_t* off, int32_t* c
                                                      off, col, (float*)val);
     if (hipGetLastError() != hipSuccess) return -1;
     return total;
+}
+
+// Builds the offset form of A (n > 0): off[nslices + 2] (the last entry is scratch),
+// ofs[nslices * OFS_MAX], mask[nslices * 256] bytes, val[cap] (A's value type).  Returns the
+// slot count (above cap nothing was filled), 0 when some slice has more than OFS_MAX
+// offsets (nothing filled), or -1 on a HIP error.  Synchronises the stream once.
+int64_t build_ofs(const pbcg_csr* A, int64_t* off, int32_t* ofs, uint8_t* mask, void* val, int64_t cap,
+                  hipStream_t s) {
+    const int n = A->n, ns = nslices(n);
+    int* over = (int*)(off + ns + 1);
+    slice_clear_kernel<<<1, 1, 0, s>>>(off + ns + 1);
+    ofs_scan_kernel<<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, off, ofs, over);
+    slice_scan_kernel<<<1, 1024, 0, s>>>(ns, off);
+    int64_t tm[2] = {0, 0};   // slots, overflow flag
+    if (hipMemcpyAsync(tm, off + ns, sizeof(tm), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    if (tm[1] != 0) return 0;
+    if (tm[0] > cap) return tm[0];
+    if (A->val_type == PBCG_F64)
+        ofs_fill_kernel<double><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const double*)A->val, off, ofs, mask,
+                                                   (double*)val);
+    else
+        ofs_fill_kernel<float><<<ns, 256, 0, s>>>(n, A->row_ptr, A->col_idx, (const float*)A->val, off, ofs, mask,
+                                                  (float*)val);
+    if (hipGetLastError() != hipSuccess) return -1;
+    return tm[0];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -596,7 +629,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int n, const int* __restric
 
 extern "C" {
 
-int pbcg_abi_version(void) { return 7; }
+int pbcg_abi_version(void) { return 8; }
 
 const char* pbcg_status_string(int status) {
     switch (status) {
@@ -929,7 +962,8 @@ struct Work {
 };
 
 bool slicing_on(const pbcg_opts* o) {
-    return o && (o->layout == PBCG_LAYOUT_AUTO || o->layout == PBCG_LAYOUT_SORTED) && o->spmv_kind == PBCG_SPMV_SEQ;
+    return o && (o->layout == PBCG_LAYOUT_AUTO || o->layout == PBCG_LAYOUT_SORTED || o->layout == PBCG_LAYOUT_SLICED) &&
+           o->spmv_kind == PBCG_SPMV_SEQ;
 }
 
 Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts* o) {
@@ -959,13 +993,13 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
         W.a_col = c.take<int32_t>((size_t)slice_cap(nnz));
         W.a_val = c.take<double>((size_t)slice_cap(nnz));
         W.a_base = c.take<int32_t>((size_t)(slice_cap(nnz) / 256 + 1));
-        W.a_perm = c.take<int32_t>(N);
+        W.a_perm = c.take<int32_t>(std::max(N, (size_t)nslices(n) * OFS_MAX));   // or the offsets
         if (o->M) {
             W.m_off = c.take<int64_t>(slice_off_len(n));
             W.m_col = c.take<int32_t>((size_t)slice_cap(o->M->nnz));
             W.m_val = c.take<double>((size_t)slice_cap(o->M->nnz));
             W.m_base = c.take<int32_t>((size_t)(slice_cap(o->M->nnz) / 256 + 1));
-            W.m_perm = c.take<int32_t>(N);
+            W.m_perm = c.take<int32_t>(std::max(N, (size_t)nslices(n) * OFS_MAX));
         }
     }
     W.need = c.off + 256;
@@ -979,11 +1013,16 @@ Work carve_work(void* ws, size_t bytes, int32_t n, int64_t nnz, const pbcg_opts*
 // plain stores are faster.
 constexpr double INFINITY_CACHE_BYTES = 256.0 * 1024 * 1024;
 
-double matrix_bytes(const pbcg_csr* A, int64_t sliced_entries, int value_bytes, bool d16 = false) {
+// bytes one SpMV reads of the matrix: CSR, or a sliced copy of `sliced_entries` entries
+// (column entries of 2 bytes with d16; none in the offset form, which reads a mask byte per
+// row and its slices' offsets instead of the row pointers)
+double matrix_bytes(const pbcg_csr* A, int64_t sliced_entries, int value_bytes, bool d16 = false, bool ofs = false) {
     if (!A) return 0.0;
     const double entries = sliced_entries > 0 ? (double)sliced_entries : (double)A->nnz;
+    const double ns = nslices(A->n);
+    if (sliced_entries > 0 && ofs) return entries * value_bytes + 256.0 * ns + 8.0 * (ns + 1) + 4.0 * OFS_MAX * ns;
     return entries * (value_bytes + (d16 ? 2 : 4)) + 4.0 * ((double)A->n + 1) +
-           (sliced_entries > 0 ? 8.0 * (nslices(A->n) + 1) : 0.0);
+           (sliced_entries > 0 ? 8.0 * (ns + 1) : 0.0);
 }
 
 constexpr int CONTINUE = -100;
@@ -1360,7 +1399,10 @@ struct Driver {
         A32c.val_type = PBCG_F32;
         if (A.sl.off) {   // the FP32 values in the sliced order (padding casts to 0)
             launch_ew(FnCastVal{W.val32, (const double*)A.sl.val}, a_entries, nullptr, s);
-            A32 = Mat(&A32c, SliceView{A.sl.off, A.sl.col, W.val32, mnt32, A.sl.d16, A.sl.base, A.sl.perm});
+            SliceView v32 = A.sl;
+            v32.val = W.val32;
+            v32.nt = mnt32;
+            A32 = Mat(&A32c, v32);
         } else {
             launch_ew(FnCastVal{W.val32, (const double*)A->val}, A->nnz, nullptr, s);
             A32 = Mat(&A32c);
@@ -1520,7 +1562,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
     if (opts->spmv_kind < PBCG_SPMV_SEQ || opts->spmv_kind > PBCG_SPMV_WAVE) return PBCG_ERR_INVALID;
     if (opts->dots != PBCG_DOTS_EXACT && opts->dots != PBCG_DOTS_PLAIN) return PBCG_ERR_INVALID;
     if (opts->rr_period < 0) return PBCG_ERR_INVALID;
-    if (opts->layout < PBCG_LAYOUT_AUTO || opts->layout > PBCG_LAYOUT_SORTED) return PBCG_ERR_INVALID;
+    if (opts->layout < PBCG_LAYOUT_AUTO || opts->layout > PBCG_LAYOUT_SLICED) return PBCG_ERR_INVALID;
     if (opts->exact_rows < 0 || opts->exact_rows > 2) return PBCG_ERR_INVALID;
     if (opts->exact_rows > 0 && (opts->M || opts->alg != PBCG_ALG_PBICGSTAB || opts->prec != PBCG_PREC_FP64))
         return PBCG_ERR_INVALID;
@@ -1561,6 +1603,21 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
                         bool* d16, SliceView* v, int64_t* entries, int* sorted) -> int {
             const int64_t cap = slice_cap(B->nnz);
             int64_t t = cap + 1;
+            // AUTO: the offset form first (banded / stencil rows); its mask bytes live in the
+            // column array, its offsets in the permutation array
+            if (opts->layout == PBCG_LAYOUT_AUTO && (int64_t)nslices(B->n) * 256 <= 4 * cap) {
+                t = build_ofs(B, off, perm, (uint8_t*)col, val, cap, D.s);
+                if (t < 0) return -1;
+                if (t > 0 && t <= cap) {
+                    *v = SliceView{off, nullptr, val};
+                    v->mask = (const uint8_t*)col;
+                    v->ofs = perm;
+                    *entries = t;
+                    *d16 = false;
+                    *sorted = 2;
+                    return 1;
+                }
+            }
             if (opts->layout != PBCG_LAYOUT_SORTED) {
                 t = build_slices(B, off, col, val, base, cap, D.s, true, d16);
                 if (t < 0) return -1;
@@ -1586,31 +1643,32 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         int a_sorted = 0, m_sorted = 0;
         const int ra = make(A, W.a_off, W.a_col, W.a_val, W.a_base, W.a_perm, &a16, &D.A.sl, &D.a_entries, &a_sorted);
         if (ra < 0) return PBCG_ERR_HIP;
-        if (ra > 0) sliced |= 1 | (a_sorted ? 16 : 0);
+        if (ra > 0) sliced |= 1 | (a_sorted == 1 ? 16 : 0) | (a_sorted == 2 ? 64 : 0);
         if (opts->M) {
             const int rm = make(opts->M, W.m_off, W.m_col, W.m_val, W.m_base, W.m_perm, &m16, &D.M.sl, &m_entries,
                                 &m_sorted);
             if (rm < 0) return PBCG_ERR_HIP;
-            if (rm > 0) sliced |= 2 | (m_sorted ? 32 : 0);
+            if (rm > 0) sliced |= 2 | (m_sorted == 1 ? 32 : 0) | (m_sorted == 2 ? 128 : 0);
         }
     }
     {
         const int64_t ma = (sliced & 1) ? D.a_entries : 0;
         const int vb = (A->val_type == PBCG_F64 && opts->prec != PBCG_PREC_FP32_MATRIX) ? 8 : 4;
         const bool a16 = D.A.sl.d16, m16 = D.M.sl.d16;
-        double ws64 = matrix_bytes(A, ma, vb, a16) + 12.0 * 8.0 * A->n;
+        const bool ao = D.A.sl.mask != nullptr, mo = D.M.sl.mask != nullptr;
+        double ws64 = matrix_bytes(A, ma, vb, a16, ao) + 12.0 * 8.0 * A->n;
         if (opts->M) {
             const int64_t mm = (sliced & 2) ? m_entries : 0;
-            ws64 += matrix_bytes(opts->M, mm, opts->M->val_type == PBCG_F64 ? 8 : 4, m16) + 8.0 * A->n;
+            ws64 += matrix_bytes(opts->M, mm, opts->M->val_type == PBCG_F64 ? 8 : 4, m16, mo) + 8.0 * A->n;
         }
         D.nt64 = ws64 > INFINITY_CACHE_BYTES;
-        D.nt32 = matrix_bytes(A, ma, 4, a16) + 11.0 * 4.0 * A->n > INFINITY_CACHE_BYTES;
+        D.nt32 = matrix_bytes(A, ma, 4, a16, ao) + 11.0 * 4.0 * A->n > INFINITY_CACHE_BYTES;
         // a matrix that does not fit the cache at all streams past it as well (measured on
         // 256^3: 1.79 -> 1.69 s; a matrix that fits stays resident instead)
-        D.A.sl.nt = (sliced & 1) && matrix_bytes(A, ma, vb, a16) > INFINITY_CACHE_BYTES;
-        D.mnt32 = (sliced & 1) && matrix_bytes(A, ma, 4, a16) > INFINITY_CACHE_BYTES;
+        D.A.sl.nt = (sliced & 1) && matrix_bytes(A, ma, vb, a16, ao) > INFINITY_CACHE_BYTES;
+        D.mnt32 = (sliced & 1) && matrix_bytes(A, ma, 4, a16, ao) > INFINITY_CACHE_BYTES;
         if (opts->M && (sliced & 2))
-            D.M.sl.nt = matrix_bytes(opts->M, m_entries, opts->M->val_type == PBCG_F64 ? 8 : 4, m16) >
+            D.M.sl.nt = matrix_bytes(opts->M, m_entries, opts->M->val_type == PBCG_F64 ? 8 : 4, m16, mo) >
                         INFINITY_CACHE_BYTES;
         if (a16) sliced |= 4;
         if (m16) sliced |= 8;
@@ -1668,6 +1726,7 @@ int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_op
         info->iterations = opts->prec == PBCG_PREC_FP32_IR ? inner_total : h.iter + iters_before;
         info->fell_back = fell_back;
         info->sliced = sliced;
+        info->sliced_entries = (sliced & 1) ? D.a_entries : 0;
         info->outer_iterations = outer;
         info->true_checks = h.true_checks;
         info->true_relres = zr ? 0.0 : h.true_rel;

@@ -185,6 +185,8 @@ struct Sliced {
     const VT* val = nullptr;
     const int32_t* base = nullptr;  // SL_D16: per slice and position, at off[c] / 256 + k
     const int32_t* perm = nullptr;  // SL_PERM: the row held by each slot (slice height 64)
+    const uint8_t* mask = nullptr;  // SL_OFS: per row, bit j set when the row has column row + d_j
+    const int32_t* ofs = nullptr;   // SL_OFS: per slice, the offsets d_0 < d_1 < ... (OFS_MAX slots)
 };
 
 constexpr int SLICE_UNROLL = 8;   // entries of a row loaded ahead of their additions
@@ -207,6 +209,16 @@ constexpr int SL_NT = 1, SL_D16 = 2;
 constexpr int SL_PERM = 4;
 constexpr int WS_ROWS = 64;
 constexpr int WSORT = 4096;
+// SL_OFS: the offset form for banded and stencil matrices, where the rows of a slice draw
+// their columns from at most OFS_MAX offsets col - row.  Slice c lists its offsets
+// d_0 < ... < d_{K-1} once; slot j of row r holds the value of entry (r, r + d_j), or 0 when
+// the row has no such entry, and bit j of the row's mask byte says which slots exist.  No
+// column entries are stored: per row, K values and one byte against K values and K column
+// entries (and the row pointers) of the other forms.  Columns ascend within a row, so the
+// slots' order is the row's storage order and the lane adds the same products in the same
+// order (missing slots are skipped, never added).
+constexpr int SL_OFS = 8;
+constexpr int OFS_MAX = 8;
 
 template <class VT, class XT, class AT, bool COMP, int SLF = 0>
 __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, int len, const XT* __restrict__ x,
@@ -273,6 +285,48 @@ __device__ __forceinline__ void slice_row(const Sliced<VT>& sl, int c, int t, in
                 } else {
                     s = s + prod;
                 }
+            }
+        }
+    }
+}
+
+// One lane's row of slice c of an offset-form copy (SL_OFS): the K slot values of the row
+// (unit-stride across the slice), the x gathers of the slots the mask marks (unmarked slots
+// read x[0] and are not added), the additions in slot order.
+template <class VT, class XT, class AT, bool COMP, int SLF>
+__device__ __forceinline__ void slice_row_ofs(const Sliced<VT>& sl, int c, int t, const XT* __restrict__ x,
+                                              AT& s, AT& cmp) {
+    constexpr int R = 256;
+    constexpr bool MNT = (SLF & SL_NT) != 0;
+    const int64_t base = sl.off[c];
+    const int K = (int)((sl.off[c + 1] - base) / R);
+    const int row = c * R + t;
+    const uint32_t m = MNT ? (uint32_t)__builtin_nontemporal_load(sl.mask + row) : (uint32_t)sl.mask[row];
+    const int dl = sl.ofs[(int64_t)c * OFS_MAX + (threadIdx.x & (OFS_MAX - 1))];   // lane l: d_(l mod 8)
+    const VT* __restrict__ vp = sl.val + base + t;
+    VT av[OFS_MAX];
+#pragma unroll
+    for (int j = 0; j < OFS_MAX; ++j) {
+        av[j] = VT(0);
+        if (j < K) av[j] = MNT ? __builtin_nontemporal_load(vp + (int64_t)j * R) : vp[(int64_t)j * R];
+    }
+    XT xv[OFS_MAX];
+#pragma unroll
+    for (int j = 0; j < OFS_MAX; ++j) xv[j] = x[((m >> j) & 1u) ? row + __builtin_amdgcn_readlane(dl, j) : 0];
+#pragma unroll
+    for (int j = 0; j < OFS_MAX; ++j) {
+        if ((m >> j) & 1u) {
+            const AT a = (AT)av[j], xx = (AT)xv[j];
+            const AT prod = a * xx;
+            if constexpr (COMP) {
+                const float pe = fmaf(a, xx, -prod);
+                const float sn = s + prod;
+                const float bb = sn - s;
+                const float err = (s - (sn - bb)) + (prod - bb);
+                s = sn;
+                cmp = cmp + (err + pe);
+            } else {
+                s = s + prod;
             }
         }
     }
@@ -394,6 +448,13 @@ __device__ __forceinline__ void seq_stage(int n, const int32_t* __restrict__ rp,
             continue;
         }
         const int r0 = c * R, r1 = min(r0 + R, n), row = r0 + t;
+        if constexpr (SL && (SLF & SL_OFS) != 0) {
+            AT s = AT(0), cmp = AT(0);
+            slice_row_ofs<VT, XT, AT, COMP, SLF>(sl, c, t, x, s, cmp);
+            if constexpr (COMP) s = s + cmp;
+            if (row < r1) body(row, s);
+            continue;
+        }
         int RA = 0, RB = 0;
         if (row < r1) { RA = rp[row]; RB = rp[row + 1]; }
         AT s = AT(0), cmp = AT(0);
@@ -586,6 +647,75 @@ __global__ void __launch_bounds__(256) slice_fill_kernel(int n, const int32_t* _
             scol[i] = k < len ? ci[a + k] : 0;
         sval[i] = k < len ? val[a + k] : VT(0);
     }
+}
+
+// Offset form, step 1 (one block per slice): the slice's distinct offsets col - row in
+// ascending order into ofs[c][0 .. K) (unused slots 0), and off[c + 1] = 256 K; a slice with
+// more than OFS_MAX offsets sets *over.  Each round finds the smallest offset above the
+// previous one over the whole slice (lane minima, wave shuffles, then the 4 waves).
+__global__ void __launch_bounds__(256) ofs_scan_kernel(int n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, int64_t* __restrict__ off,
+                                                       int32_t* __restrict__ ofs, int* __restrict__ over) {
+    __shared__ long long smin[4];
+    const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
+    int a = 0, e = 0;
+    if (row < n) { a = rp[row]; e = rp[row + 1]; }
+    long long last = LLONG_MIN;
+    int K = 0;
+    for (int j = 0; j <= OFS_MAX; ++j) {
+        long long lo = LLONG_MAX;   // smallest offset of the row above `last` (columns ascend)
+        for (int k = a; k < e; ++k) {
+            const long long d = (long long)ci[k] - row;
+            if (d > last) { lo = d; break; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) lo = min(lo, (long long)__shfl_xor(lo, o));
+        if ((t & 63) == 0) smin[t >> 6] = lo;
+        __syncthreads();
+        lo = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
+        __syncthreads();
+        if (lo == LLONG_MAX) break;           // uniform over the block
+        if (j == OFS_MAX) {                   // one offset too many
+            if (t == 0) atomicOr(over, 1);
+            break;
+        }
+        if (t == 0) ofs[(int64_t)c * OFS_MAX + j] = (int32_t)lo;
+        last = lo;
+        K = j + 1;
+    }
+    if (t < OFS_MAX && t >= K) ofs[(int64_t)c * OFS_MAX + t] = 0;
+    if (t == 0) {
+        off[c + 1] = 256LL * K;
+        if (c == 0) off[0] = 0;
+    }
+}
+
+// Offset form, step 2 (one block per slice, after the prefix sums of off): slot values and
+// mask bytes of every row (rows past n: mask 0, values 0).
+template <class VT>
+__global__ void __launch_bounds__(256) ofs_fill_kernel(int n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const VT* __restrict__ val,
+                                                       const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ ofs, uint8_t* __restrict__ mask,
+                                                       VT* __restrict__ sval) {
+    const int c = blockIdx.x, t = threadIdx.x, row = c * 256 + t;
+    const int64_t base = off[c];
+    const int K = (int)((off[c + 1] - base) / 256);
+    int a = 0, e = 0;
+    if (row < n) { a = rp[row]; e = rp[row + 1]; }
+    uint32_t m = 0;
+    int k = a;
+    for (int j = 0; j < K; ++j) {
+        const long long d = ofs[(int64_t)c * OFS_MAX + j];
+        VT v = VT(0);
+        if (k < e && (long long)ci[k] - row == d) {
+            v = val[k];
+            m |= 1u << j;
+            ++k;
+        }
+        sval[base + (int64_t)j * 256 + t] = v;
+    }
+    mask[row] = (uint8_t)m;
 }
 
 // Row-sorted copy, step 1: perm over each window of WSORT rows, by decreasing row length

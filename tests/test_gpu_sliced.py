@@ -60,11 +60,34 @@ def sorted_entries(A):
     return int(64 * lp.reshape(nws, 64).max(axis=1).sum()) if nws else 0
 
 
-def expect_sliced_bits(A, layout=None):
-    """info['sliced'] of a solve with layout AUTO (or SORTED): bit 0 when a copy of A is
-    built, bit 2 when its column entries are 16-bit residuals, bit 4 when it is the
-    row-sorted copy (AUTO: when the 256-row copy's padding is too large)."""
+def ofs_slots(A):
+    """Host count of the offset form's value slots: 256 x the number of distinct offsets
+    col - row of every 256-row slice; None when some slice has more than 8 (or A has no
+    entries)."""
+    if A.nnz == 0:
+        return None
+    lens = np.diff(A.row_ptr.astype(np.int64))
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), lens)
+    d = A.col_idx.astype(np.int64) - rows
+    pairs = np.unique((rows // 256) * (1 << 33) + (d + (1 << 32)))
+    cnt = np.bincount(pairs >> 33, minlength=(A.n + 255) // 256)
+    return None if cnt.max() > 8 else int(256 * cnt.sum())
+
+
+def expect_ofs(A):
     cap = A.nnz + A.nnz // 8 + 256
+    t = ofs_slots(A)
+    return t is not None and t <= cap and ((A.n + 255) // 256) * 256 <= 4 * cap
+
+
+def expect_sliced_bits(A, layout=None):
+    """info['sliced'] of a solve with layout AUTO, SLICED or SORTED: bit 0 when a copy of A
+    is built, bit 2 when its column entries are 16-bit residuals, bit 4 when it is the
+    row-sorted copy, bit 6 when it is the offset form (AUTO: when every slice has at most
+    8 offsets, else as SLICED)."""
+    cap = A.nnz + A.nnz // 8 + 256
+    if layout in (None, pk.LAYOUT_AUTO) and expect_ofs(A):
+        return 1 | 64
     if layout != pk.LAYOUT_SORTED:
         return (1 | (4 if max_spread(A) <= 65535 else 0)) if expect_built(A) else 0
     return (1 | 16) if sorted_entries(A) <= cap else 0
@@ -168,18 +191,22 @@ def test_preconditioned_solve_slices_m():
     A = pk.CSR.from_host(p.A)
     b = to_dev(p.b)
     J = pk.jacobi(A)
-    xa, ia = pk.solve(A, b, M=J, tol=1e-10)
     xc, ic = pk.solve(A, b, M=J, tol=1e-10, layout=pk.LAYOUT_CSR)
-    assert ia["sliced"] == 1 | 2 | 4 | 8 and ic["sliced"] == 0   # both copies with 16-bit offsets
-    assert ia["iterations"] == ic["iterations"]
-    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+    assert ic["sliced"] == 0
+    # AUTO: both copies in the offset form; SLICED: both with 16-bit column residuals
+    for layout, bits in ((pk.LAYOUT_AUTO, 1 | 2 | 64 | 128), (pk.LAYOUT_SLICED, 1 | 2 | 4 | 8)):
+        xa, ia = pk.solve(A, b, M=J, tol=1e-10, layout=layout)
+        assert ia["sliced"] == bits
+        assert ia["iterations"] == ic["iterations"]
+        assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
     # M on A's pattern: scaled copy of A's values
     M = A.with_values(A.val * 0.5)
-    xa, ia = pk.solve(A, b, M=M, tol=1e-10, max_iter=50)
     xc, ic = pk.solve(A, b, M=M, tol=1e-10, max_iter=50, layout=pk.LAYOUT_CSR)
-    assert ia["sliced"] == 1 | 2 | 4 | 8
-    assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
-    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+    for layout, bits in ((pk.LAYOUT_AUTO, 1 | 2 | 64 | 128), (pk.LAYOUT_SLICED, 1 | 2 | 4 | 8)):
+        xa, ia = pk.solve(A, b, M=M, tol=1e-10, max_iter=50, layout=layout)
+        assert ia["sliced"] == bits
+        assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
+        assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
 
 
 @pytest.mark.parametrize("prec", [pk.PREC_FP64, pk.PREC_FP32_IR])
@@ -190,12 +217,12 @@ def test_solve_sliced_32bit_columns(prec):
     p = g.problem("cd2d_64", scale=300)                    # n = 90,000
     Ah = with_long_range_entry(p.A, -1e-3 * p.A.val[0])
     assert max_spread(Ah) > 65535 and expect_built(Ah)
-    assert max_spread(p.A) <= 65535 and expect_sliced_bits(p.A) == 5
+    assert max_spread(p.A) <= 65535 and expect_sliced_bits(p.A, pk.LAYOUT_SLICED) == 5
     xs = np.random.default_rng(3).uniform(-1, 1, Ah.n)
     bh = spmv(Ah, xs)
     A = pk.CSR.from_host(Ah)
     b = to_dev(bh)
-    xa, ia = pk.solve(A, b, tol=1e-10, max_iter=60, prec=prec)
+    xa, ia = pk.solve(A, b, tol=1e-10, max_iter=60, prec=prec, layout=pk.LAYOUT_SLICED)
     xc, ic = pk.solve(A, b, tol=1e-10, max_iter=60, prec=prec, layout=pk.LAYOUT_CSR)
     assert ia["sliced"] == 1 and ic["sliced"] == 0
     assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
@@ -240,7 +267,7 @@ def test_solve_ragged_16bit_residuals(name):
     oracle."""
     A0 = wide_rows() if name == "wide_rows" else dict(cases())[name]
     Ah = dominant(A0)
-    assert expect_sliced_bits(Ah) == 5, (name, max_spread(Ah), expect_built(Ah))
+    assert expect_sliced_bits(Ah) == 5, (name, max_spread(Ah), expect_built(Ah))   # too many offsets for AUTO's offset form
     xs = np.random.default_rng(9).uniform(-1, 1, Ah.n)
     bh = spmv(Ah, xs)
     A = pk.CSR.from_host(Ah)
@@ -313,3 +340,65 @@ def test_row_sorted_preconditioner():
     assert ia["sliced"] == 1 | 2 | 16 | 32 and ic["sliced"] == 0
     assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
     assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+
+
+def banded(n, offsets, seed, drop=0.03, extra=None):
+    """Rows with entries at row + d for d in `offsets` (inside [0, n)), each dropped with
+    probability `drop` (the diagonal kept), every 41st row empty but its diagonal; `extra`:
+    (row, offset) entries added to make one slice exceed 8 offsets."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        cols = [i + d for d in offsets if 0 <= i + d < n and (d == 0 or (i % 41 and rng.random() >= drop))]
+        if extra and i == extra[0]:
+            cols.append(i + extra[1])
+        cols = sorted(set(cols))
+        rows.append([(c, float(rng.standard_normal())) for c in cols])
+    rp, ci, va = [0], [], []
+    for r in rows:
+        ci += [c for c, _ in r]
+        va += [v for _, v in r]
+        rp.append(len(ci))
+    return dominant(g.CSR(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va)))
+
+
+def offset_cases():
+    offs8 = (-300, -17, -1, 0, 1, 17, 300, 512)
+    return [("cd2d_64", g.problem("cd2d_64").A), ("cd3d_128_s20", g.problem("cd3d_128", scale=20).A),
+            ("cd3d_256_var_s17", g.problem("cd3d_256_var", scale=17).A),
+            ("spai_eval_128_s9", g.problem("spai_eval_128", scale=9).A),
+            ("banded8_1000", banded(1000, offs8, 21)),                            # 8 offsets, ragged tail
+            ("banded5_700", banded(700, (-40, -1, 0, 1, 40), 22)),
+            ("banded9_1000", banded(1000, offs8, 23, extra=(300, 650)))]           # slice 1: 9 offsets
+
+
+@pytest.mark.parametrize("name,Ah", offset_cases(), ids=[c[0] for c in offset_cases()])
+def test_solve_offset_form_bitwise(name, Ah):
+    """The offset form (per slice the offsets col - row, per row a mask byte and one value
+    slot per offset): stencils with their boundary rows, banded rows with random missing
+    entries and empty rows, a ragged tail; a slice with 9 offsets keeps the column form.
+    Same bits as on CSR and as the oracle: 8 iterations, then to convergence in FP64, the
+    FP32 refinement (Dot2 FP32 SpMV on the form) and the FP32-matrix form."""
+    want = expect_sliced_bits(Ah)
+    assert (want == 65) == (name != "banded9_1000"), (name, ofs_slots(Ah))
+    xs = np.random.default_rng(9).uniform(-1, 1, Ah.n)
+    bh = spmv(Ah, xs)
+    A = pk.CSR.from_host(Ah)
+    b = to_dev(bh)
+    xa, ia = pk.solve(A, b, tol=1e-10, max_iter=8)
+    xc, ic = pk.solve(A, b, tol=1e-10, max_iter=8, layout=pk.LAYOUT_CSR)
+    assert ia["sliced"] == want and ic["sliced"] == 0
+    if want == 65:
+        assert ia["sliced_entries"] == ofs_slots(Ah)
+    assert ia["status"] == ic["status"] and ia["iterations"] == ic["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64))
+    ora = ctier.pbicgstab(Ah, bh, tol=1e-10, max_iter=8)
+    assert ora["iterations"] == ia["iterations"]
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), ora["x"].view(np.uint64))
+    for prec in (pk.PREC_FP64, pk.PREC_FP32_IR, pk.PREC_FP32_MATRIX):
+        xa, ia = pk.solve(A, b, tol=1e-10, prec=prec, max_iter=3000)
+        xc, ic = pk.solve(A, b, tol=1e-10, prec=prec, max_iter=3000, layout=pk.LAYOUT_CSR)
+        assert ia["sliced"] & 65 == want & 65
+        for k in ("status", "iterations", "outer_iterations", "true_checks"):
+            assert ia[k] == ic[k], (prec, k)
+        assert np.array_equal(xa.cpu().numpy().view(np.uint64), xc.cpu().numpy().view(np.uint64)), prec

@@ -56,7 +56,7 @@ def test_struct_layout_matches_header(tmp_path):
         assert lay[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert lay[(cname, f)] == getattr(py, f).offset, (cname, f)
-    assert pk.lib().pbcg_abi_version() == 7
+    assert pk.lib().pbcg_abi_version() == 8
 
 
 def test_status_strings_and_defaults():
