@@ -369,18 +369,20 @@ def offset_cases():
             ("spai_eval_128_s9", g.problem("spai_eval_128", scale=9).A),
             ("banded8_1000", banded(1000, offs8, 21)),                            # 8 offsets, ragged tail
             ("banded5_700", banded(700, (-40, -1, 0, 1, 40), 22)),
-            ("banded9_1000", banded(1000, offs8, 23, extra=(300, 650)))]           # slice 1: 9 offsets
+            ("banded9_1000", banded(1000, offs8, 23, extra=(300, 650))),           # slice 1: 9 offsets
+            ("banded8_sparse", banded(1000, offs8, 24, drop=0.3))]                 # slots above nnz/8 + 256
 
 
 @pytest.mark.parametrize("name,Ah", offset_cases(), ids=[c[0] for c in offset_cases()])
 def test_solve_offset_form_bitwise(name, Ah):
     """The offset form (per slice the offsets col - row, per row a mask byte and one value
     slot per offset): stencils with their boundary rows, banded rows with random missing
-    entries and empty rows, a ragged tail; a slice with 9 offsets keeps the column form.
+    entries and empty rows, a ragged tail; a slice with 9 offsets, and slots beyond
+    nnz + nnz/8 + 256, keep the column form.
     Same bits as on CSR and as the oracle: 8 iterations, then to convergence in FP64, the
     FP32 refinement (Dot2 FP32 SpMV on the form) and the FP32-matrix form."""
     want = expect_sliced_bits(Ah)
-    assert (want == 65) == (name != "banded9_1000"), (name, ofs_slots(Ah))
+    assert (want == 65) == (name not in ("banded9_1000", "banded8_sparse")), (name, ofs_slots(Ah))
     xs = np.random.default_rng(9).uniform(-1, 1, Ah.n)
     bh = spmv(Ah, xs)
     A = pk.CSR.from_host(Ah)
