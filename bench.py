@@ -35,7 +35,7 @@ Also reported (outside the timed steps):
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--solve-only]
                        [--legs cd3d_128,claim,cd2d_64,learned,rand_1m] [--epochs 30]
-                       [--traffic-run [--workload cd3d_256_var|cd3d_128]]
+                       [--traffic-run [--workload cd3d_256_var|cd3d_128]] [--infer-run]
 """
 import argparse
 import hashlib
@@ -451,6 +451,23 @@ def traffic_run(pk, torch, A, b, n, nnz, dev):
         f"layout {layout_name(info)}, layout_bytes {layout_bytes(info, nnz, n)})")
 
 
+def infer_run(pk, torch, g, dev):
+    """The bf16 inference kernel alone, for rocprofv3 counter runs: the held-out 128^3
+    matrix's features, the 5,057 MLP parameters drawn from a seeded N(0, 0.05^2) (the
+    kernel's work does not depend on their values: no data-dependent branches), 10
+    launches."""
+    from paper_2404_13216_amd import spai
+    ev = g.problem("spai_eval_128")
+    A = pk.CSR.from_host(ev.A, dev)
+    sm = spai.SpaiMatrix(A)
+    nparam = pk.lib().spai_param_count()
+    params = torch.from_numpy((np.random.default_rng(0).standard_normal(nparam) * 0.05).astype(np.float32)).to(dev)
+    for _ in range(10):
+        sm.m_bf16(params)
+    torch.cuda.synchronize()
+    log(f"infer run done (nnz {ev.A.nnz}, 10 launches)")
+
+
 def resident_leg(pk, torch, g, dev, reps, with_claim):
     """The 128^3 constant-coefficient workload: its 146 MB sliced matrix stays in the
     256 MB Infinity Cache across the iteration (the phases stream the vectors past it),
@@ -590,6 +607,9 @@ def main():
     ap.add_argument("--traffic-run", action="store_true",
                     help="launch each measured kernel 10 times (for rocprofv3 --pmc runs) and exit")
     ap.add_argument("--workload", default=HEADLINE, help="workload of --traffic-run")
+    ap.add_argument("--infer-run", action="store_true",
+                    help="launch the bf16 inference on the held-out 128^3 matrix 10 times (for rocprofv3 "
+                         "counter runs) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: bench.py measures one GPU's throughput; "
@@ -602,6 +622,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if args.infer_run:
+        infer_run(pk, torch, g, dev)
+        return
     t0 = time.time()
     wl = args.workload if args.traffic_run else HEADLINE
     prob = g.problem(wl)
