@@ -31,6 +31,9 @@ constexpr int IR_FP64_FINISH = 10000; // iteration limit of the FP64 finish afte
 constexpr int IR_FINISH_RR = 50;      // residual replacement period of that finish
 constexpr int IR_BATCH = 4;           // FP32 iterations enqueued between status polls (at most)
 constexpr int KEXP = 3;              // expansion terms per lane in the solver kernels
+constexpr int EXDOT_U = 4;           // elements per lane and trip of a single exact dot (2 loads each)
+constexpr int EXDOT_BLOCK = 1024;    // threads per block of the standalone exact dot
+constexpr int PHASE_U = 2;           // the same for the fused phases (7 or 8 loads each)
 constexpr double INFINITY_CACHE_BYTES_D = 256.0 * 1024 * 1024;   // MI355X Infinity Cache
 constexpr int FP32M_RR = 50;          // default replacement period of the FP32-matrix form
 
@@ -417,14 +420,14 @@ XFin<D, Op, GM> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const in
     grid = std::min(grid, GM);
     if constexpr (D == 1) {  // the standalone dot exposes the expansion length
 #define EW_CASE(KK) \
-    case KK: ew_dot_kernel<D, KK, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen); break;
+    case KK: ew_dot_kernel<D, KK, Op, EXDOT_U><<<grid, block, 0, s>>>(op, n, site, halt, seen); break;
         switch (K) {
             EW_CASE(2) EW_CASE(3) EW_CASE(4) EW_CASE(6) EW_CASE(8)
-            default: ew_dot_kernel<D, KEXP, Op><<<grid, block, 0, s>>>(op, n, site, halt, seen);
+            default: ew_dot_kernel<D, KEXP, Op, EXDOT_U><<<grid, block, 0, s>>>(op, n, site, halt, seen);
         }
 #undef EW_CASE
     } else {
-        klaunch(ew_dot_kernel<D, KEXP, Op>, grid, block, 0, s, op, n, site, halt, seen);
+        klaunch(ew_dot_kernel<D, KEXP, Op, PHASE_U>, grid, block, 0, s, op, n, site, halt, seen);
     }
     return XFin<D, Op, GM>{op, site, grid, halt};
 }
@@ -847,25 +850,27 @@ int exdot_noalloc(int64_t n, const double* x, const double* y, double* out, void
     void* base = nullptr;
     const int rc = scratch_address(s, &base);
     if (rc != PBCG_OK) return rc;
-    const int64_t per = (int64_t)DOT_BLOCK * 8;
-    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, NOALLOC_GRID));
+    const int64_t per = (int64_t)EXDOT_BLOCK * 8;
+    const int gmax = n > (int64_t(1) << 25) ? 256 : NOALLOC_GRID;
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, gmax));
     // every launched block writes its whole record before the finalize reads it, so
     // nothing in the scratch array has to start at zero
     xd::Site site;
     site.hdr = (xd::RecHdr*)base;
     site.dig = (long long*)((char*)base + NOALLOC_HDR);
-    exdot_launch(n, x, y, out, site, s, g, DOT_BLOCK, KEXP);
+    exdot_launch(n, x, y, out, site, s, g, EXDOT_BLOCK, KEXP);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
 
 int exdot(int64_t n, const double* x, const double* y, double* out, void* ws, size_t ws_bytes, void* stream) {
-    // a standalone dot streams only two vectors: up to 512 blocks (at least 8 elements per
-    // lane) keep enough loads in flight -- 2^26 elements 4.1 -> 5.8 TB/s against 256 blocks;
-    // the result bits do not depend on the shape
-    const int64_t per = (int64_t)DOT_BLOCK * 8;
-    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 512));
-    return exdot_config(n, x, y, out, g, DOT_BLOCK, KEXP, ws, ws_bytes, stream);
+    // a standalone dot streams only two vectors: blocks of 1024 threads, 4 elements per lane
+    // and trip, 512 blocks up to 2^25 elements and 256 above (at least 8 elements per lane)
+    // keep enough loads in flight; the result bits do not depend on the shape
+    const int64_t per = (int64_t)EXDOT_BLOCK * 8;
+    const int gmax = n > (int64_t(1) << 25) ? 256 : 512;
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, gmax));
+    return exdot_config(n, x, y, out, g, EXDOT_BLOCK, KEXP, ws, ws_bytes, stream);
 }
 
 size_t plain_dot_workspace_bytes(int64_t n) {

@@ -808,7 +808,9 @@ __global__ void __launch_bounds__(256) wslice_fill_kernel(int n, int nws, const 
 //   ld(i, in[NIN])              global loads of element i
 //   st(i, in, xa[D], ya[D])     updates and stores of element i; dot operands
 //   finalize(const double* d)   run by a finalize role (XFin) once the records are summed
-template <int D, int K, class Op>
+// U elements per lane and trip: all U elements' loads are issued before the dependent
+// exact-accumulation work of the first (the result is the exact sum whatever the order).
+template <int D, int K, class Op, int U = 2>
 __global__ void __launch_bounds__(1024)
 ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt, int* seen) {
     if (halt && *halt) {
@@ -823,29 +825,26 @@ ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt, int* seen) {
     for (int d = 0; d < D; ++d)
 #pragma unroll
         for (int k = 0; k < K; ++k) e[d][k] = 0.0;
-    // grid-stride loop, two elements per trip: both elements' loads are issued before
-    // the dependent exact-accumulation work of the first
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + stride < n; i += 2 * stride) {
-        double ia[Op::NIN], ib[Op::NIN];
-        op.ld(i, ia);
-        op.ld(i + stride, ib);
-        double xa[D], ya[D];
-        op.st(i, ia, xa, ya);
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        double in[U][Op::NIN];
 #pragma unroll
-        for (int d = 0; d < D; ++d)
-            xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
-        op.st(i + stride, ib, xa, ya);
+        for (int u = 0; u < U; ++u) op.ld(i + u * stride, in[u]);
 #pragma unroll
-        for (int d = 0; d < D; ++d)
-            xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+        for (int u = 0; u < U; ++u) {
+            double xa[D], ya[D];
+            op.st(i + u * stride, in[u], xa, ya);
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+        }
     }
-    if (i < n) {
-        double ia[Op::NIN];
-        op.ld(i, ia);
+    for (; i < n; i += stride) {
+        double in[Op::NIN];
+        op.ld(i, in);
         double xa[D], ya[D];
-        op.st(i, ia, xa, ya);
+        op.st(i, in, xa, ya);
 #pragma unroll
         for (int d = 0; d < D; ++d)
             xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
