@@ -285,7 +285,6 @@ int plain_dot(int64_t n, const void* x, const void* y, int32_t dtype, void* out,
               void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------
- * Allocation-free exact dot/* ---------------------------------------------------------------------------------
  * Allocation-free exact dot, for callers that cannot allocate device memory or pass a
  * workspace (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same result as exdot, bit for bit, with the same kernels; the per-block

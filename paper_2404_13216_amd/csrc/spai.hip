@@ -176,7 +176,7 @@ __device__ __forceinline__ float mlp_forward(const SmemW& s, const float* x, flo
 }
 
 __global__ void __launch_bounds__(BLOCK) k_forward(int64_t nnz, const float* __restrict__ feat, const float* __restrict__ params,
-                                                   const int* __restrict__ rowidx, const int32_t* __restrict__ ci,
+                                                   const int* __restrict__ rowidx,
                                                    const double* __restrict__ diag, float* __restrict__ fout,
                                                    float* __restrict__ mout) {
     __shared__ SmemW s;
@@ -559,7 +559,7 @@ int spai_forward(int64_t nnz, const float* feat, const float* params, const int3
                  const double* diag, float* f_out, float* m_out, void* stream) {
     if (nnz <= 0 || !feat || !params || !rowidx || !col_idx || !diag || !m_out) return PBCG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    k_forward<<<grid_for(nnz), BLOCK, 0, s>>>(nnz, feat, params, rowidx, col_idx, diag, f_out, m_out);
+    k_forward<<<grid_for(nnz), BLOCK, 0, s>>>(nnz, feat, params, rowidx, diag, f_out, m_out);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
@@ -613,7 +613,7 @@ int spai_loss_grad(const pbcg_csr* A, const float* feat, const int32_t* rowidx, 
     const int64_t nnz = A->nnz;
     const float scale_loss = 1.0f / ((float)k * (float)n);
     const float scale_grad = 2.0f / ((float)k * (float)n);
-    k_forward<<<grid_for(nnz), BLOCK, 0, s>>>(nnz, feat, params, rowidx, A->col_idx, diag, nullptr, m_tmp);
+    k_forward<<<grid_for(nnz), BLOCK, 0, s>>>(nnz, feat, params, rowidx, diag, nullptr, m_tmp);
     const int nb = (n + BLOCK - 1) / BLOCK;
     k_residual<<<nb, BLOCK, 0, s>>>(n, k, A->row_ptr, A->col_idx, m_tmp, U, V, w.R, w.part);
     k_loss<<<1, 64, 0, s>>>(nb, w.part, scale_loss, loss);
