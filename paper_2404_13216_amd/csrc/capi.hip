@@ -377,8 +377,13 @@ void launch_spmv_exact(const Mat& A, const double* x, const double* b, Epi epi, 
     if (grid <= 0) return;
     auto go = [&](auto vt, auto f) {
         using VT = decltype(vt);
-        klaunch(spmv_exact_kernel<VT, Epi, Fin, RESID, decltype(f)::value>, grid, BLOCK, 0, s, n, A->row_ptr,
-                A->col_idx, (const VT*)A->val, x, b, epi, fin, halt);
+        constexpr bool F = decltype(f)::value;
+        if (F && A.sl.mask)   // the register path reads the offset form when the solver has one
+            klaunch(spmv_exact_kernel<VT, Epi, Fin, RESID, true, true>, grid, BLOCK, 0, s, n, A->row_ptr,
+                    A->col_idx, (const VT*)A->val, x, b, epi, fin, halt, typed<VT>(A.sl));
+        else
+            klaunch(spmv_exact_kernel<VT, Epi, Fin, RESID, F>, grid, BLOCK, 0, s, n, A->row_ptr, A->col_idx,
+                    (const VT*)A->val, x, b, epi, fin, halt, Sliced<VT>{});
     };
     if (A->val_type == PBCG_F64) {
         if (fast) go(double{}, std::true_type{});
@@ -398,8 +403,13 @@ void launch_spmv_exact_dot(const Mat& A, const double* x, const double* b, Epi e
     const int grid = std::max(1, std::min(DOT_GRID_MAX, (n + rows - 1) / rows));
     auto go = [&](auto vt, auto f) {
         using VT = decltype(vt);
-        spmv_exact_dot_kernel<D, KEXP, VT, Epi, RESID, decltype(f)::value><<<grid, BLOCK, 0, s>>>(
-            n, A->row_ptr, A->col_idx, (const VT*)A->val, x, b, epi, site, halt);
+        constexpr bool F = decltype(f)::value;
+        if (F && A.sl.mask)
+            spmv_exact_dot_kernel<D, KEXP, VT, Epi, RESID, true, true><<<grid, BLOCK, 0, s>>>(
+                n, A->row_ptr, A->col_idx, (const VT*)A->val, x, b, epi, site, halt, typed<VT>(A.sl));
+        else
+            spmv_exact_dot_kernel<D, KEXP, VT, Epi, RESID, F><<<grid, BLOCK, 0, s>>>(
+                n, A->row_ptr, A->col_idx, (const VT*)A->val, x, b, epi, site, halt, Sliced<VT>{});
     };
     if (A->val_type == PBCG_F64) {
         if (fast) go(double{}, std::true_type{});

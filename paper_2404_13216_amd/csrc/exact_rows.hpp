@@ -323,21 +323,94 @@ __device__ __forceinline__ bool exact_row_fast(int row, const int32_t* __restric
     return true;
 }
 
+// The same from the offset form of A (slice c = the row's 256-row slice, t its lane): the
+// row's value slots (unit-stride across the slice), its mask byte and the slice's offsets,
+// all loaded together; every term is held (at most OFS_MAX), none is read twice.
+template <class VT, bool RESID>
+__device__ __forceinline__ bool exact_row_fast_ofs(int row, int c, int t, const Sliced<VT>& sl,
+                                                   const double* __restrict__ x, const double* __restrict__ b,
+                                                   double& v) {
+    const int64_t base = sl.off[c];
+    const int K = (int)((sl.off[c + 1] - base) / 256);
+    const uint32_t m = sl.mask[row];
+    double ha[OFS_MAX], hx[OFS_MAX];
+    int hc[OFS_MAX];
+#pragma unroll
+    for (int j = 0; j < OFS_MAX; ++j) {
+        ha[j] = 0.0;
+        hc[j] = 0;
+        if (j < K) {
+            ha[j] = (double)sl.val[base + (int64_t)j * 256 + t];
+            if ((m >> j) & 1u) hc[j] = row + sl.ofs[(int64_t)c * OFS_MAX + j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < OFS_MAX; ++j) hx[j] = x[hc[j]];       // an unmarked slot reads x[0]
+    uint32_t fl = 0;
+    int cmin = INT_MAX, cmax = INT_MIN;
+#pragma unroll
+    for (int j = 0; j < OFS_MAX; ++j) {
+        if ((m >> j) & 1u) xr_scan<RESID>(ha[j], hx[j], fl, cmin, cmax);
+    }
+    double bv = 0.0;
+    if constexpr (RESID) {
+        bv = b[row];
+        if (!isfinite(bv)) {
+            if (isnan(bv)) fl |= xd::F_NAN;
+            else fl |= bv > 0.0 ? xd::F_PINF : xd::F_NINF;
+        } else if (bv != 0.0) {
+            uint64_t mb;
+            int P;
+            bool ng;
+            xd::decompose(bv, mb, P, ng);
+            cmin = min(cmin, P >> 5);
+            cmax = max(cmax, P >> 5);
+        }
+    }
+    if (fl) {
+        if ((fl & xd::F_NAN) || ((fl & xd::F_PINF) && (fl & xd::F_NINF))) v = __longlong_as_double(0x7ff8000000000000ll);
+        else v = (fl & xd::F_PINF) ? __longlong_as_double(0x7ff0000000000000ll)
+                                   : __longlong_as_double((long long)0xfff0000000000000ull);
+        return true;
+    }
+    if (cmin > cmax) {
+        v = 0.0;
+        return true;
+    }
+    if (cmax - cmin > XW - 5) return false;
+    long long w[XW];
+#pragma unroll
+    for (int j = 0; j < XW; ++j) w[j] = 0;
+#pragma unroll
+    for (int j = 0; j < OFS_MAX; ++j) {
+        if (((m >> j) & 1u) && ha[j] != 0.0 && hx[j] != 0.0) xw_add_product(w, cmin, RESID ? -ha[j] : ha[j], hx[j]);
+    }
+    if constexpr (RESID) {
+        if (bv != 0.0) xw_add_double(w, cmin, bv);
+    }
+    v = xw_round(w, cmin);
+    return true;
+}
+
 // One chunk of 256 rows for a block of 256 threads: each lane its own row on the fast
-// path, then the rows that need the LDS path in groups of 16 lanes; `out(row, value)` for
+// path (OFS: read from the offset form sl, whose slices are these chunks), then the rows
+// that need the LDS path in groups of 16 lanes (read from CSR); `out(row, value)` for
 // every row of the chunk.  accs / flags: the LDS path's accumulators (zero), list: 256
 // ints, count: two ints used alternately (parity = the block's chunk counter; both zero
 // before the first chunk).  Block-uniform.
-template <class VT, bool RESID, class Out>
+template <class VT, bool RESID, bool OFS, class Out>
 __device__ __forceinline__ void exact_rows_chunk(int r0, int n, int parity, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci, const VT* __restrict__ val,
                                                  const double* __restrict__ x, const double* __restrict__ b,
-                                                 unsigned long long* accs, uint32_t* flags, int* list, int* count,
-                                                 Out& out) {
+                                                 const Sliced<VT>& sl, unsigned long long* accs, uint32_t* flags,
+                                                 int* list, int* count, Out& out) {
     const int t = threadIdx.x, row = r0 + t;
     if (row < n) {
         double v;
-        if (exact_row_fast<VT, RESID>(row, rp, ci, val, x, b, v)) out(row, v);
+        bool done;
+        if constexpr (OFS) done = exact_row_fast_ofs<VT, RESID>(row, r0 / 256, t, sl, x, b, v);
+        else done = exact_row_fast<VT, RESID>(row, rp, ci, val, x, b, v);
+        if (done) out(row, v);
         else list[atomicAdd(&count[parity], 1)] = row;
     }
     __syncthreads();
@@ -381,11 +454,11 @@ struct XrStore {
 // y = A x with exactly rounded rows (RESID: r = b - A x, each row rounded once), epilogue
 // epi(row, value); block 0 may carry a finalize role.  FAST: the one-lane-per-row register
 // path first (short rows), else every row on the LDS path.
-template <class VT, class Epi, class Fin, bool RESID, bool FAST>
+template <class VT, class Epi, class Fin, bool RESID, bool FAST, bool OFS = false>
 __global__ void __launch_bounds__(256)
 spmv_exact_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                   const VT* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
-                  Epi epi, Fin fin, const int* halt) {
+                  Epi epi, Fin fin, const int* halt, Sliced<VT> sl) {
     if (halt && *halt) return;
     constexpr int XS = XR_SMEM + (FAST ? 256 * 4 + 16 : 0);
     constexpr int SMEM = Fin::SMEM > XS ? Fin::SMEM : XS;
@@ -412,7 +485,8 @@ spmv_exact_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restri
         const int nchunk = (n + 255) / 256;
         int parity = 0;
         for (int c = (int)blockIdx.x - bfirst; c < nchunk; c += G, parity ^= 1)
-            exact_rows_chunk<VT, RESID>(c * 256, n, parity, rp, ci, val, x, b, accs, flags, list, count, out);
+            exact_rows_chunk<VT, RESID, OFS>(c * 256, n, parity, rp, ci, val, x, b, sl, accs, flags, list, count,
+                                             out);
     } else {
         exact_rows_lds<VT, RESID>(n, (int)blockIdx.x - bfirst, G, rp, ci, val, x, b, accs, flags, out);
     }
@@ -434,11 +508,11 @@ struct XrDot {
 
 // The same with D exact dots of the rows' values in the epilogue (the true residual and
 // its norm): epi.row(row, value, xa, ya) as in the row-sequential dot kernels.
-template <int D, int K, class VT, class Epi, bool RESID, bool FAST>
+template <int D, int K, class VT, class Epi, bool RESID, bool FAST, bool OFS = false>
 __global__ void __launch_bounds__(256)
 spmv_exact_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                       const VT* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
-                      Epi epi, xd::Site site, const int* halt) {
+                      Epi epi, xd::Site site, const int* halt, Sliced<VT> sl) {
     if (halt && *halt) return;
     XD_SHARED(D)
     __shared__ __align__(16) unsigned char smem[XR_SMEM + (FAST ? 256 * 4 + 16 : 0)];
@@ -462,7 +536,8 @@ spmv_exact_dot_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __re
         const int nchunk = (n + 255) / 256;
         int parity = 0;
         for (int c = blockIdx.x; c < nchunk; c += gridDim.x, parity ^= 1)
-            exact_rows_chunk<VT, RESID>(c * 256, n, parity, rp, ci, val, x, b, accs, flags, list, count, out);
+            exact_rows_chunk<VT, RESID, OFS>(c * 256, n, parity, rp, ci, val, x, b, sl, accs, flags, list, count,
+                                             out);
     } else {
         exact_rows_lds<VT, RESID>(n, blockIdx.x, gridDim.x, rp, ci, val, x, b, accs, flags, out);
     }

@@ -173,6 +173,57 @@ def test_solve_exact_rows_hard_rows():
     assert info["true_relres"] == ref.true_relres
 
 
+def banded_paths_case():
+    """A banded matrix (at most 7 offsets per 256-row slice, so the solver holds it in the
+    offset form and the register path reads that form) with the value families of
+    paths_case: narrow blocks, a block of wide exponents (LDS path), ties and cancellations,
+    subnormal products, a ragged tail.  Returns (A, x0, b), all finite."""
+    rng = np.random.default_rng(12)
+    n = 1400
+    offs = (-300, -17, -1, 0, 1, 17, 300)
+    x = rng.uniform(-1, 1, n) * np.exp2(rng.integers(-20, 20, n))
+    x[900:1000] = rng.choice([1.0, -1.0, 0.5, 2.0 ** -53, 3.0], 100)
+    x[1100:1200] = rng.uniform(-1, 1, 100) * 2.0 ** -540
+    rows = []
+    for i in range(n):
+        cols = [i + d for d in offs if 0 <= i + d < n and (d == 0 or rng.random() > 0.02)]
+        k = len(cols)
+        blk = i // 256
+        if blk == 1 or (blk == 4 and i % 3 == 0):
+            vals = rng.standard_normal(k) * np.exp2(rng.integers(-90, 90, k))
+        elif blk == 3:
+            vals = rng.choice([1.0, -1.0, 2.0 ** 52, -(2.0 ** 52), 0.5], k)
+        elif blk == 4 and i % 3 == 1:
+            vals = rng.standard_normal(k) * 2.0 ** -540
+        else:
+            vals = rng.standard_normal(k)
+        rows.append(list(zip(cols, vals.tolist())))
+    A = csr_rows(rows, n)
+    b = rng.uniform(-1, 1, n) * np.exp2(rng.integers(-40, 40, n))
+    b[768:1024] = rng.choice([0.0, 1.0, -2.0 ** -53, 2.0 ** 53], 256)
+    return A, x, b
+
+
+def test_solve_exact_rows_offset_form():
+    """Exactly rounded rows read from the solver's offset form (the register path) and from
+    CSR (the LDS path for rows spanning wide exponent ranges): a few iterations from x0 bit
+    for bit against the oracle, and against the same solve on CSR (layout CSR)."""
+    A, x0, b = banded_paths_case()
+    ex = solvers.default_dot(A.n)
+    ref = solvers.pbicgstab(A, b, x0=x0, tol=1e-300, max_iter=4, dot=ex, spmv=spmv_exact,
+                            resid=lambda A_, b_, x_: resid_exact(A_, b_, x_))
+    dA, db = pk.CSR.from_host(A), to_dev(b)
+    x, info = pk.solve(dA, db, x0=to_dev(x0), tol=1e-300, max_iter=4, exact_rows=2, history=4)
+    assert info["sliced"] & 64, info["sliced"]          # the offset form was built
+    assert info["status"] == ref.status and info["iterations"] == ref.iterations
+    assert np.array_equal(bits(info["history"]), bits(ref.history))
+    assert np.array_equal(bits(x.cpu().numpy()), bits(ref.x))
+    assert info["true_relres"] == ref.true_relres
+    xc, ic = pk.solve(dA, db, x0=to_dev(x0), tol=1e-300, max_iter=4, exact_rows=2, layout=pk.LAYOUT_CSR)
+    assert ic["sliced"] == 0
+    assert np.array_equal(bits(xc.cpu().numpy()), bits(ref.x))
+
+
 def test_exact_rows_replacement_and_history():
     p = g.problem("cd2d_64", scale=20)
     ex = solvers.default_dot(p.A.n)
