@@ -75,8 +75,19 @@ xd::Site carve_site(Carver& c, int grid_max) {
 }
 
 // blocks of DOT_BLOCK threads, >= 8 elements per lane, at most one block per CU
+// grid of the plain (fixed-tree) dots: 8 elements per lane, at most 256 blocks (the tree's
+// shape, which fixes the plain dots' rounding, follows from it)
 int dot_grid(int64_t n) {
     int64_t g = (n + (int64_t)DOT_BLOCK * 8 - 1) / ((int64_t)DOT_BLOCK * 8);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, DOT_GRID_DEFAULT));
+}
+
+// grid of the fused phases and of the solver's other exact dots: one element per lane until
+// 256 blocks are reached, so a small system spreads its rows over several compute units (8
+// elements per lane put a 4,096-row system's phase on one block: 15.8 us for phase A); the
+// exact dots' bits do not depend on the grid
+int xdot_grid(int64_t n) {
+    int64_t g = (n + (int64_t)DOT_BLOCK - 1) / (int64_t)DOT_BLOCK;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, DOT_GRID_DEFAULT));
 }
 
@@ -426,7 +437,7 @@ void launch_spmv_exact_dot(const Mat& A, const double* x, const double* b, Epi e
 template <int D, int GM = DOT_GMAX, class Op>
 XFin<D, Op, GM> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const int* halt, hipStream_t s,
                                        int grid = 0, int block = DOT_BLOCK, int K = KEXP, int* seen = nullptr) {
-    if (grid <= 0) grid = dot_grid(n);
+    if (grid <= 0) grid = xdot_grid(n);
     grid = std::min(grid, GM);
     if constexpr (D == 1) {  // the standalone dot exposes the expansion length
 #define EW_CASE(KK) \
