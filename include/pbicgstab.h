@@ -341,9 +341,9 @@ int pbcg_phase_b(int32_t n, const pbcg_vectors* V, const double* scal,
  * from the best iterate, with residual replacement every 50 iterations
  * (info->fell_back = 1).
  * `info` (host) may be NULL.  Workspace: pbicgstab_workspace_bytes(n, nnz, opts); with
- * layout AUTO it includes room for the sliced copies of A and M (12 bytes per entry,
- * nnz + nnz/8 + 256 entries each), which every call rebuilds (one stream
- * synchronisation each).
+ * layout AUTO, SLICED or SORTED it includes room for the solver's copies of A and M (12
+ * bytes per entry, nnz + nnz/8 + 256 entries each, which also hold the offset form),
+ * which every call rebuilds (one or two stream synchronisations each).
  */
 size_t pbicgstab_workspace_bytes(int32_t n, int64_t nnz, const pbcg_opts* opts);
 int pbicgstab_solve(const pbcg_csr* A, const double* b, double* x, const pbcg_opts* opts,
