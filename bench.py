@@ -538,6 +538,26 @@ def micro_kernels(pk, torch, g, A, n, nnz, dev, reps):
         key = f"exdot_2^{ne.bit_length() - 1}" + ("" if fam == "uniform" else f"_{fam}")
         kern[key] = {"us": dt * 1e6, "bytes": 16 * ne, "GBs": 16 * ne / dt / 1e9}
         del bufs
+    # calibration of what streaming reaches on this part (torch's own element-wise kernels,
+    # not this library's): a 1 GiB copy (read + write) and c = a + b over 1 GiB vectors
+    # (two reads, one write), rotating over two sets so that nothing is cache-resident
+    ne = 1 << 27
+    sets = [[torch.empty(ne, dtype=torch.float64, device=dev).fill_(1.0) for _ in range(3)] for _ in range(2)]
+    cnt = [0]
+
+    def copy():
+        a, b, _ = sets[cnt[0] % 2]
+        cnt[0] += 1
+        b.copy_(a)
+
+    def add():
+        a, b, c = sets[cnt[0] % 2]
+        cnt[0] += 1
+        torch.add(a, b, out=c)
+    for key, fn, nb in (("stream_copy_1GiB", copy, 16 * ne), ("stream_add_1GiB", add, 24 * ne)):
+        dt = time_launches(fn, min(reps, 10), torch)
+        kern[key] = {"us": dt * 1e6, "bytes": nb, "GBs": nb / dt / 1e9, "kernel": "torch element-wise"}
+    del sets
     for k, v in kern.items():
         v["frac_of_peak"] = v["GBs"] / HBM_PEAK_GBS
     log("micro kernels:", json.dumps(kern))
