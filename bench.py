@@ -52,6 +52,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 CSRC = os.path.join(ROOT, "paper_2404_13216_amd", "csrc")
 HEADLINE = "cd3d_256_var"
+WORKLOAD_DESC = {"cd3d_256_var": "cd3d_256_var: 3D upwind convection-diffusion 256^3, kappa=exp(N(0,1)) cell-wise "
+                                  "(harmonic faces), v=(50,25,10), seed 3",
+                 "cd3d_128": "cd3d_128: 3D upwind convection-diffusion 128^3, v=(30,20,10), seed 1 "
+                             "(Infinity-Cache-resident matrix)"}
 TRAFFIC_FILES = {"cd3d_256_var": os.path.join(ROOT, "profiles", "hbm_traffic_cd3d_256_var.md"),
                  "cd3d_128": os.path.join(ROOT, "profiles", "hbm_traffic_cd3d_128.md")}
 KEV = 128  # iterations of each timed solve whose kernels carry timing events
@@ -626,11 +630,18 @@ def main():
     ap.add_argument("--epochs", type=int, default=30, help="learned-preconditioner training epochs")
     ap.add_argument("--traffic-run", action="store_true",
                     help="launch each measured kernel 10 times (for rocprofv3 --pmc runs) and exit")
-    ap.add_argument("--workload", default=HEADLINE, help="workload of --traffic-run")
+    ap.add_argument("--workload", default=HEADLINE,
+                    help="workload of --traffic-run, or of a --solve-only profiling run (cd3d_256_var, cd3d_128)")
     ap.add_argument("--infer-run", action="store_true",
                     help="launch the bf16 inference on the held-out 128^3 matrix 10 times (for rocprofv3 "
                          "counter runs) and exit")
     args = ap.parse_args()
+    if args.workload != HEADLINE and not (args.traffic_run or args.solve_only):
+        print(json.dumps({"error": "--workload other than the headline needs --traffic-run or --solve-only"}))
+        sys.exit(2)
+    if args.workload not in WORKLOAD_DESC:
+        print(json.dumps({"error": "unknown workload %s (choices: %s)" % (args.workload, ", ".join(WORKLOAD_DESC))}))
+        sys.exit(2)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: bench.py measures one GPU's throughput; "
                                    "--gpus must be 1"}))
@@ -646,7 +657,7 @@ def main():
         infer_run(pk, torch, g, dev)
         return
     t0 = time.time()
-    wl = args.workload if args.traffic_run else HEADLINE
+    wl = args.workload
     prob = g.problem(wl)
     A = pk.CSR.from_host(prob.A, dev)
     b = torch.from_numpy(prob.b).to(dev)
@@ -699,8 +710,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cd3d_256_var: 3D upwind convection-diffusion 256^3, kappa=exp(N(0,1)) cell-wise "
-                               "(harmonic faces), v=(50,25,10), seed 3",
+        "config": {"workload": WORKLOAD_DESC[wl],
                    "n": n, "nnz": nnz, "tol": 1e-10, "x0": "0", "alg": "p-BiCGStab",
                    "dots": "exact (rounded once)",
                    "spmv": "row-sequential, " + layout_name(info)},
@@ -713,7 +723,7 @@ def main():
     }
     # dominant kernel of the iteration: the SpMV (two launches per iteration)
     traffic = None
-    tf = TRAFFIC_FILES[HEADLINE]
+    tf = TRAFFIC_FILES[wl]
     if os.path.exists(tf):
         txt = open(tf).read()
         blob = txt[txt.index("```json") + 7: txt.index("```", txt.index("```json") + 7)]
@@ -722,7 +732,7 @@ def main():
             ks = tr["kernels"]
             traffic = (ks["spmv_seq"]["bytes_per_launch"] + ks.get("spmv_aw", ks["spmv_seq"])["bytes_per_launch"]) / 2
     sp = kern["spmv_seq"]
-    out["roofline"] = {"kernel": "spmv_seq", "bound": "hbm", "achieved": sp["GBs"],
+    out["roofline"] = {"kernel": "spmv_seq", "bound": "hbm" if wl == HEADLINE else "cache", "achieved": sp["GBs"],
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sp["GBs"] / HBM_PEAK_GBS,
                        "traffic": traffic, "algorithmic_bytes_per_launch": sp["bytes"],
                        "algorithmic_bytes": "12 per nonzero + 20 per row",
