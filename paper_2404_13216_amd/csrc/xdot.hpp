@@ -78,7 +78,7 @@ __device__ __forceinline__ void lds_add(unsigned long long* acc, int c, uint64_t
 }
 
 // Deposit a finite non-zero double exactly.
-__device__ __noinline__ void deposit_double(unsigned long long* acc, double v) {
+__device__ __forceinline__ void deposit_double(unsigned long long* acc, double v) {
     uint64_t m; int P; bool neg;
     decompose(v, m, P, neg);
     int c = P >> 5, s = P & 31;
@@ -90,7 +90,7 @@ __device__ __noinline__ void deposit_double(unsigned long long* acc, double v) {
 }
 
 // Deposit the exact product of two finite non-zero doubles (any magnitudes).
-__device__ __noinline__ void deposit_product(unsigned long long* acc, double x, double y) {
+__device__ __forceinline__ void deposit_product(unsigned long long* acc, double x, double y) {
     uint64_t mx, my; int Px, Py; bool nx, ny;
     decompose(x, mx, Px, nx);
     decompose(y, my, Py, ny);
