@@ -380,23 +380,38 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ float bf_round(float x) { return (float)(__bf16)x; }   // RNE (v_cvt_pk_bf16_f32)
 
-// GELU for inference: z Phi(z), with Phi(-|z|) = erfc(|z| / sqrt 2) / 2 from Abramowitz &
-// Stegun 7.1.26 (Hastings' rational approximation, |error| <= 1.5e-7 on erf: about one
-// FP32 ulp near 1, far below the bf16 rounding the result gets next):
-// erfc(u) = t (a1 + t (a2 + ... + t a5)) e^{-u^2}, t = 1 / (1 + p u).  With u = |z| / sqrt 2
-// folded into p, the 1/2 into the a_k and the exponential taken as 2^(-z^2 log2(e) / 2):
-// one reciprocal, one exponential and nine other operations per GELU.
-__device__ __forceinline__ float gelu_infer(float z) {
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(z), 1.0f));
-    float q = fmaf(t, 1.061405429f * 0.5f, -1.453152027f * 0.5f);
-    q = fmaf(t, q, 1.421413741f * 0.5f);
-    q = fmaf(t, q, -0.284496736f * 0.5f);
-    q = fmaf(t, q, 0.254829592f * 0.5f);
-    const float e = __builtin_amdgcn_exp2f((z * z) * -0.72134752044448170f);
-    const float h = (t * q) * e;                 // Phi(-|z|)
+// GELU for inference by linear interpolation in a table of GT_N intervals of width 2^-8 on
+// [-8, 8), held in LDS.  Entry k = (G(z_k), G(z_{k+1}) - G(z_k)) at the nodes z_k = -8 + k/256
+// (exact in FP32), with G(z) = z Phi(z) from erfcf in FP32 (erfc keeps the negative tail's
+// relative accuracy).  Interpolation error <= h^2/8 max|G''| = 2^-16/8 * 2 phi(0) ~ 1.5e-6, and
+// the rounding of the table position t = 256 z + 2048 moves z by at most 2^-21: both far below
+// the bf16 rounding the result gets next.  Below -8 the first interval extends (|G| < 1e-14
+// there); from 7.996 on the nodes carry G(z) = z exactly in FP32 (Phi = 1 - 7e-16), so the last
+// interval's linear extension is G(z) = z for every larger z.  NaN stays NaN (f is).  Per GELU:
+// one FMA for t, a clamp, a conversion, a subtraction, the address, one LDS read of 8 bytes and
+// one FMA -- no transcendental on the hot path.
+constexpr int GT_N = 4096;
+
+__device__ __forceinline__ float gelu_ref(float z) {
+    const float h = 0.5f * erfcf(fabsf(z) * 0.70710678118654752f);     // Phi(-|z|)
     return z * (z >= 0.0f ? 1.0f - h : h);
+}
+
+__device__ void gelu_table_init(float2* tab) {
+    for (int k = threadIdx.x; k < GT_N; k += blockDim.x) {
+        const float z0 = -8.0f + (float)k * (1.0f / 256.0f);
+        const float g0 = gelu_ref(z0), g1 = gelu_ref(z0 + (1.0f / 256.0f));
+        tab[k] = make_float2(g0, g1 - g0);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ float gelu_lookup(const float2* tab, float z) {
+    const float t = fmaf(z, 256.0f, 2048.0f);
+    const int k = (int)fminf(fmaxf(t, 0.0f), (float)(GT_N - 1));
+    const float2 e = tab[k];
+    return fmaf(t - (float)k, e.y, e.x);
 }
 
 // One wave handles tiles of 16 nonzeros with v_mfma_f32_16x16x32_bf16 (lane l = 16 g + c
@@ -406,11 +421,15 @@ __device__ __forceinline__ float gelu_infer(float z) {
 // 16 mt + 4 g + j of nonzero c, which are exactly the B operand of layer 2 once the 64
 // hidden units are ordered (per 32-unit k-step ks) as 16 (2 ks) + 4 g + j, then
 // 16 (2 ks + 1) + 4 g + j -- so W2's columns are taken in that order and no value
-// crosses lanes.  Layer 3 (64 -> 1) sums each lane's 16 units and the four lane groups.
+// crosses lanes.  The biases enter as the accumulators' initial values.  Layer 3 (64 -> 1)
+// sums each lane's 16 units with packed bf16 dot products (v_dot2_f32_bf16, FP32
+// accumulation), then the four lane groups.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
                                                     const float* __restrict__ params, const int* __restrict__ rowidx,
                                                     const double* __restrict__ diag, float* __restrict__ mout) {
+    __shared__ float2 gtab[GT_N];
+    gelu_table_init(gtab);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int c = lane & 15, grp = lane >> 4;
     // A operands: W1 (4 m-tiles, K padded to 32) and the column-permuted W2 (4 m-tiles x 2
@@ -428,13 +447,14 @@ k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
                 aw2[mt][ks][j] = (__bf16)params[OFF_W2 + row * HID + unit];
             }
     }
-    float b1v[4][4], b2v[4][4], w3v[4][4];
+    floatx4 b1v[4], b2v[4];
+    bf16x2 w3p[4][2];
     for (int mt = 0; mt < 4; ++mt)
         for (int j = 0; j < 4; ++j) {
             const int u = 16 * mt + 4 * grp + j;
             b1v[mt][j] = params[OFF_B1 + u];
             b2v[mt][j] = params[OFF_B2 + u];
-            w3v[mt][j] = bf_round(params[OFF_W3 + u]);
+            w3p[mt][j >> 1][j & 1] = (__bf16)params[OFF_W3 + u];
         }
     const float b3 = params[OFF_B3];
     const int64_t ntiles = (nnz + 15) / 16;
@@ -449,10 +469,9 @@ k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
         }
         bf16x8 h1[2];
         for (int mt = 0; mt < 4; ++mt) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw1[mt], bx, acc, 0, 0, 0);
+            const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw1[mt], bx, b1v[mt], 0, 0, 0);
             for (int j = 0; j < 4; j += 2) {   // two values per conversion instruction
-                const f32x2 g2 = {gelu_infer(acc[j] + b1v[mt][j]), gelu_infer(acc[j + 1] + b1v[mt][j + 1])};
+                const f32x2 g2 = {gelu_lookup(gtab, acc[j]), gelu_lookup(gtab, acc[j + 1])};
                 const bf16x2 h2 = __builtin_convertvector(g2, bf16x2);
                 h1[mt >> 1][4 * (mt & 1) + j] = h2[0];
                 h1[mt >> 1][4 * (mt & 1) + j + 1] = h2[1];
@@ -461,15 +480,13 @@ k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
         // layer 2: B = H1 in the permuted unit order (k-step ks = m-tiles 2 ks, 2 ks + 1)
         float part = 0.0f;
         for (int mt = 0; mt < 4; ++mt) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[mt][0], h1[0], acc, 0, 0, 0);
+            floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[mt][0], h1[0], b2v[mt], 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[mt][1], h1[1], acc, 0, 0, 0);
             // layer 3: f = sum_u bf16(gelu(z2_u)) w3_u + b3
             for (int j = 0; j < 4; j += 2) {
-                const f32x2 g2 = {gelu_infer(acc[j] + b2v[mt][j]), gelu_infer(acc[j + 1] + b2v[mt][j + 1])};
+                const f32x2 g2 = {gelu_lookup(gtab, acc[j]), gelu_lookup(gtab, acc[j + 1])};
                 const bf16x2 r2 = __builtin_convertvector(g2, bf16x2);
-                part = part + (float)r2[0] * w3v[mt][j];
-                part = part + (float)r2[1] * w3v[mt][j + 1];
+                part = __builtin_amdgcn_fdot2_f32_bf16(r2, w3p[mt][j >> 1], part, false);
             }
         }
         part = part + __shfl_xor(part, 16);
