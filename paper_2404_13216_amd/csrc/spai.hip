@@ -424,42 +424,57 @@ __device__ __forceinline__ float gelu_lookup(const float2* tab, float z) {
 // crosses lanes.  The biases enter as the accumulators' initial values.  Layer 3 (64 -> 1)
 // sums each lane's 16 units with packed bf16 dot products (v_dot2_f32_bf16, FP32
 // accumulation), then the four lane groups.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+// The weights (A operands in each lane's layout), biases and w3 live in LDS next to the GELU
+// table and are read where they are used, by volatile LDS loads that the compiler cannot
+// hoist into registers: the kernel then needs 63 VGPRs, so eight waves per SIMD stay
+// resident (the register-held form had 126 VGPRs and four waves).  Two 1,024-thread blocks
+// (45 KB of LDS each) fill a CU.
+constexpr int INFER_BLOCK = 1024;
+template <class T> __device__ __forceinline__ T lds_load(const T* p) {
+    return *(__attribute__((address_space(3))) const volatile T*)p;
+}
+
+__global__ void __launch_bounds__(INFER_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
 k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
                                                     const float* __restrict__ params, const int* __restrict__ rowidx,
                                                     const double* __restrict__ diag, float* __restrict__ mout) {
+    // W1 (4 m-tiles, K padded to 32) and the column-permuted W2 (4 m-tiles x 2 k-steps),
+    // rounded to bf16, per lane l = 16 g + c; biases and w3 in the C layout (unit
+    // 16 mt + 4 g + j, the same for the 16 lanes of a group)
     __shared__ float2 gtab[GT_N];
+    __shared__ bf16x8 sw1[4][64], sw2[4][2][64];
+    __shared__ floatx4 sb1[4][4], sb2[4][4];
+    __shared__ bf16x2 sw3[4][4][2];
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        const int mt = i >> 4, g = (i >> 2) & 3, j = i & 3, u = 16 * mt + 4 * g + j;
+        sb1[mt][g][j] = params[OFF_B1 + u];
+        sb2[mt][g][j] = params[OFF_B2 + u];
+        sw3[mt][g][j >> 1][j & 1] = (__bf16)params[OFF_W3 + u];
+    }
+    for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {
+        const int mt = i >> 6, ln = i & 63, cc = ln & 15, gg = ln >> 4, row = 16 * mt + cc;
+        bf16x8 w;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * gg + j;
+            w[j] = (__bf16)(k < NF ? params[OFF_W1 + row * NF + k] : 0.0f);
+        }
+        sw1[mt][ln] = w;
+        for (int ks = 0; ks < 2; ++ks) {
+            for (int j = 0; j < 8; ++j) {
+                const int unit = 16 * (2 * ks + (j >> 2)) + 4 * gg + (j & 3);
+                w[j] = (__bf16)params[OFF_W2 + row * HID + unit];
+            }
+            sw2[mt][ks][ln] = w;
+        }
+    }
     gelu_table_init(gtab);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int c = lane & 15, grp = lane >> 4;
-    // A operands: W1 (4 m-tiles, K padded to 32) and the column-permuted W2 (4 m-tiles x 2
-    // k-steps), rounded to bf16; biases and w3 in the C layout (unit 16 mt + 4 grp + j)
-    bf16x8 aw1[4], aw2[4][2];
-    for (int mt = 0; mt < 4; ++mt) {
-        const int row = 16 * mt + c;
-        for (int j = 0; j < 8; ++j) {
-            const int k = 8 * grp + j;
-            aw1[mt][j] = (__bf16)(k < NF ? params[OFF_W1 + row * NF + k] : 0.0f);
-        }
-        for (int ks = 0; ks < 2; ++ks)
-            for (int j = 0; j < 8; ++j) {
-                const int unit = 16 * (2 * ks + (j >> 2)) + 4 * grp + (j & 3);
-                aw2[mt][ks][j] = (__bf16)params[OFF_W2 + row * HID + unit];
-            }
-    }
-    floatx4 b1v[4], b2v[4];
-    bf16x2 w3p[4][2];
-    for (int mt = 0; mt < 4; ++mt)
-        for (int j = 0; j < 4; ++j) {
-            const int u = 16 * mt + 4 * grp + j;
-            b1v[mt][j] = params[OFF_B1 + u];
-            b2v[mt][j] = params[OFF_B2 + u];
-            w3p[mt][j >> 1][j & 1] = (__bf16)params[OFF_W3 + u];
-        }
     const float b3 = params[OFF_B3];
     const int64_t ntiles = (nnz + 15) / 16;
-    const int64_t wstride = (int64_t)gridDim.x * 4;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wid; tile < ntiles; tile += wstride) {
+    constexpr int WAVES = INFER_BLOCK / 64;
+    const int64_t wstride = (int64_t)gridDim.x * WAVES;
+    for (int64_t tile = (int64_t)blockIdx.x * WAVES + wid; tile < ntiles; tile += wstride) {
         const int64_t q = tile * 16 + c;          // this lane's nonzero
         // layer 1: B = features of the tile's nonzeros, rows 8 grp .. 8 grp + 7 of K
         bf16x8 bx;
@@ -469,7 +484,7 @@ k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
         }
         bf16x8 h1[2];
         for (int mt = 0; mt < 4; ++mt) {
-            const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw1[mt], bx, b1v[mt], 0, 0, 0);
+            const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_load(&sw1[mt][lane]), bx, lds_load(&sb1[mt][grp]), 0, 0, 0);
             for (int j = 0; j < 4; j += 2) {   // two values per conversion instruction
                 const f32x2 g2 = {gelu_lookup(gtab, acc[j]), gelu_lookup(gtab, acc[j + 1])};
                 const bf16x2 h2 = __builtin_convertvector(g2, bf16x2);
@@ -480,13 +495,13 @@ k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
         // layer 2: B = H1 in the permuted unit order (k-step ks = m-tiles 2 ks, 2 ks + 1)
         float part = 0.0f;
         for (int mt = 0; mt < 4; ++mt) {
-            floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[mt][0], h1[0], b2v[mt], 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[mt][1], h1[1], acc, 0, 0, 0);
+            floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_load(&sw2[mt][0][lane]), h1[0], lds_load(&sb2[mt][grp]), 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_load(&sw2[mt][1][lane]), h1[1], acc, 0, 0, 0);
             // layer 3: f = sum_u bf16(gelu(z2_u)) w3_u + b3
             for (int j = 0; j < 4; j += 2) {
                 const f32x2 g2 = {gelu_lookup(gtab, acc[j]), gelu_lookup(gtab, acc[j + 1])};
                 const bf16x2 r2 = __builtin_convertvector(g2, bf16x2);
-                part = __builtin_amdgcn_fdot2_f32_bf16(r2, w3p[mt][j >> 1], part, false);
+                part = __builtin_amdgcn_fdot2_f32_bf16(r2, lds_load(&sw3[mt][grp][j >> 1]), part, false);
             }
         }
         part = part + __shfl_xor(part, 16);
@@ -586,9 +601,10 @@ int spai_infer_bf16(int64_t nnz, const float* feat, const float* params, const i
     if (nnz <= 0 || !feat || !params || !rowidx || !diag || !m_out) return PBCG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     const int64_t tiles = (nnz + 15) / 16;
-    // up to 4 waves per SIMD resident (the kernel is held to 128 VGPRs): 1024 blocks
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 1024));
-    k_infer_bf16<<<grid, 256, 0, s>>>(nnz, feat, params, rowidx, diag, m_out);
+    // eight waves per SIMD resident: 8,192 waves in all
+    constexpr int waves = INFER_BLOCK / 64;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + waves - 1) / waves, 1024 * 8 / waves));
+    k_infer_bf16<<<grid, INFER_BLOCK, 0, s>>>(nnz, feat, params, rowidx, diag, m_out);
     HIPCHK(hipGetLastError());
     return PBCG_OK;
 }
