@@ -385,12 +385,12 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // [-8, 8), held in LDS.  Entry k = (G(z_k), G(z_{k+1}) - G(z_k)) at the nodes z_k = -8 + k/256
 // (exact in FP32), with G(z) = z Phi(z) from erfcf in FP32 (erfc keeps the negative tail's
 // relative accuracy).  Interpolation error <= h^2/8 max|G''| = 2^-16/8 * 2 phi(0) ~ 1.5e-6, and
-// the rounding of the table position t = 256 z + 2048 moves z by at most 2^-21: both far below
-// the bf16 rounding the result gets next.  Below -8 the first interval extends (|G| < 1e-14
+// the rounding of the table position t = 256 z + 2048 (accumulated at that scale, a few FP32
+// ulps of 2048) moves z by a few 2^-21: both far below the bf16 rounding the result gets next.  Below -8 the first interval extends (|G| < 1e-14
 // there); from 7.996 on the nodes carry G(z) = z exactly in FP32 (Phi = 1 - 7e-16), so the last
 // interval's linear extension is G(z) = z for every larger z.  NaN stays NaN (f is).  Per GELU:
-// one FMA for t, a clamp, a conversion, a subtraction, the address, one LDS read of 8 bytes and
-// one FMA -- no transcendental on the hot path.
+// a clamp, two conversions, a subtraction, the address, one LDS read of 8 bytes and one FMA --
+// no transcendental on the hot path.
 constexpr int GT_N = 4096;
 
 __device__ __forceinline__ float gelu_ref(float z) {
@@ -407,9 +407,9 @@ __device__ void gelu_table_init(float2* tab) {
     __syncthreads();
 }
 
-__device__ __forceinline__ float gelu_lookup(const float2* tab, float z) {
-    const float t = fmaf(z, 256.0f, 2048.0f);
-    const int k = (int)fminf(fmaxf(t, 0.0f), (float)(GT_N - 1));
+// G(z) from the table position t = 256 z + 2048, which the inference MFMAs produce directly.
+__device__ __forceinline__ float gelu_lookup(const float2* tab, float t) {
+    const int k = (int)__builtin_amdgcn_fmed3f(t, 0.0f, (float)(GT_N - 1));   // one v_med3_f32
     const float2 e = tab[k];
     return fmaf(t - (float)k, e.y, e.x);
 }
@@ -440,15 +440,17 @@ k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
                                                     const double* __restrict__ diag, float* __restrict__ mout) {
     // W1 (4 m-tiles, K padded to 32) and the column-permuted W2 (4 m-tiles x 2 k-steps),
     // rounded to bf16, per lane l = 16 g + c; biases and w3 in the C layout (unit
-    // 16 mt + 4 g + j, the same for the 16 lanes of a group)
+    // 16 mt + 4 g + j, the same for the 16 lanes of a group).  W1, W2 are stored times 256
+    // (exact in bf16) and the biases as 256 b + 2048, so that the MFMAs yield the GELU table
+    // position t = 256 z + 2048 of each pre-activation z.
     __shared__ float2 gtab[GT_N];
     __shared__ bf16x8 sw1[4][64], sw2[4][2][64];
     __shared__ floatx4 sb1[4][4], sb2[4][4];
     __shared__ bf16x2 sw3[4][4][2];
     for (int i = threadIdx.x; i < 64; i += blockDim.x) {
         const int mt = i >> 4, g = (i >> 2) & 3, j = i & 3, u = 16 * mt + 4 * g + j;
-        sb1[mt][g][j] = params[OFF_B1 + u];
-        sb2[mt][g][j] = params[OFF_B2 + u];
+        sb1[mt][g][j] = fmaf(params[OFF_B1 + u], 256.0f, 2048.0f);
+        sb2[mt][g][j] = fmaf(params[OFF_B2 + u], 256.0f, 2048.0f);
         sw3[mt][g][j >> 1][j & 1] = (__bf16)params[OFF_W3 + u];
     }
     for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {
@@ -456,13 +458,13 @@ k_infer_bf16(int64_t nnz, const float* __restrict__ feat,
         bf16x8 w;
         for (int j = 0; j < 8; ++j) {
             const int k = 8 * gg + j;
-            w[j] = (__bf16)(k < NF ? params[OFF_W1 + row * NF + k] : 0.0f);
+            w[j] = (__bf16)(k < NF ? 256.0f * params[OFF_W1 + row * NF + k] : 0.0f);
         }
         sw1[mt][ln] = w;
         for (int ks = 0; ks < 2; ++ks) {
             for (int j = 0; j < 8; ++j) {
                 const int unit = 16 * (2 * ks + (j >> 2)) + 4 * gg + (j & 3);
-                w[j] = (__bf16)params[OFF_W2 + row * HID + unit];
+                w[j] = (__bf16)(256.0f * params[OFF_W2 + row * HID + unit]);
             }
             sw2[mt][ks][ln] = w;
         }
