@@ -78,6 +78,32 @@ def test_bf16_inference_vs_emulation(mat):
     assert np.all(np.abs(m - ref) <= 2.0 ** -7 * (np.abs(ref) + inv)), np.max(np.abs(m - ref) / (np.abs(ref) + inv))
 
 
+def test_bf16_inference_wide_preactivations(mat):
+    """Pre-activations far outside [-8, 8) (weights scaled up, large biases): the GELU
+    table's first interval extended below -8 (G ~ 0) and its last one above 8 (G(z) = z)
+    against the exact-GELU emulation."""
+    th = rand_params(9, scale=0.05).astype(np.float32).astype(np.float64)
+    W1, b1, W2, b2, w3, b3 = ospai.unpack(th)
+    W1 *= 8.0
+    b1[:] = np.random.default_rng(10).standard_normal(64) * 4.0
+    W2 *= 1.5
+    th = th.astype(np.float32).astype(np.float64)
+    rows = np.repeat(np.arange(mat.A.n), np.diff(mat.A.row_ptr))
+    phi = ospai.features(mat.A)
+    # the emulation's pre-activations reach both extensions of the table (about -22 .. 21)
+    W1, b1, W2, b2 = ospai.unpack(th)[:4]
+    x0 = ospai.to_bf16(phi.astype(np.float32)).astype(np.float64)
+    z1 = x0 @ ospai.to_bf16(W1.astype(np.float32)).astype(np.float64).T + b1
+    h1 = ospai.to_bf16(ospai.gelu(z1).astype(np.float32)).astype(np.float64)
+    z2 = h1 @ ospai.to_bf16(W2.astype(np.float32)).astype(np.float64).T + b2
+    assert min(z1.min(), z2.min()) < -8.0 and min(z1.max(), z2.max()) > 8.0
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    m = sm.m_bf16(torch.from_numpy(th.astype(np.float32)).cuda()).cpu().numpy()
+    ref = ospai.infer_bf16_values(th, phi, mat.A.diag()[rows])
+    inv = 1.0 / np.abs(mat.A.diag()[rows])
+    assert np.all(np.abs(m - ref) <= 2.0 ** -7 * (np.abs(ref) + inv)), np.max(np.abs(m - ref) / (np.abs(ref) + inv))
+
+
 def test_loss_grad_and_adam_step(mat):
     A = mat.A
     sm = spai.SpaiMatrix(pk.CSR.from_host(A))
