@@ -384,13 +384,14 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // GELU for inference by linear interpolation in a table of GT_N intervals of width 2^-8 on
 // [-8, 8), held in LDS.  Entry k = (G(z_k), G(z_{k+1}) - G(z_k)) at the nodes z_k = -8 + k/256
 // (exact in FP32), with G(z) = z Phi(z) from erfcf in FP32 (erfc keeps the negative tail's
-// relative accuracy).  Interpolation error <= h^2/8 max|G''| = 2^-16/8 * 2 phi(0) ~ 1.5e-6, and
-// the rounding of the table position t = 256 z + 2048 (accumulated at that scale, a few FP32
-// ulps of 2048) moves z by a few 2^-21: both far below the bf16 rounding the result gets next.  Below -8 the first interval extends (|G| < 1e-14
-// there); from 7.996 on the nodes carry G(z) = z exactly in FP32 (Phi = 1 - 7e-16), so the last
-// interval's linear extension is G(z) = z for every larger z.  NaN stays NaN (f is).  Per GELU:
-// a clamp, two conversions, a subtraction, the address, one LDS read of 8 bytes and one FMA --
-// no transcendental on the hot path.
+// relative accuracy).  Interpolation error <= h^2/8 max|G''| = 2^-16/8 * 2 phi(0) ~ 1.5e-6;
+// the table position t = 256 z + 2048, accumulated at that scale, is off by a few FP32 ulps
+// of 2048, which moves z by a few 2^-21: both far below the bf16 rounding the result gets
+// next.  The first interval is flat (slope 0), so every z below -8 gives G(-8) (|G| < 1e-14
+// there); from 7.996 on the nodes carry G(z) = z exactly in FP32 (Phi = 1 - 7e-16), so the
+// last interval's linear extension is G(z) = z for every larger z.  NaN stays NaN.  Per
+// GELU: a clamp, two conversions, a subtraction, the address, one LDS read of 8 bytes and
+// one FMA -- no transcendental on the hot path.
 constexpr int GT_N = 4096;
 
 __device__ __forceinline__ float gelu_ref(float z) {
@@ -402,7 +403,7 @@ __device__ void gelu_table_init(float2* tab) {
     for (int k = threadIdx.x; k < GT_N; k += blockDim.x) {
         const float z0 = -8.0f + (float)k * (1.0f / 256.0f);
         const float g0 = gelu_ref(z0), g1 = gelu_ref(z0 + (1.0f / 256.0f));
-        tab[k] = make_float2(g0, g1 - g0);
+        tab[k] = make_float2(g0, k == 0 ? 0.0f : g1 - g0);
     }
     __syncthreads();
 }

@@ -104,6 +104,23 @@ def test_bf16_inference_wide_preactivations(mat):
     assert np.all(np.abs(m - ref) <= 2.0 ** -7 * (np.abs(ref) + inv)), np.max(np.abs(m - ref) / (np.abs(ref) + inv))
 
 
+def test_bf16_inference_extreme_preactivations(mat):
+    """Layer-1 pre-activations near +-1e4 (alternating huge biases): GELU must give z above
+    the table and stay bounded near zero far below it."""
+    th = rand_params(9, scale=0.05).astype(np.float32).astype(np.float64)
+    b1 = ospai.unpack(th)[1]
+    b1[:] = np.where(np.arange(64) % 2 == 0, 1.0e4, -1.0e4) * (1 + np.arange(64) / 64.0)
+    th = th.astype(np.float32).astype(np.float64)
+    rows = np.repeat(np.arange(mat.A.n), np.diff(mat.A.row_ptr))
+    phi = ospai.features(mat.A)
+    sm = spai.SpaiMatrix(pk.CSR.from_host(mat.A))
+    m = sm.m_bf16(torch.from_numpy(th.astype(np.float32)).cuda()).cpu().numpy()
+    ref = ospai.infer_bf16_values(th, phi, mat.A.diag()[rows])
+    inv = 1.0 / np.abs(mat.A.diag()[rows])
+    assert np.all(np.isfinite(m))
+    assert np.all(np.abs(m - ref) <= 2.0 ** -7 * (np.abs(ref) + inv)), np.max(np.abs(m - ref) / (np.abs(ref) + inv))
+
+
 def test_loss_grad_and_adam_step(mat):
     A = mat.A
     sm = spai.SpaiMatrix(pk.CSR.from_host(A))
