@@ -441,10 +441,10 @@ XFin<D, Op, GM> launch_ew_dot_deferred(Op op, int64_t n, xd::Site site, const in
     grid = std::min(grid, GM);
     if constexpr (D == 1) {  // the standalone dot exposes the expansion length
 #define EW_CASE(KK) \
-    case KK: ew_dot_kernel<D, KK, Op, EXDOT_U><<<grid, block, 0, s>>>(op, n, site, halt, seen); break;
+    case KK: ew_dot_kernel<D, KK, Op, EXDOT_U, true><<<grid, block, 0, s>>>(op, n, site, halt, seen); break;
         switch (K) {
             EW_CASE(2) EW_CASE(3) EW_CASE(4) EW_CASE(6) EW_CASE(8)
-            default: ew_dot_kernel<D, KEXP, Op, EXDOT_U><<<grid, block, 0, s>>>(op, n, site, halt, seen);
+            default: ew_dot_kernel<D, KEXP, Op, EXDOT_U, true><<<grid, block, 0, s>>>(op, n, site, halt, seen);
         }
 #undef EW_CASE
     } else {

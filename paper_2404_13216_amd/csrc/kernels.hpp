@@ -810,7 +810,10 @@ __global__ void __launch_bounds__(256) wslice_fill_kernel(int n, int nws, const 
 //   finalize(const double* d)   run by a finalize role (XFin) once the records are summed
 // U elements per lane and trip: all U elements' loads are issued before the dependent
 // exact-accumulation work of the first (the result is the exact sum whatever the order).
-template <int D, int K, class Op, int U = 2>
+// QUEUE (single dots): products outside TwoProd's range go through each wave's LDS queue
+// and are deposited 64 at a time (xd::accumulate_q) instead of by the few lanes that meet
+// them while the rest of the wave waits.
+template <int D, int K, class Op, int U = 2, bool QUEUE = false>
 __global__ void __launch_bounds__(1024)
 ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt, int* seen) {
     if (halt && *halt) {
@@ -818,6 +821,13 @@ ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt, int* seen) {
         return;
     }
     XD_SHARED(D)
+    constexpr int QW = QUEUE ? 16 : 1;
+    __shared__ double sh_qx[QW][128], sh_qy[QW][128];
+    __shared__ int sh_qn[QW];
+    double* qx = sh_qx[QUEUE ? (threadIdx.x >> 6) : 0];
+    double* qy = sh_qy[QUEUE ? (threadIdx.x >> 6) : 0];
+    int* qn = &sh_qn[QUEUE ? (threadIdx.x >> 6) : 0];
+    if (QUEUE && (threadIdx.x & 63) == 0) *qn = 0;
     xd::block_init<D>(sh_acc, sh_flags);
     op.load();
     double e[D][K];
@@ -837,7 +847,8 @@ ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt, int* seen) {
             op.st(i + u * stride, in[u], xa, ya);
 #pragma unroll
             for (int d = 0; d < D; ++d)
-                xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+                if constexpr (QUEUE) xd::accumulate_q<K>(e[d], xa[d], ya[d], sh_acc, &sh_flags[d], qx, qy, qn);
+                else xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
         }
     }
     for (; i < n; i += stride) {
@@ -847,8 +858,10 @@ ew_dot_kernel(Op op, int64_t n, xd::Site site, const int* halt, int* seen) {
         op.st(i, in, xa, ya);
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
+            if constexpr (QUEUE) xd::accumulate_q<K>(e[d], xa[d], ya[d], sh_acc, &sh_flags[d], qx, qy, qn);
+            else xd::accumulate<K>(e[d], xa[d], ya[d], sh_acc + d * xd::NCH, &sh_flags[d]);
     }
+    if constexpr (QUEUE) xd::drain_queue(sh_acc, qx, qy, qn);
     xd::block_flush<D, K>(e, sh_acc);
     xd::block_write<D>(site, sh_acc, sh_flags, sh_tmp, sh_rng);
 }

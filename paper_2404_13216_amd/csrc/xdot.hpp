@@ -18,7 +18,8 @@
 //     floating-point expansion with Knuth's TwoSum (error-free).  A non-zero
 //     remainder after the K-th term, and every product outside the TwoProd range
 //     (tiny, huge, or underflowed to zero), is deposited into the LDS accumulator
-//     as an exact integer (ds_add_u64 atomics; integer adds commute).
+//     as an exact integer (ds_add_u64 atomics; integer adds commute).  The standalone dot
+//     queues the out-of-range products per wave and deposits them 64 at a time.
 //  2. Per wave at the end of the loop: each expansion term is summed exactly over
 //     the 64 lanes inside a 4-chunk window (FP64 sums of integers < 2^38 are exact)
 //     and one lane deposits the 4 window chunks; lanes outside the window deposit
@@ -149,6 +150,68 @@ __device__ __forceinline__ void accumulate(double (&e)[K], double x, double y,
             deposit_product(acc, x, y);      // tiny, underflowed or huge product
         }
     }
+}
+
+// Accumulate x*y exactly, with the rare products outside TwoProd's exact range queued per
+// wave instead of deposited by the few lanes that meet them: the active lanes append them
+// to the wave's LDS queue (qx, qy: 128 entries, compaction by ballot; *qn, in LDS, counts
+// them), and once 64 are queued the active lanes deposit those 64 between them.  Any set
+// of active lanes may call it (a wave's last trip can be partial); every lane of the wave
+// must have the same qx, qy, qn.  drain_queue deposits what is left.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    const int lane = threadIdx.x & 63;
+    return __popcll(lane ? (m << (64 - lane)) : 0ull);
+}
+
+template <int K>
+__device__ __forceinline__ void accumulate_q(double (&e)[K], double x, double y, unsigned long long* acc,
+                                             uint32_t* flags, double* qx, double* qy, int* qn) {
+    double p = x * y;
+    int pe = (int)((dbits(p) >> 52) & 0x7ff);
+    bool queue = false;
+    if (pe >= 54 && pe <= 2002) {
+        double err = fma(x, y, -p);
+        expand<K>(e, p, 0, acc);
+        expand<K>(e, err, K > 1 ? 1 : 0, acc);
+    } else {
+        bool fx = isfinite(x), fy = isfinite(y);
+        if (!(fx && fy)) {
+            uint32_t f;
+            if (isnan(x) || isnan(y) || x == 0.0 || y == 0.0) f = F_NAN;
+            else f = ((x > 0.0) == (y > 0.0)) ? F_PINF : F_NINF;
+            atomicOr(flags, f);
+        } else if (x != 0.0 && y != 0.0) {
+            queue = true;
+        }
+    }
+    const uint64_t qm = __ballot(queue);
+    if (qm) {
+        int n = *qn;
+        if (queue) {
+            const int pos = n + lanes_below(qm);
+            qx[pos] = x;
+            qy[pos] = y;
+        }
+        n += __popcll(qm);
+        if (n >= 64) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const uint64_t act = __ballot(true);
+            const int nact = __popcll(act);
+            for (int j = lanes_below(act); j < 64; j += nact) deposit_product(acc, qx[n - 64 + j], qy[n - 64 + j]);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            n -= 64;
+        }
+        *qn = n;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+__device__ __forceinline__ void drain_queue(unsigned long long* acc, const double* qx, const double* qy,
+                                            const int* qn) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int n = *qn;
+    const int lane = threadIdx.x & 63;
+    if (lane < n) deposit_product(acc, qx[lane], qy[lane]);
 }
 
 // Cross-lane moves within a row of 16 lanes (DPP, register to register): quad_perm
