@@ -85,9 +85,10 @@ __device__ __forceinline__ void deposit_double(unsigned long long* acc, double v
     int c = P >> 5, s = P & 31;
     uint64_t lo = m << s;
     uint64_t hi = s ? (m >> (64 - s)) : 0;
-    lds_add(acc, c, lo & 0xffffffffull, neg);
-    lds_add(acc, c + 1, lo >> 32, neg);
-    lds_add(acc, c + 2, hi, neg);
+    const long long sg = neg ? -1 : 1;
+    atomicAdd(acc + c, (unsigned long long)(sg * (long long)(lo & 0xffffffffull)));
+    atomicAdd(acc + c + 1, (unsigned long long)(sg * (long long)(lo >> 32)));
+    if (hi) atomicAdd(acc + c + 2, (unsigned long long)(sg * (long long)hi));
 }
 
 // Deposit the exact product of two finite non-zero doubles (any magnitudes).
